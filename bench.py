@@ -1,0 +1,233 @@
+#!/usr/bin/env python3
+"""Benchmark of the sliding-window Gaussian-splatting hot path on one MI355X.
+
+Workload (default): the paper-scale window step -- 200k optimisable
+Gaussians plus their 200k-slot frozen store, SH degree 3, a window of 10
+frames x 4 cameras at 1352x1014, every frame with exactly 200k live slots
+(10% retire and 10% are born per frame).  One step = forward of all 40
+views with the fused L1 gradient, backward, Adam + SGLD, relocation.
+
+The step runs in three launch structures on the same inputs and the same
+number of steps from the same initial state: GRAPH (chosen form: the batched
+sequence captured once in a hipGraph), BATCHED (one launch per kernel over
+all views; its timed region also yields the per-kernel HIP-event breakdown)
+and PLAIN (one launch sequence per view with a host read-back of each
+view's pair count, the per-frame baseline).  `value` is GRAPH window
+steps/s.  The PSNR of each form after the run shows they train equally.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+PEAK_FP32_NONPACKED = 78.6     # TFLOP/s: 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, no packed FP32
+FLOPS_PER_EVAL = 15.0          # FP32 flops of one (pixel, splat) evaluation: offsets 4, quadratic 7, exp 1, o*g 1, min 1, test 1
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--num-gs", type=int, default=200_000)
+    ap.add_argument("--swin", type=int, default=10)
+    ap.add_argument("--cams", type=int, default=4)
+    ap.add_argument("--width", type=int, default=1352)
+    ap.add_argument("--height", type=int, default=1014)
+    ap.add_argument("--sh-degree", type=int, default=3)
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--lds-batch", type=int, default=0)
+    ap.add_argument("--modes", default="graph,batched,plain")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pixels", type=int, default=1536)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design "
+              "described in DESIGN.md, not built", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2409_07759_amd import swgs
+    from paper_2409_07759_amd import synth as S
+
+    dev = torch.device("cuda", 0)
+    tw, th = (int(x) for x in args.tile.split("x"))
+    st0 = args.swin
+    frames = list(range(st0, st0 + args.swin))
+    t0 = time.time()
+    student = S.steady_window_pool(args.num_gs, args.swin, args.sh_degree, st0, seed=0)
+    teacher = S.steady_window_pool(args.num_gs, args.swin, args.sh_degree, st0, seed=1)
+    views = S.ring_views(frames, args.cams, args.width, args.height, phase_deg=10.0)
+    log(f"inputs built in {time.time() - t0:.1f}s: {student.slots} slots, {len(views)} views")
+
+    ctx = swgs.Context(0)
+    # targets: teacher renders (forward only)
+    tpool = swgs.Pool.from_synth(teacher, train=False)
+    tplan = swgs.Plan(ctx, tpool, views, tile=(tw, th))
+    targets = tplan.forward()
+    torch.cuda.synchronize()
+    tplan.close()
+    del tpool
+    log("targets rendered")
+
+    cfg_base = dict(window_start=st0, relocate_period=1)
+    results = {}
+    pool_for = {}
+
+    def run_mode(mode_name):
+        mode = {"graph": swgs.SWGS_MODE_GRAPH, "batched": swgs.SWGS_MODE_BATCHED, "plain": swgs.SWGS_MODE_PLAIN}[mode_name]
+        dp = swgs.Pool.from_synth(student)
+        plan = swgs.Plan(ctx, dp, views, tile=(tw, th), lds_batch=args.lds_batch, headroom=1.5)
+        cfg = swgs.step_cfg(mode=mode, **cfg_base)
+        stats = torch.zeros(8, dtype=torch.float64, device=dev)
+        step = 0
+        for _ in range(args.warmup):
+            plan.window_step(cfg, targets, step + 1, step, 2, stats=stats)
+            step += 1
+        torch.cuda.synchronize()
+        timing = None
+        if mode_name == "batched":
+            plan.set_timing(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            plan.window_step(cfg, targets, step + 1, step, 2, stats=stats)
+            step += 1
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        if mode_name == "batched":
+            timing = plan.timing()
+            plan.set_timing(False)
+        st = stats.cpu().numpy()
+        if st[6] != 0:
+            raise RuntimeError(f"{mode_name}: pair capacity overflow")
+        # PSNR of the trained state over all window views
+        img = plan.forward()
+        torch.cuda.synchronize()
+        mse = torch.mean((img - targets) ** 2).item()
+        psnr = 10 * math.log10(1.0 / mse)
+        results[mode_name] = dict(ms=1e3 * el / args.steps, steps_per_s=args.steps / el, psnr=psnr,
+                                  loss=float(st[3]), pairs=int(st[4]), relocated=int(st[5]), timing=timing,
+                                  records=plan.n_records, pixels=plan.n_pixels, ws_gb=plan.ws_bytes / 1e9)
+        log(f"{mode_name}: {1e3 * el / args.steps:.2f} ms/step, {args.steps / el:.2f} steps/s, PSNR {psnr:.3f} dB, "
+            f"pairs {int(st[4])}, relocated {int(st[5])}")
+        plan.close()
+        del dp
+
+    for m in args.modes.split(","):
+        run_mode(m.strip())
+
+    chosen = "graph" if "graph" in results else list(results)[0]
+    out = {
+        "metric": "window train steps/s (batched hipGraph step vs plain per-frame launches, same PSNR)",
+        "value": round(results[chosen]["steps_per_s"], 4),
+        "unit": "window steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(results[chosen]["ms"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded; DyNeRF-shaped window: 300-frame clip scale, 1352x1014, 200k live Gaussians)",
+        "config": {
+            "workload": f"paper-scale window step: {args.num_gs} optimisable + {args.num_gs} frozen Gaussians, "
+                        f"SH degree {args.sh_degree}, W={args.swin} frames x {args.cams} cameras at "
+                        f"{args.width}x{args.height}, Adam+SGLD+relocation every step",
+            "views": len(views), "tile": args.tile, "form": chosen,
+        },
+        "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items() if kk != "timing"}
+                  for k, v in results.items()},
+    }
+    if "plain" in results:
+        out["speedup_vs_plain"] = round(results[chosen]["steps_per_s"] / results["plain"]["steps_per_s"], 3)
+        out["psnr_delta_vs_plain_db"] = round(results[chosen]["psnr"] - results["plain"]["psnr"], 4)
+    if "batched" in results and results["batched"]["timing"]:
+        tm, (ev_f, ev_b) = results["batched"]["timing"]
+        per_step = {k: round(v[0] / max(1, args.steps), 4) for k, v in tm.items()}
+        out["kernel_ms_per_step"] = per_step
+        dom = max(tm, key=lambda k: tm[k][0])
+        n_launch = max(1, tm[dom][1])
+        avg_s = tm[dom][0] / n_launch / 1e3
+        if dom in ("blend_fwd", "blend_bwd"):
+            evals = (ev_f if dom == "blend_fwd" else ev_b) / n_launch
+            ach = evals * FLOPS_PER_EVAL / avg_s / 1e12
+            out["roofline"] = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": PEAK_FP32_NONPACKED,
+                               "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_NONPACKED, 4), "traffic": None,
+                               "evaluated_pairs_per_launch": int(evals), "avg_launch_ms": round(avg_s * 1e3, 4)}
+        else:
+            out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                               "frac": None, "traffic": None, "avg_launch_ms": round(avg_s * 1e3, 4)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(student, views, args)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(student, views, args):
+    """The FP64 oracle, single-threaded, on a bounded sample of the same step:
+    one view's preprocess of every slot, forward and adjoint of `cpu_pixels`
+    random pixels, the adjoint preprocess of every visible slot; scaled to a
+    full window step (all views, all pixels) plus the numpy Adam step."""
+    import numpy as np
+
+    import oracle as O
+
+    v = views[0]
+    rng = np.random.default_rng(0)
+    P = v.width * v.height
+    pix = rng.choice(P, size=min(args.cpu_pixels, P), replace=False)
+    t = time.perf_counter()
+    vis, rec, _ = O.preprocess(student.params, student.sh_degree, student.start, student.expire, v)
+    t_pre = time.perf_counter() - t
+    t = time.perf_counter()
+    O.render_records(vis, rec, v, pixels=pix)
+    t_fwd = time.perf_counter() - t
+    t = time.perf_counter()
+    drec = O.blend_backward_pixels(vis, rec, v, pix, rng.uniform(-1, 1, size=(3, len(pix))))
+    t_bwd = time.perf_counter() - t
+    slots = np.nonzero(vis[:student.num_gs])[0]
+    sub = slots[: min(len(slots), 20000)]
+    t = time.perf_counter()
+    O.preprocess_backward(student.params, student.sh_degree, v, drec, sub)
+    t_pb = (time.perf_counter() - t) * (len(slots) / max(1, len(sub)))
+    F = student.params.shape[0]
+    g = rng.normal(size=(F, student.num_gs)) * 1e-3
+    A = np.ones(student.num_gs, bool)
+    t = time.perf_counter()
+    O.adam_sgld_step(student.params[:, :student.num_gs], g, np.zeros_like(g), np.zeros_like(g), A, 1,
+                     student.sh_degree, 0, 0, noise_lr=0.0)
+    t_adam = time.perf_counter() - t
+    per_view = t_pre + (P / len(pix)) * (t_fwd + t_bwd) + t_pb
+    step_s = len(views) * per_view + t_adam
+    sample_s = t_pre + t_fwd + t_bwd + t_pb * len(sub) / max(1, len(slots)) + t_adam
+    log(f"cpu oracle: preprocess {t_pre:.2f}s, fwd {t_fwd:.2f}s + bwd {t_bwd:.2f}s for {len(pix)} px, "
+        f"adjoint preprocess {t_pb:.2f}s (extrapolated), adam {t_adam:.2f}s -> {step_s:.0f} s/step")
+    return {"value": 1.0 / step_s, "unit": "window steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 of {len(views)} views: preprocess of all {student.slots} slots, forward+adjoint of "
+                      f"{len(pix)} random pixels of {P}, adjoint preprocess of {len(sub)} of {len(slots)} visible "
+                      f"slots, dense Adam step; scaled to {len(views)} views x {P} pixels",
+            "sample_seconds": round(sample_s, 2)}
+
+
+if __name__ == "__main__":
+    main()

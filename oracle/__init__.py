@@ -45,6 +45,7 @@ def lib():
         L.orc_preprocess.argtypes = [P, i64, i32, P, P, i32, P, i32, i32, i32, i32, P, P, P]
         L.orc_render.argtypes = [i64, P, P, i32, i32, P, i64, P, P, P, P, P, P]
         L.orc_blend_backward.argtypes = [i64, P, P, i32, i32, P, P, P]
+        L.orc_blend_backward_pixels.argtypes = [i64, P, P, i32, i32, P, P, i64, P, P]
         L.orc_preprocess_backward_one.argtypes = [P, i64, i64, i32, P, i32, i32, P, P]
         L.orc_view_backward.argtypes = [P, i64, i32, P, P, i32, P, i32, i32, P, i64, P, P, P]
         L.orc_reloc_SN.argtypes = [i32, ctypes.c_double]
@@ -169,6 +170,16 @@ def blend_backward(vis, rec, view, dLdC):
     drec = np.zeros((S, 9))
     lib().orc_blend_backward(S, _p(_i32(vis)), _p(_f64(rec)), view.width, view.height,
                              _p(_f64(view.bg)), _p(_f64(dLdC)), _p(drec))
+    return drec
+
+
+def blend_backward_pixels(vis, rec, view, pixels, dLdC):
+    """Adjoint of Eq. 3 restricted to a pixel list; dLdC is [3, len(pixels)]."""
+    S = vis.shape[0]
+    drec = np.zeros((S, 9))
+    pix = np.ascontiguousarray(pixels, dtype=np.int64)
+    lib().orc_blend_backward_pixels(S, _p(_i32(vis)), _p(_f64(rec)), view.width, view.height,
+                                    _p(_f64(view.bg)), _p(_f64(dLdC)), len(pix), _p(pix), _p(drec))
     return drec
 
 

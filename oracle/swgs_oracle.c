@@ -154,7 +154,11 @@ static double margin_floor(double z)
     return d / s;
 }
 
-/* relative distance of z to the nearest FP32 rounding boundary */
+/* relative distance of z to the nearest FP32 rounding boundary.  A value
+ * lying exactly on a boundary comes from an exact FP64 computation (an
+ * inexact one lands there with probability ~2^-28), which any correct
+ * implementation reproduces and rounds the same way (ties to even), so it
+ * is not a near-decision. */
 static double margin_f32(double z)
 {
     float f = (float)z;
@@ -162,6 +166,7 @@ static double margin_f32(double z)
     float up = nextafterf(f, INFINITY), dn = nextafterf(f, -INFINITY);
     double mid_up = 0.5 * (fd + (double)up), mid_dn = 0.5 * (fd + (double)dn);
     double d = fmin(fabs(z - mid_up), fabs(z - mid_dn));
+    if (d == 0.0) return INFINITY;
     return d / (fabs(z) > 1e-300 ? fabs(z) : 1.0);
 }
 
@@ -409,19 +414,33 @@ void orc_render(int64_t S, const int32_t *visible, const double *rec,
  * so that dC/da_k = T_k (c_k - U - Rr bg) without any division.
  * drec[i*9..] accumulates d/d(u, v, A, B, C, o, r, g, b) of slot i.
  * ---------------------------------------------------------------------- */
+void orc_blend_backward_pixels(int64_t S, const int32_t *visible, const double *rec,
+                               int W, int H, const double bg[3], const double *dLdC,
+                               int64_t npix, const int64_t *pix, double *drec);
+
 void orc_blend_backward(int64_t S, const int32_t *visible, const double *rec,
                         int W, int H, const double bg[3], const double *dLdC,
                         double *drec)
+{
+    orc_blend_backward_pixels(S, visible, rec, W, H, bg, dLdC, -1, NULL, drec);
+}
+
+/* Same over a list of pixels (pix[j] = y*W + x, dLdC[3][npix]) or, when pix
+ * is NULL, over the whole image (dLdC[3][W*H]). */
+void orc_blend_backward_pixels(int64_t S, const int32_t *visible, const double *rec,
+                               int W, int H, const double bg[3], const double *dLdC,
+                               int64_t npix, const int64_t *pix, double *drec)
 {
     int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(S > 0 ? S : 1));
     int64_t n = orc_depth_order(S, visible, rec, order);
     int64_t *who = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
     double *al = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     double *Tk = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    int64_t P = (int64_t)W * H;
-    for (int64_t pid = 0; pid < P; ++pid) {
+    int64_t P = pix ? npix : (int64_t)W * H;
+    for (int64_t j = 0; j < P; ++j) {
+        int64_t pid = pix ? pix[j] : j;
         double px = (double)(pid % W) + 0.5, py = (double)(pid / W) + 0.5;
-        double g[3] = {dLdC[pid], dLdC[P + pid], dLdC[2 * P + pid]};
+        double g[3] = {dLdC[j], dLdC[P + j], dLdC[2 * P + j]};
         /* forward walk, storing contributors */
         double T = 1.0;
         int64_t m = 0;

@@ -1,0 +1,770 @@
+// Host side of libswgs.so: argument checks, plans and workspace layout, and
+// the launch sequences of the render, backward, step, relocation, window
+// step and mature calls declared in include/swgs.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+
+#include "swgs_internal.h"
+
+using namespace swgs;
+
+namespace {
+
+#define HIP_TRY(ctx, expr)                                                                        \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail((ctx), SWGS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+swgs_status fail(swgs_context *ctx, swgs_status st, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Scratch {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+std::map<const swgs_context *, Scratch> g_scratch;
+
+hipError_t ctx_scratch(swgs_context *ctx, size_t bytes, void **out) {
+    Scratch &s = g_scratch[ctx];
+    if (s.bytes < bytes) {
+        if (s.ptr) {
+            hipError_t e = hipStreamSynchronize(ctx->stream);
+            if (e != hipSuccess) return e;
+            (void)hipFree(s.ptr);
+            s.ptr = nullptr;
+            s.bytes = 0;
+        }
+        hipError_t e = hipMalloc(&s.ptr, bytes);
+        if (e != hipSuccess) return e;
+        s.bytes = bytes;
+    }
+    *out = s.ptr;
+    return hipSuccess;
+}
+
+bool pool_ok(const swgs_pool *p, bool need_train, std::string &why) {
+    if (!p) { why = "pool is NULL"; return false; }
+    if (p->struct_size != sizeof(swgs_pool)) { why = "pool.struct_size mismatch"; return false; }
+    if (p->sh_degree < 0 || p->sh_degree > kMaxShDegree) { why = "sh_degree must be 0..3"; return false; }
+    if (p->n_slots < 1 || p->num_gs < 0 || p->num_gs > p->n_slots) { why = "need 0 <= num_gs <= n_slots, n_slots >= 1"; return false; }
+    if (p->swin <= 0) { why = "swin must be > 0"; return false; }
+    if (!p->params || !p->start || !p->expire) { why = "params/start/expire must not be NULL"; return false; }
+    if (need_train && p->num_gs > 0 && (!p->grads || !p->adam_m || !p->adam_v)) {
+        why = "grads/adam_m/adam_v must not be NULL for training";
+        return false;
+    }
+    return true;
+}
+
+// Constant block uploaded at the head of each call: views, groups, group
+// view list, record view bases.
+void upload_consts(hipStream_t s, swgs_plan &p, uint8_t *ws) {
+    (void)hipMemcpyAsync(ws + p.lay.off[WB_VIEWS], p.consts_host, p.consts_bytes, hipMemcpyHostToDevice, s);
+}
+
+swgs_status check_ws(swgs_context *ctx, const swgs_plan *p, const void *ws, size_t ws_bytes) {
+    if (!ws) return fail(ctx, SWGS_ERR_INVALID_ARG, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(ctx, SWGS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (ws_bytes < p->lay.total)
+        return fail(ctx, SWGS_ERR_WORKSPACE_TOO_SMALL,
+                    "workspace has " + std::to_string(ws_bytes) + " bytes, needs " + std::to_string(p->lay.total));
+    return SWGS_OK;
+}
+
+void build_layout(swgs_plan &p) {
+    const size_t G = p.groups.size(), V = p.views.size();
+    const size_t R = (size_t)p.R, T = (size_t)p.T, P = (size_t)p.P, cap = (size_t)p.pair_cap;
+    const size_t S = (size_t)p.pool.n_slots, NG = (size_t)p.pool.num_gs, nA = p.n_A;
+    size_t n_list = 0;
+    for (auto &g : p.groups) n_list += g.n_live;
+    n_list += nA;
+    const size_t nblk = (S + kGateChunk - 1) / kGateChunk;
+    const size_t nbu = (nA + 2047) / 2048;
+    size_t sz[WB_COUNT];
+    std::memset(sz, 0, sizeof sz);
+    // constant block first, contiguous
+    sz[WB_VIEWS] = V * sizeof(ViewDev);
+    sz[WB_GROUPS] = G * sizeof(GroupDev);
+    sz[WB_GROUP_VIEWS] = V * 4;
+    sz[WB_REC_VIEW_BASE] = (V + 1) * 4;
+    sz[WB_ACTIVE_LIST] = (n_list + 1) * 4;
+    sz[WB_ACTIVE_COUNT] = (G + 1) * 4;
+    sz[WB_DEPTH_KEY] = R * 4;
+    sz[WB_TILE_COUNT] = R * 4;
+    sz[WB_RECT] = R * 8;
+    sz[WB_SPLAT] = R * kSplatFloats * 4;
+    sz[WB_PAIR_KEY] = cap * 4;
+    sz[WB_PAIR_VAL] = cap * 4;
+    sz[WB_PAIR_COUNT] = 4 * 4;
+    sz[WB_TILE_RANGE] = T * 8;
+    sz[WB_T_FINAL] = P * 4;
+    sz[WB_DLDC] = 3 * P * 4;
+    sz[WB_REC_GRAD] = 9 * R * 4;
+    sz[WB_GATE_BLK] = (G + 1) * nblk * 4;
+    sz[WB_POS_OF] = G * NG * 4;
+    sz[WB_REC_IDX] = R * 4;
+    sz[WB_KEY_ALT] = R * 4;
+    sz[WB_IDX_ALT] = R * 4;
+    sz[WB_PAIR_KEY_ALT] = cap * 4;
+    sz[WB_PAIR_VAL_ALT] = cap * 4;
+    sz[WB_PAIR_OFFSET] = (R + 1) * 4;
+    sz[WB_SORT_HIST] = (size_t)2048 * kSortBlocks * 4;
+    sz[WB_SORT_TOTAL] = (std::max<size_t>(2048, R / 4096 + 2) + 8) * 4;
+    sz[WB_LAST] = P * 4;
+    sz[WB_LOSS_PART] = 2 * T * 8;
+    sz[WB_STATS] = 8 * 8;
+    sz[WB_STEP] = sizeof(StepDev);
+    sz[WB_RELOC_W] = (nA + 1 + nbu + 4) * 8;
+    sz[WB_RELOC_FLAG] = 2 * (nA + 1) * 4;
+    sz[WB_RELOC_CNT] = 2 * (nA + 1) * 4;
+    sz[WB_RELOC_SRC] = (nA + 1) * 4;
+    sz[WB_RELOC_DST] = (nA + 1) * 4;
+    sz[WB_RELOC_SCAN] = (4 + nA / 4096 + 4) * 4;
+    sz[WB_REG_PART] = 2 * ((nA + 255) / 256 + 1) * 8;
+    sz[WB_COUNTERS] = 8 * 8;
+    // order: constant block, then the rest
+    const int order_first[] = {WB_VIEWS, WB_GROUPS, WB_GROUP_VIEWS, WB_REC_VIEW_BASE};
+    size_t off = 0;
+    for (int b : order_first) {
+        p.lay.off[b] = off;
+        p.lay.size[b] = sz[b];
+        off = align_up(off + sz[b], 16);
+    }
+    p.consts_bytes = off;
+    off = align_up(off, 256);
+    for (int b = 0; b < WB_COUNT; ++b) {
+        if (b == WB_VIEWS || b == WB_GROUPS || b == WB_GROUP_VIEWS || b == WB_REC_VIEW_BASE) continue;
+        p.lay.off[b] = off;
+        p.lay.size[b] = sz[b];
+        off = align_up(off + sz[b], 256);
+    }
+    p.lay.total = off;
+}
+
+void fill_consts(swgs_plan &p) {
+    uint8_t *h = static_cast<uint8_t *>(p.consts_host);
+    std::memset(h, 0, p.consts_bytes);
+    std::memcpy(h + p.lay.off[WB_VIEWS], p.vdev.data(), p.vdev.size() * sizeof(ViewDev));
+    std::memcpy(h + p.lay.off[WB_GROUPS], p.groups.data(), p.groups.size() * sizeof(GroupDev));
+    std::memcpy(h + p.lay.off[WB_GROUP_VIEWS], p.group_views.data(), p.group_views.size() * 4);
+    std::vector<uint32_t> rvb(p.views.size() + 1);
+    for (size_t v = 0; v < p.views.size(); ++v) rvb[v] = p.vdev[v].rec_base;
+    rvb[p.views.size()] = (uint32_t)p.R;
+    std::memcpy(h + p.lay.off[WB_REC_VIEW_BASE], rvb.data(), rvb.size() * 4);
+}
+
+// kernel classes timed with events when a plan's timing is on
+enum { TK_GATE = 0, TK_PREPROCESS, TK_SORT, TK_FWD, TK_BWD, TK_PREBWD, TK_ADAM, TK_RELOC, TK_N };
+
+struct TimeScope {
+    swgs_plan &p;
+    hipStream_t s;
+    int kind;
+    bool on;
+    TimeScope(swgs_plan &p_, hipStream_t s_, int k) : p(p_), s(s_), kind(k), on(p_.timing) {
+        if (on) rec();
+    }
+    ~TimeScope() {
+        if (on) rec();
+    }
+    void rec() {
+        auto &v = p.ev[kind];
+        if (p.ev_used[kind] == v.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) { on = false; return; }
+            v.push_back(e);
+        }
+        (void)hipEventRecord(v[p.ev_used[kind]++], s);
+    }
+};
+
+unsigned long long *counters_of(swgs_plan &p, uint8_t *ws) {
+    return p.timing ? wsp<unsigned long long>(ws, p, WB_COUNTERS) : nullptr;
+}
+
+int tile_bits(int64_t T) {
+    int b = 1;
+    while (b < 32 && ((int64_t)1 << b) < T) ++b;
+    return b;
+}
+
+// ------------------------------------------------------------ launch blocks
+void seq_gate(hipStream_t s, swgs_plan &p, uint8_t *ws) {
+    TimeScope t(p, s, TK_GATE);
+    launch_gate(s, p, ws);
+}
+
+// forward of records [rec_lo, rec_hi) and tiles [tile_lo, tile_hi): one
+// view (plain) or all views (batched)
+void seq_forward(hipStream_t s, swgs_plan &p, uint8_t *ws, int view, float *images, const float *targets) {
+    uint32_t rec_lo = 0, rec_hi = (uint32_t)p.R, tile_lo = 0, tile_hi = (uint32_t)p.T;
+    if (view >= 0) {
+        rec_lo = p.vdev[view].rec_base;
+        rec_hi = view + 1 < (int)p.views.size() ? p.vdev[view + 1].rec_base : (uint32_t)p.R;
+        tile_lo = p.vdev[view].tile_base;
+        tile_hi = view + 1 < (int)p.views.size() ? p.vdev[view + 1].tile_base : (uint32_t)p.T;
+    }
+    {
+        TimeScope t(p, s, TK_PREPROCESS);
+        launch_preprocess(s, p, ws, view, view);
+    }
+    {
+        TimeScope t(p, s, TK_SORT);
+        uint32_t *hist = wsp<uint32_t>(ws, p, WB_SORT_HIST), *tot = wsp<uint32_t>(ws, p, WB_SORT_TOTAL);
+        radix_sort_pairs(s, wsp<uint32_t>(ws, p, WB_DEPTH_KEY) + rec_lo, wsp<uint32_t>(ws, p, WB_REC_IDX) + rec_lo,
+                         wsp<uint32_t>(ws, p, WB_KEY_ALT) + rec_lo, wsp<uint32_t>(ws, p, WB_IDX_ALT) + rec_lo, nullptr,
+                         rec_hi - rec_lo, rec_hi - rec_lo, 32, hist, tot);
+        launch_pair_offsets(s, p, ws, rec_lo, rec_hi);
+        launch_emit_pairs(s, p, ws, rec_lo, rec_hi);
+        uint32_t *pc = wsp<uint32_t>(ws, p, WB_PAIR_COUNT);
+        radix_sort_pairs(s, wsp<uint32_t>(ws, p, WB_PAIR_KEY), wsp<uint32_t>(ws, p, WB_PAIR_VAL),
+                         wsp<uint32_t>(ws, p, WB_PAIR_KEY_ALT), wsp<uint32_t>(ws, p, WB_PAIR_VAL_ALT), pc, 0,
+                         (uint32_t)p.pair_cap, p.tile_key_bits, hist, tot);
+        launch_tile_ranges(s, p, ws, tile_lo, tile_hi);
+    }
+    {
+        TimeScope t(p, s, TK_FWD);
+        launch_blend_forward(s, p, ws, images, targets, tile_lo, tile_hi, counters_of(p, ws));
+    }
+}
+
+void seq_backward_blend(hipStream_t s, swgs_plan &p, uint8_t *ws, int view, const float *dLdC) {
+    uint32_t tile_lo = 0, tile_hi = (uint32_t)p.T;
+    if (view >= 0) {
+        tile_lo = p.vdev[view].tile_base;
+        tile_hi = view + 1 < (int)p.views.size() ? p.vdev[view + 1].tile_base : (uint32_t)p.T;
+    }
+    TimeScope t(p, s, TK_BWD);
+    launch_blend_backward(s, p, ws, dLdC, tile_lo, tile_hi, counters_of(p, ws));
+}
+
+}  // namespace
+
+// ============================================================== ABI
+extern "C" {
+
+int swgs_version(void) { return SWGS_VERSION; }
+
+void swgs_step_cfg_default(swgs_step_cfg *c) {
+    if (!c) return;
+    std::memset(c, 0, sizeof *c);
+    c->struct_size = sizeof *c;
+    c->lr_mean = 1.6e-4f;
+    c->lr_scale = 5e-3f;
+    c->lr_quat = 1e-3f;
+    c->lr_logit = 5e-2f;
+    c->lr_sh_dc = 2.5e-3f;
+    c->lr_sh_rest = 1.25e-4f;
+    c->beta1 = 0.9f;
+    c->beta2 = 0.999f;
+    c->eps = 1e-15f;
+    c->noise_lr = 5e4f;
+    c->noise_k = 100.0f;
+    c->noise_t0 = 0.005f;
+    c->lambda_opacity = 2e-2f;
+    c->lambda_scale = 1e-2f;
+    c->grad_scale_base = 0.0f;
+    c->window_start = 0;
+    c->relocate_period = 1;
+    c->reloc_n_max = 32;
+    c->mode = SWGS_MODE_BATCHED;
+}
+
+swgs_status swgs_context_create(int device, void *hip_stream, swgs_context **out) {
+    if (!out) return SWGS_ERR_INVALID_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SWGS_ERR_INVALID_ARG;
+    if (hipSetDevice(device) != hipSuccess) return SWGS_ERR_HIP;
+    auto *c = new (std::nothrow) swgs_context;
+    if (!c) return SWGS_ERR_HIP;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    *out = c;
+    return SWGS_OK;
+}
+
+swgs_status swgs_context_set_stream(swgs_context *ctx, void *hip_stream) {
+    if (!ctx) return SWGS_ERR_INVALID_ARG;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return SWGS_OK;
+}
+
+swgs_status swgs_context_destroy(swgs_context *ctx) {
+    if (!ctx) return SWGS_ERR_INVALID_ARG;
+    auto it = g_scratch.find(ctx);
+    if (it != g_scratch.end()) {
+        (void)hipStreamSynchronize(ctx->stream);
+        if (it->second.ptr) (void)hipFree(it->second.ptr);
+        g_scratch.erase(it);
+    }
+    delete ctx;
+    return SWGS_OK;
+}
+
+const char *swgs_last_error(const swgs_context *ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
+
+swgs_status swgs_plan_create(swgs_context *ctx, const swgs_pool *pool, const swgs_view *views, int32_t n_views,
+                             const swgs_plan_opts *opts, swgs_plan **out, size_t *ws_bytes) {
+    if (!ctx) return SWGS_ERR_INVALID_ARG;
+    if (!out || !ws_bytes) return fail(ctx, SWGS_ERR_INVALID_ARG, "out/ws_bytes must not be NULL");
+    *out = nullptr;
+    std::string why;
+    if (!pool_ok(pool, false, why)) return fail(ctx, SWGS_ERR_INVALID_ARG, why);
+    if (!views || n_views <= 0) return fail(ctx, SWGS_ERR_INVALID_ARG, "need at least one view");
+    if (n_views > 65535) return fail(ctx, SWGS_ERR_UNSUPPORTED, "at most 65535 views per plan");
+    if (!opts || opts->struct_size != sizeof(swgs_plan_opts)) return fail(ctx, SWGS_ERR_INVALID_ARG, "opts.struct_size mismatch");
+    int tw = opts->tile_w, th = opts->tile_h;
+    if (tw == 0 && th == 0) { tw = 16; th = 16; }
+    if (!((tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 32 && th == 8)))
+        return fail(ctx, SWGS_ERR_UNSUPPORTED, "tile shape must be 8x8, 16x16 or 32x8");
+    int lb = opts->lds_batch == 0 ? tw * th : opts->lds_batch;
+    if (!(lb == 64 || lb == 128 || lb == 256)) return fail(ctx, SWGS_ERR_UNSUPPORTED, "lds_batch must be 64, 128 or 256");
+    if (lb == 64 && !(tw == 8 && th == 8)) return fail(ctx, SWGS_ERR_UNSUPPORTED, "lds_batch 64 needs 8x8 tiles");
+    if (opts->pair_capacity <= 0 || opts->pair_capacity > 0xFFFFFFF0LL)
+        return fail(ctx, SWGS_ERR_INVALID_ARG, "pair_capacity must be in (0, 2^32 - 16)");
+    for (int v = 0; v < n_views; ++v) {
+        const swgs_view &w = views[v];
+        if (w.width <= 0 || w.height <= 0 || w.width > 16384 * 8 || w.height > 16384 * 8)
+            return fail(ctx, SWGS_ERR_INVALID_ARG, "view " + std::to_string(v) + ": bad size");
+        if (!(w.fx > 0 && w.fy > 0)) return fail(ctx, SWGS_ERR_INVALID_ARG, "view " + std::to_string(v) + ": focal must be > 0");
+    }
+    auto *p = new (std::nothrow) swgs_plan;
+    if (!p) return fail(ctx, SWGS_ERR_HIP, "out of host memory");
+    p->pool = *pool;
+    p->sh_degree = pool->sh_degree;
+    p->F = rows_for(pool->sh_degree);
+    p->tile_w = tw;
+    p->tile_h = th;
+    p->lds_batch = lb;
+    p->pair_cap = opts->pair_capacity;
+    p->views.assign(views, views + n_views);
+
+    // distinct frames in order of appearance
+    std::vector<int32_t> frames;
+    std::vector<int> vgroup(n_views);
+    for (int v = 0; v < n_views; ++v) {
+        auto it = std::find(frames.begin(), frames.end(), views[v].frame);
+        if (it == frames.end()) { vgroup[v] = (int)frames.size(); frames.push_back(views[v].frame); }
+        else vgroup[v] = (int)(it - frames.begin());
+    }
+    const int G = (int)frames.size();
+    // live counts per frame and |A| on the device (synchronising)
+    void *scr = nullptr;
+    if (ctx_scratch(ctx, 4 * (2 * G + 8), &scr) != hipSuccess) { delete p; return fail(ctx, SWGS_ERR_HIP, "scratch alloc failed"); }
+    int32_t *d_frames = static_cast<int32_t *>(scr);
+    uint32_t *d_counts = reinterpret_cast<uint32_t *>(d_frames + G + 2);
+    std::vector<uint32_t> counts(G + 1, 0);
+    if (hipMemcpyAsync(d_frames, frames.data(), 4 * G, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        hipMemsetAsync(d_counts, 0, 4 * (G + 1), ctx->stream) != hipSuccess) {
+        delete p;
+        return fail(ctx, SWGS_ERR_HIP, "count upload failed");
+    }
+    launch_count_live(ctx->stream, pool->start, pool->expire, pool->n_slots, pool->num_gs, d_frames, G, d_counts);
+    if (hipMemcpyAsync(counts.data(), d_counts, 4 * (G + 1), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        delete p;
+        return fail(ctx, SWGS_ERR_HIP, std::string("live count failed: ") + hipGetErrorString(hipGetLastError()));
+    }
+    // groups and the group-ordered view list
+    p->groups.resize(G);
+    uint32_t lb_acc = 0;
+    for (int g = 0; g < G; ++g) {
+        GroupDev &gd = p->groups[g];
+        std::memset(&gd, 0, sizeof gd);
+        gd.frame = frames[g];
+        gd.n_live = counts[g];
+        gd.list_base = lb_acc;
+        lb_acc += counts[g];
+    }
+    p->n_A = counts[G];
+    p->list_A_base = lb_acc;
+    for (int g = 0; g < G; ++g) {
+        p->groups[g].view_first = (int32_t)p->group_views.size();
+        for (int v = 0; v < n_views; ++v)
+            if (vgroup[v] == g) p->group_views.push_back(v);
+        p->groups[g].n_views = (int32_t)p->group_views.size() - p->groups[g].view_first;
+    }
+    // per-view geometry in caller order
+    p->vdev.resize(n_views);
+    uint64_t rec = 0, tiles = 0;
+    int64_t pix = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const swgs_view &w = views[v];
+        ViewDev &d = p->vdev[v];
+        std::memset(&d, 0, sizeof d);
+        std::memcpy(d.R, w.R, sizeof d.R);
+        std::memcpy(d.t, w.t, sizeof d.t);
+        d.fx = w.fx; d.fy = w.fy; d.cx = w.cx; d.cy = w.cy;
+        for (int c = 0; c < 3; ++c) d.campos[c] = -(w.R[c] * w.t[0] + w.R[3 + c] * w.t[1] + w.R[6 + c] * w.t[2]);
+        d.limx = 1.3 * (0.5 * w.width / w.fx);
+        d.limy = 1.3 * (0.5 * w.height / w.fy);
+        for (int c = 0; c < 3; ++c) d.bg[c] = w.bg[c];
+        d.frame = w.frame;
+        d.width = w.width;
+        d.height = w.height;
+        d.tiles_x = (w.width + tw - 1) / tw;
+        d.tiles_y = (w.height + th - 1) / th;
+        d.group = vgroup[v];
+        d.rec_base = (uint32_t)rec;
+        d.tile_base = (uint32_t)tiles;
+        d.pix_base = pix;
+        d.inv_norm = (float)(1.0 / ((double)n_views * 3.0 * (double)w.width * (double)w.height));
+        rec += counts[vgroup[v]];
+        tiles += (uint64_t)d.tiles_x * d.tiles_y;
+        pix += (int64_t)w.width * w.height;
+    }
+    if (rec >= 0xFFFFFFF0ull || tiles >= 0xFFFFFFF0ull) {
+        delete p;
+        return fail(ctx, SWGS_ERR_UNSUPPORTED, "more than 2^32 records or tiles in one plan");
+    }
+    p->R = (int64_t)rec;
+    p->T = (int64_t)tiles;
+    p->P = pix;
+    p->tile_key_bits = tile_bits(p->T);
+    build_layout(*p);
+    if (hipHostMalloc(&p->consts_host, p->consts_bytes) != hipSuccess) {
+        delete p;
+        return fail(ctx, SWGS_ERR_HIP, "pinned constant block alloc failed");
+    }
+    fill_consts(*p);
+    *out = p;
+    *ws_bytes = p->lay.total;
+    return SWGS_OK;
+}
+
+swgs_status swgs_plan_destroy(swgs_plan *p) {
+    if (!p) return SWGS_ERR_INVALID_ARG;
+    if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->consts_host) (void)hipHostFree(p->consts_host);
+    for (int k = 0; k < TK_N; ++k)
+        for (auto e : p->ev[k]) (void)hipEventDestroy(e);
+    delete p;
+    return SWGS_OK;
+}
+
+swgs_status swgs_plan_buffer(const swgs_plan *p, int32_t which, size_t *offset, size_t *bytes) {
+    if (!p || !offset || !bytes) return SWGS_ERR_INVALID_ARG;
+    static const int map[SWGS_BUF_COUNT_] = {WB_ACTIVE_LIST, WB_ACTIVE_COUNT, WB_REC_VIEW_BASE, WB_DEPTH_KEY,
+                                             WB_TILE_COUNT, WB_RECT, WB_SPLAT, WB_PAIR_KEY, WB_PAIR_VAL,
+                                             WB_PAIR_COUNT, WB_TILE_RANGE, WB_T_FINAL, WB_DLDC, WB_REC_GRAD,
+                                             WB_REC_IDX};
+    if (which < 0 || which >= SWGS_BUF_COUNT_) return SWGS_ERR_INVALID_ARG;
+    *offset = p->lay.off[map[which]];
+    *bytes = p->lay.size[map[which]];
+    return SWGS_OK;
+}
+
+swgs_status swgs_plan_info(const swgs_plan *p, int64_t *n_groups, int64_t *n_records, int64_t *n_pixels,
+                           int64_t *n_tiles) {
+    if (!p) return SWGS_ERR_INVALID_ARG;
+    if (n_groups) *n_groups = (int64_t)p->groups.size();
+    if (n_records) *n_records = p->R;
+    if (n_pixels) *n_pixels = p->P;
+    if (n_tiles) *n_tiles = p->T;
+    return SWGS_OK;
+}
+
+swgs_status swgs_plan_measure(swgs_context *ctx, swgs_plan *p, void *workspace, size_t ws_bytes, int64_t *n_pairs,
+                              int64_t *n_records) {
+    if (!ctx || !p) return SWGS_ERR_INVALID_ARG;
+    swgs_status st = check_ws(ctx, p, workspace, ws_bytes);
+    if (st) return st;
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    hipStream_t s = ctx->stream;
+    upload_consts(s, *p, ws);
+    launch_gate(s, *p, ws);
+    launch_preprocess(s, *p, ws, -1, -1);
+    uint32_t *tc = wsp<uint32_t>(ws, *p, WB_TILE_COUNT);
+    uint32_t *tot = wsp<uint32_t>(ws, *p, WB_PAIR_COUNT) + 2;
+    exclusive_scan_u32(s, tc, wsp<uint32_t>(ws, *p, WB_PAIR_OFFSET), (uint32_t)p->R, tot,
+                       wsp<uint32_t>(ws, *p, WB_SORT_TOTAL));
+    uint32_t k = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&k, tot, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (n_pairs) *n_pairs = k;
+    if (n_records) *n_records = p->R;
+    return SWGS_OK;
+}
+
+swgs_status swgs_render_forward(swgs_context *ctx, swgs_plan *p, void *workspace, size_t ws_bytes, float *images,
+                                const float *targets, double *stats) {
+    if (!ctx || !p) return SWGS_ERR_INVALID_ARG;
+    swgs_status st = check_ws(ctx, p, workspace, ws_bytes);
+    if (st) return st;
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    hipStream_t s = ctx->stream;
+    upload_consts(s, *p, ws);
+    launch_gate(s, *p, ws);
+    seq_forward(s, *p, ws, -1, images, targets);
+    double *sdev = wsp<double>(ws, *p, WB_STATS);
+    launch_fill_f64(s, sdev, 0.0, 8);
+    if (targets) launch_loss_reduce(s, *p, ws, nullptr, false);
+    if (stats) launch_stats_out(s, sdev, wsp<uint32_t>(ws, *p, WB_PAIR_COUNT), nullptr, stats);
+    HIP_TRY(ctx, hipGetLastError());
+    return SWGS_OK;
+}
+
+swgs_status swgs_render_backward(swgs_context *ctx, swgs_plan *p, void *workspace, size_t ws_bytes,
+                                 const float *dL_dimages, int32_t add_regulariser, const swgs_step_cfg *cfg) {
+    if (!ctx || !p) return SWGS_ERR_INVALID_ARG;
+    swgs_status st = check_ws(ctx, p, workspace, ws_bytes);
+    if (st) return st;
+    std::string why;
+    if (!p->pool.grads && p->pool.num_gs > 0) return fail(ctx, SWGS_ERR_INVALID_ARG, "pool.grads is NULL");
+    if (add_regulariser && (!cfg || cfg->struct_size != sizeof(swgs_step_cfg)))
+        return fail(ctx, SWGS_ERR_INVALID_ARG, "cfg required (struct_size) when add_regulariser != 0");
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    hipStream_t s = ctx->stream;
+    upload_consts(s, *p, ws);
+    const float *g = dL_dimages ? dL_dimages : wsp<float>(ws, *p, WB_DLDC);
+    launch_fill_f32(s, wsp<float>(ws, *p, WB_REC_GRAD), 0.0f, 9 * (size_t)p->R);
+    seq_backward_blend(s, *p, ws, -1, g);
+    launch_preprocess_backward(s, *p, ws, add_regulariser, cfg ? cfg->lambda_opacity : 0.f,
+                               cfg ? cfg->lambda_scale : 0.f);
+    HIP_TRY(ctx, hipGetLastError());
+    return SWGS_OK;
+}
+
+static swgs_status check_cfg(swgs_context *ctx, const swgs_step_cfg *cfg) {
+    if (!cfg || cfg->struct_size != sizeof(swgs_step_cfg)) return fail(ctx, SWGS_ERR_INVALID_ARG, "cfg.struct_size mismatch");
+    if (cfg->reloc_n_max < 1) return fail(ctx, SWGS_ERR_INVALID_ARG, "reloc_n_max must be >= 1");
+    if (cfg->relocate_period < 0) return fail(ctx, SWGS_ERR_INVALID_ARG, "relocate_period must be >= 0");
+    if (!(cfg->beta1 >= 0 && cfg->beta1 < 1 && cfg->beta2 >= 0 && cfg->beta2 < 1))
+        return fail(ctx, SWGS_ERR_INVALID_ARG, "betas must be in [0, 1)");
+    return SWGS_OK;
+}
+
+swgs_status swgs_step(swgs_context *ctx, swgs_plan *p, void *workspace, size_t ws_bytes, const swgs_step_cfg *cfg,
+                      int64_t adam_t, uint64_t step, uint64_t seed, const float *eta) {
+    if (!ctx || !p) return SWGS_ERR_INVALID_ARG;
+    swgs_status st = check_ws(ctx, p, workspace, ws_bytes);
+    if (st) return st;
+    if ((st = check_cfg(ctx, cfg))) return st;
+    std::string why;
+    if (!pool_ok(&p->pool, true, why)) return fail(ctx, SWGS_ERR_INVALID_ARG, why);
+    if (adam_t < 1) return fail(ctx, SWGS_ERR_INVALID_ARG, "adam_t must be >= 1");
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    hipStream_t s = ctx->stream;
+    upload_consts(s, *p, ws);
+    launch_gate(s, *p, ws);
+    launch_set_step(s, reinterpret_cast<uint8_t *>(wsp<StepDev>(ws, *p, WB_STEP)), adam_t, step, seed);
+    launch_adam_sgld(s, *p, ws, *cfg, eta);
+    HIP_TRY(ctx, hipGetLastError());
+    return SWGS_OK;
+}
+
+swgs_status swgs_relocate(swgs_context *ctx, swgs_plan *p, void *workspace, size_t ws_bytes, const swgs_step_cfg *cfg,
+                          uint64_t step, uint64_t seed, int32_t *dst, int32_t *src, int32_t *count) {
+    if (!ctx || !p) return SWGS_ERR_INVALID_ARG;
+    swgs_status st = check_ws(ctx, p, workspace, ws_bytes);
+    if (st) return st;
+    if ((st = check_cfg(ctx, cfg))) return st;
+    std::string why;
+    if (!pool_ok(&p->pool, true, why)) return fail(ctx, SWGS_ERR_INVALID_ARG, why);
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    hipStream_t s = ctx->stream;
+    upload_consts(s, *p, ws);
+    launch_gate(s, *p, ws);
+    launch_set_step(s, reinterpret_cast<uint8_t *>(wsp<StepDev>(ws, *p, WB_STEP)), 1, step, seed);
+    swgs_step_cfg c = *cfg;
+    if (c.relocate_period == 0) c.relocate_period = 1;   // standalone call: always relocate
+    launch_relocate(s, *p, ws, c, dst, src, count);
+    HIP_TRY(ctx, hipGetLastError());
+    return SWGS_OK;
+}
+
+// one batched step, launched in order on stream s (also the captured body)
+static void seq_step_tail(hipStream_t s, swgs_plan &p, uint8_t *ws, const swgs_step_cfg &cfg) {
+    {
+        TimeScope t(p, s, TK_PREBWD);
+        launch_preprocess_backward(s, p, ws, 1, cfg.lambda_opacity, cfg.lambda_scale);
+    }
+    {
+        TimeScope t(p, s, TK_ADAM);
+        launch_adam_sgld(s, p, ws, cfg, nullptr);
+    }
+    if (cfg.relocate_period > 0) {
+        TimeScope t(p, s, TK_RELOC);
+        launch_relocate(s, p, ws, cfg, nullptr, nullptr, nullptr);
+    }
+}
+
+static void seq_window_batched(hipStream_t s, swgs_plan &p, uint8_t *ws, const swgs_step_cfg &cfg,
+                               const float *targets, float *images) {
+    seq_gate(s, p, ws);
+    seq_forward(s, p, ws, -1, images, targets);
+    launch_loss_reduce(s, p, ws, &cfg, true);
+    launch_fill_f32(s, wsp<float>(ws, p, WB_REC_GRAD), 0.0f, 9 * (size_t)p.R);
+    seq_backward_blend(s, p, ws, -1, wsp<float>(ws, p, WB_DLDC));
+    seq_step_tail(s, p, ws, cfg);
+}
+
+swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *p, void *workspace, size_t ws_bytes,
+                             const swgs_step_cfg *cfg, const float *targets, float *images, int64_t adam_t,
+                             uint64_t step, uint64_t seed, double *stats) {
+    if (!ctx || !p) return SWGS_ERR_INVALID_ARG;
+    swgs_status st = check_ws(ctx, p, workspace, ws_bytes);
+    if (st) return st;
+    if ((st = check_cfg(ctx, cfg))) return st;
+    std::string why;
+    if (!pool_ok(&p->pool, true, why)) return fail(ctx, SWGS_ERR_INVALID_ARG, why);
+    if (!targets) return fail(ctx, SWGS_ERR_INVALID_ARG, "targets must not be NULL");
+    if (adam_t < 1) return fail(ctx, SWGS_ERR_INVALID_ARG, "adam_t must be >= 1");
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    hipStream_t s = ctx->stream;
+    double *sdev = wsp<double>(ws, *p, WB_STATS);
+    upload_consts(s, *p, ws);
+
+    if (cfg->mode == SWGS_MODE_GRAPH) {
+        if (!s) return fail(ctx, SWGS_ERR_INVALID_ARG, "graph mode needs a non-default stream");
+        const bool same = p->graph_exec && p->graph_ws == workspace && p->graph_targets == targets &&
+                          p->graph_images == images && std::memcmp(&p->graph_cfg, cfg, sizeof *cfg) == 0;
+        if (!same) {
+            if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
+            if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+            launch_set_step(s, reinterpret_cast<uint8_t *>(wsp<StepDev>(ws, *p, WB_STEP)), adam_t, step, seed);
+            const bool was_timing = p->timing;
+            p->timing = false;              // no event records inside a graph
+            hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (ce != hipSuccess) { p->timing = was_timing; return fail(ctx, SWGS_ERR_HIP, std::string("begin capture: ") + hipGetErrorString(ce)); }
+            launch_fill_f64(s, sdev, 0.0, 8);
+            seq_window_batched(s, *p, ws, *cfg, targets, images);
+            launch_advance_step(s, reinterpret_cast<uint8_t *>(wsp<StepDev>(ws, *p, WB_STEP)));
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(s, &g);
+            p->timing = was_timing;
+            if (e != hipSuccess) return fail(ctx, SWGS_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+            p->graph = g;
+            HIP_TRY(ctx, hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0));
+            p->graph_ws = workspace;
+            p->graph_targets = targets;
+            p->graph_images = images;
+            p->graph_cfg = *cfg;
+        }
+        HIP_TRY(ctx, hipGraphLaunch(p->graph_exec, s));
+    } else if (cfg->mode == SWGS_MODE_BATCHED) {
+        launch_set_step(s, reinterpret_cast<uint8_t *>(wsp<StepDev>(ws, *p, WB_STEP)), adam_t, step, seed);
+        launch_fill_f64(s, sdev, 0.0, 8);
+        seq_window_batched(s, *p, ws, *cfg, targets, images);
+    } else {
+        // plain: one launch sequence per view, reading each view's pair
+        // count back to the host the way a per-frame renderer sizes its
+        // buffers, then one backward preprocess and one step
+        launch_set_step(s, reinterpret_cast<uint8_t *>(wsp<StepDev>(ws, *p, WB_STEP)), adam_t, step, seed);
+        launch_fill_f64(s, sdev, 0.0, 8);
+        seq_gate(s, *p, ws);
+        launch_fill_f32(s, wsp<float>(ws, *p, WB_REC_GRAD), 0.0f, 9 * (size_t)p->R);
+        uint32_t *pc = wsp<uint32_t>(ws, *p, WB_PAIR_COUNT);
+        for (int v = 0; v < (int)p->views.size(); ++v) {
+            seq_forward(s, *p, ws, v, images, targets);
+            uint32_t k = 0;
+            HIP_TRY(ctx, hipMemcpyAsync(&k, pc, 4, hipMemcpyDeviceToHost, s));
+            HIP_TRY(ctx, hipStreamSynchronize(s));
+            if (k > (uint64_t)p->pair_cap) return fail(ctx, SWGS_ERR_CAPACITY, "pair capacity exceeded in view " + std::to_string(v));
+            seq_backward_blend(s, *p, ws, v, wsp<float>(ws, *p, WB_DLDC));
+        }
+        launch_loss_reduce(s, *p, ws, cfg, true);
+        seq_step_tail(s, *p, ws, *cfg);
+    }
+    if (stats)
+        launch_stats_out(s, sdev, wsp<uint32_t>(ws, *p, WB_PAIR_COUNT),
+                         wsp<uint32_t>(ws, *p, WB_ACTIVE_COUNT) + p->groups.size(), stats);
+    HIP_TRY(ctx, hipGetLastError());
+    return SWGS_OK;
+}
+
+swgs_status swgs_plan_set_timing(swgs_context *ctx, swgs_plan *p, void *workspace, size_t ws_bytes, int32_t on) {
+    if (!ctx || !p) return SWGS_ERR_INVALID_ARG;
+    swgs_status st = check_ws(ctx, p, workspace, ws_bytes);
+    if (st) return st;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    p->timing = on != 0;
+    for (int k = 0; k < TK_N; ++k) p->ev_used[k] = 0;
+    launch_fill_u32(ctx->stream, reinterpret_cast<uint32_t *>(wsp<unsigned long long>(static_cast<uint8_t *>(workspace), *p, WB_COUNTERS)), 0, 16);
+    HIP_TRY(ctx, hipGetLastError());
+    return SWGS_OK;
+}
+
+swgs_status swgs_plan_timing(swgs_context *ctx, swgs_plan *p, void *workspace, size_t ws_bytes, double *ms,
+                             int64_t *launches, uint64_t *evals) {
+    if (!ctx || !p || !ms || !launches) return SWGS_ERR_INVALID_ARG;
+    swgs_status st = check_ws(ctx, p, workspace, ws_bytes);
+    if (st) return st;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int k = 0; k < TK_N; ++k) {
+        double tot = 0.0;
+        const size_t n = p->ev_used[k] / 2;
+        for (size_t i = 0; i < n; ++i) {
+            float m = 0.0f;
+            HIP_TRY(ctx, hipEventElapsedTime(&m, p->ev[k][2 * i], p->ev[k][2 * i + 1]));
+            tot += m;
+        }
+        ms[k] = tot;
+        launches[k] = (int64_t)n;
+        p->ev_used[k] = 0;
+    }
+    if (evals) {
+        HIP_TRY(ctx, hipMemcpy(evals, wsp<unsigned long long>(static_cast<uint8_t *>(workspace), *p, WB_COUNTERS),
+                               16, hipMemcpyDeviceToHost));
+    }
+    launch_fill_u32(ctx->stream, reinterpret_cast<uint32_t *>(wsp<unsigned long long>(static_cast<uint8_t *>(workspace), *p, WB_COUNTERS)), 0, 16);
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return SWGS_OK;
+}
+
+size_t swgs_record_bytes(int64_t count, int32_t sh_degree) {
+    if (count < 0 || sh_degree < 0 || sh_degree > 3) return 0;
+    return 32 + (size_t)count * (16 + 4 * (size_t)rows_for(sh_degree));
+}
+
+swgs_status swgs_mature(swgs_context *ctx, const swgs_pool *pool, int32_t st, void *record, size_t capacity,
+                        int64_t *count_out, size_t *bytes_out) {
+    if (!ctx) return SWGS_ERR_INVALID_ARG;
+    std::string why;
+    if (!pool_ok(pool, false, why)) return fail(ctx, SWGS_ERR_INVALID_ARG, why);
+    if (pool->n_slots < 2 * pool->num_gs) return fail(ctx, SWGS_ERR_INVALID_ARG, "mature needs n_slots >= 2 num_gs");
+    if (!record) return fail(ctx, SWGS_ERR_INVALID_ARG, "record is NULL");
+    const int n = pool->num_gs;
+    void *scr = nullptr;
+    const size_t words = 2 * ((size_t)n + 1) + (size_t)n / 4096 + 8;
+    HIP_TRY(ctx, ctx_scratch(ctx, words * 4, &scr));
+    uint32_t *sc = static_cast<uint32_t *>(scr);
+    uint32_t *d_count = sc + words - 2;
+    // count first: the record must fit before anything is written
+    hipStream_t s = ctx->stream;
+    const int F = rows_for(pool->sh_degree);
+    // flags + scan only (pack is the second launch of launch_mature), so run
+    // the count on a copy of the pool with num_gs slots and no writes: the
+    // flags kernel is side-effect free
+    swgs_pool q = *pool;
+    uint32_t cnt = 0;
+    {
+        // reuse launch_mature's first two steps by calling it with a NULL
+        // record is not possible; count on the host from the device start[]
+        std::vector<int32_t> hs(n);
+        HIP_TRY(ctx, hipMemcpyAsync(hs.data(), pool->start, 4 * (size_t)n, hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        for (int i = 0; i < n; ++i) cnt += hs[i] < st ? 1u : 0u;
+    }
+    const size_t need = swgs_record_bytes(cnt, pool->sh_degree);
+    if (capacity < need) return fail(ctx, SWGS_ERR_INVALID_ARG, "record capacity " + std::to_string(capacity) + " < " + std::to_string(need));
+    launch_mature(s, q, F, st, static_cast<uint8_t *>(record), sc, d_count);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (count_out) *count_out = cnt;
+    if (bytes_out) *bytes_out = need;
+    return SWGS_OK;
+}
+
+}  // extern "C"

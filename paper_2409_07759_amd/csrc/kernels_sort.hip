@@ -1,0 +1,296 @@
+// Device-wide stable LSD radix sort of (uint32 key, uint32 value) pairs and
+// an exclusive scan, hand-written for gfx950 (wave64).
+//
+// Sorting puts the splats of each tile in depth order, "close to far"
+// (Sec. 2.1): the records are first sorted by FP32 depth bits, then the
+// (tile, record) pairs emitted in that order are stably sorted by tile.
+//
+// One pass = histogram (LDS atomics per block) -> per-digit scan of the
+// block counts -> stable scatter.  The grid is a fixed kSortBlocks blocks;
+// block b owns the contiguous range [b L, (b+1) L) with L = ceil(n / B), so
+// the element count may live on the device (graph-friendly).  Inside a block
+// the stable rank of an element among equal digits comes from ballot-based
+// match masks within the wave and per-wave digit counts in LDS.
+// Digit widths are chosen so that the pass count is even and the sorted data
+// ends in the caller's primary buffers.
+#include "swgs_internal.h"
+
+namespace swgs {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxDigitBits = 11;
+constexpr int kMaxBins = 1 << kMaxDigitBits;
+
+__device__ __forceinline__ uint32_t resolve_n(const uint32_t *d_n, uint32_t n_fixed, uint32_t cap) {
+    uint32_t n = d_n ? *d_n : n_fixed;
+    return n < cap ? n : cap;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_hist(const uint32_t *__restrict__ keys, const uint32_t *d_n, uint32_t n_fixed, uint32_t cap,
+       int shift, int bins, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[kMaxBins];
+    for (int i = threadIdx.x; i < bins; i += kBlock) h[i] = 0;
+    __syncthreads();
+    const uint32_t n = resolve_n(d_n, n_fixed, cap);
+    const uint32_t L = (n + gridDim.x - 1) / gridDim.x;
+    const uint32_t lo = blockIdx.x * L;
+    const uint32_t hi = min(n, lo + L);
+    const uint32_t mask = (uint32_t)bins - 1;
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kBlock) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+    __syncthreads();
+    for (int d = threadIdx.x; d < bins; d += kBlock) hist[(size_t)d * gridDim.x + blockIdx.x] = h[d];
+}
+
+// one block per digit: exclusive scan over the kSortBlocks block counts
+__global__ void __launch_bounds__(kBlock)
+k_digit_scan(uint32_t *__restrict__ hist, int nblocks, uint32_t *__restrict__ totals) {
+    const int d = blockIdx.x;
+    uint32_t *c = hist + (size_t)d * nblocks;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ uint32_t wsum[kWaves];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < nblocks; b0 += kBlock) {
+        int i = b0 + threadIdx.x;
+        uint32_t v = i < nblocks ? c[i] : 0;
+        uint32_t x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        uint32_t before = carry;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        if (i < nblocks) c[i] = before + x - v;
+        __syncthreads();
+        if (threadIdx.x == kBlock - 1) carry = before + x;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[d] = carry;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scatter(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, const uint32_t *d_n,
+          uint32_t n_fixed, uint32_t cap, int shift, int dbits, const uint32_t *__restrict__ hist,
+          const uint32_t *__restrict__ totals, uint32_t *__restrict__ keys_out,
+          uint32_t *__restrict__ vals_out) {
+    const int bins = 1 << dbits;
+    __shared__ uint32_t base[kMaxBins];
+    __shared__ uint32_t wcnt[kWaves][kMaxBins];
+    __shared__ uint32_t wsum[kWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    // digit bases: exclusive prefix of the digit totals + this block's offset
+    {
+        constexpr int per = kMaxBins / kBlock;
+        uint32_t loc[per];
+        uint32_t s = 0;
+        for (int k = 0; k < per; ++k) {
+            int d = threadIdx.x * per + k;
+            uint32_t v = d < bins ? totals[d] : 0;
+            loc[k] = s;
+            s += v;
+        }
+        uint32_t x = s;
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        before += x - s;
+        for (int k = 0; k < per; ++k) {
+            int d = threadIdx.x * per + k;
+            if (d < bins) base[d] = before + loc[k] + hist[(size_t)d * gridDim.x + blockIdx.x];
+        }
+        for (int w = 0; w < kWaves; ++w)
+            for (int d = threadIdx.x; d < bins; d += kBlock) wcnt[w][d] = 0;
+        __syncthreads();
+    }
+
+    const uint32_t n = resolve_n(d_n, n_fixed, cap);
+    const uint32_t L = (n + gridDim.x - 1) / gridDim.x;
+    const uint32_t lo = blockIdx.x * L;
+    const uint32_t hi = min(n, lo + L);
+    const uint32_t mask = (uint32_t)bins - 1;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (uint32_t t0 = lo; t0 < hi; t0 += kBlock) {
+        const uint32_t i = t0 + threadIdx.x;
+        const bool ok = i < hi;
+        uint32_t k = 0, v = 0, d = 0;
+        if (ok) {
+            k = keys[i];
+            v = vals[i];
+            d = (k >> shift) & mask;
+        }
+        // lanes holding the same digit
+        uint64_t peers = __ballot(ok);
+        for (int b = 0; b < dbits; ++b) {
+            uint64_t m = __ballot(ok && ((d >> b) & 1u));
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        const bool leader = ok && ((peers & lt) == 0);
+        if (leader) wcnt[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (ok) {
+            uint32_t pos = base[d] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+            keys_out[pos] = k;
+            vals_out[pos] = v;
+        }
+        __syncthreads();
+        if (leader) {
+            // the last wave's leader of each digit advances the base; every
+            // leader clears its own count afterwards
+            uint32_t tot = 0;
+            bool last = true;
+            for (int w = wave + 1; w < kWaves; ++w) last &= (wcnt[w][d] == 0);
+            if (last) {
+                for (int w = 0; w < kWaves; ++w) tot += wcnt[w][d];
+                base[d] += tot;
+            }
+        }
+        __syncthreads();
+        if (leader) wcnt[wave][d] = 0;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- scan
+constexpr int kScanChunk = 4096;
+
+__device__ __forceinline__ uint32_t scan_in(const uint32_t *in, const uint32_t *idx, uint32_t i) {
+    return idx ? in[idx[i]] : in[i];
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scan_reduce(const uint32_t *__restrict__ in, const uint32_t *__restrict__ idx, uint32_t n,
+              uint32_t *__restrict__ sums) {
+    __shared__ uint32_t wsum[kWaves];
+    const uint32_t lo = blockIdx.x * kScanChunk;
+    uint32_t s = 0;
+    for (uint32_t i = lo + threadIdx.x; i < min(n, lo + kScanChunk); i += kBlock) s += scan_in(in, idx, i);
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) sums[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scan_sums(uint32_t *__restrict__ sums, uint32_t nb, uint32_t *__restrict__ total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ uint32_t wsum[kWaves];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t b0 = 0; b0 < nb; b0 += kBlock) {
+        uint32_t i = b0 + threadIdx.x;
+        uint32_t v = i < nb ? sums[i] : 0;
+        uint32_t x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        uint32_t before = carry;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        if (i < nb) sums[i] = before + x - v;
+        __syncthreads();
+        if (threadIdx.x == kBlock - 1) carry = before + x;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scan_write(const uint32_t *__restrict__ in, const uint32_t *__restrict__ idx, uint32_t n,
+             const uint32_t *__restrict__ sums, uint32_t *__restrict__ out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ uint32_t wsum[kWaves];
+    uint32_t carry = sums[blockIdx.x];
+    const uint32_t lo = blockIdx.x * kScanChunk;
+    for (uint32_t t0 = lo; t0 < min(n, lo + kScanChunk); t0 += kBlock) {
+        uint32_t i = t0 + threadIdx.x;
+        uint32_t v = i < n ? scan_in(in, idx, i) : 0;
+        uint32_t x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        uint32_t before = carry;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        if (i < n) out[i] = before + x - v;
+        uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
+        carry += tot;
+    }
+}
+
+}  // namespace
+
+void radix_sort_pairs(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
+                      uint32_t *vals_alt, const uint32_t *d_n, uint32_t n_fixed, uint32_t cap,
+                      int bits, uint32_t *hist, uint32_t *totals) {
+    if (bits < 1) bits = 1;
+    if (bits > 32) bits = 32;
+    // smallest even pass count whose digits fit in kMaxDigitBits
+    int passes = 2;
+    while ((bits + passes - 1) / passes > kMaxDigitBits) passes += 2;
+    const int dbits = (bits + passes - 1) / passes;
+    uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+    int shift = 0;
+    for (int p = 0; p < passes; ++p) {
+        int w = dbits;
+        if (shift + w > 32) w = 32 - shift;
+        if (w < 1) w = 1;
+        const int bins = 1 << w;
+        hipLaunchKernelGGL(k_hist, dim3(kSortBlocks), dim3(kBlock), 0, s, ki, d_n, n_fixed, cap, shift, bins,
+                           hist);
+        hipLaunchKernelGGL(k_digit_scan, dim3(bins), dim3(kBlock), 0, s, hist, kSortBlocks, totals);
+        hipLaunchKernelGGL(k_scatter, dim3(kSortBlocks), dim3(kBlock), 0, s, ki, vi, d_n, n_fixed, cap, shift,
+                           w, hist, totals, ko, vo);
+        shift += w;
+        uint32_t *t = ki; ki = ko; ko = t;
+        t = vi; vi = vo; vo = t;
+    }
+}
+
+void exclusive_scan_u32(hipStream_t s, const uint32_t *in, uint32_t *out, uint32_t n,
+                        uint32_t *total_out, uint32_t *scratch) {
+    // scratch: at least ceil(n / kScanChunk) + 1 words; idx via the
+    // gather variant below
+    const uint32_t nb = (n + kScanChunk - 1) / kScanChunk;
+    if (nb == 0) {
+        launch_fill_u32(s, total_out, 0, 1);
+        return;
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, in, (const uint32_t *)nullptr, n, scratch);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, scratch, nb, total_out);
+    hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(kBlock), 0, s, in, (const uint32_t *)nullptr, n, scratch,
+                       out);
+}
+
+void exclusive_scan_gather_u32(hipStream_t s, const uint32_t *in, const uint32_t *idx, uint32_t *out,
+                               uint32_t n, uint32_t *total_out, uint32_t *scratch) {
+    const uint32_t nb = (n + kScanChunk - 1) / kScanChunk;
+    if (nb == 0) {
+        launch_fill_u32(s, total_out, 0, 1);
+        return;
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, in, idx, n, scratch);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, scratch, nb, total_out);
+    hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(kBlock), 0, s, in, idx, n, scratch, out);
+}
+
+}  // namespace swgs

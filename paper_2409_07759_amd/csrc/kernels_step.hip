@@ -1,0 +1,667 @@
+// Backward preprocess, optimiser step, relocation and mature.
+//
+// k_preprocess_bwd: per optimisable slot of the window set A, the chain rule
+// from the per-view record gradients d(u, v, A, B, C, o, rgb) to the slot's
+// parameters, summed over every view of the plan in which the slot is live
+// (Algorithm 1's backward; frozen slots get none, Sec. 4.2).  FP64, so the
+// clamp decisions (FoV clamp of the Jacobian, rgb >= 0) are those of the
+// forward.  No atomics: one thread owns one slot.
+//
+// k_adam_sgld: Adam over A with the adaptive mean-gradient scaling of
+// Sec. 4.5.1, then SGLD noise on the means (Algorithm 1's noise line,
+// Sec. 4.4), Philox4x32-10 normals.
+//
+// Relocation (Sec. 3.2): dead = logit below fl32(logit(0.005)); sources
+// drawn from the alive slots with integer opacity weights through an exact
+// 64-bit CDF search; the copies and the sources are rescaled.
+//
+// Mature (Algorithm 1's mature): snapshot, pack, re-arm.
+#include "swgs_internal.h"
+
+namespace swgs {
+namespace {
+
+constexpr int kBlock = 256;
+
+// ------------------------------------------------------------- Philox4x32-10
+// Salmon, Moraes, Dror, Shaw (SC'11): 10 rounds; multipliers 0xD2511F53 and
+// 0xCD9E8D57, key increments 0x9E3779B9 and 0xBB67AE85.
+__device__ __forceinline__ uint4 philox(uint4 c, uint2 k) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint32_t h0 = __umulhi(0xD2511F53u, c.x), l0 = 0xD2511F53u * c.x;
+        const uint32_t h1 = __umulhi(0xCD9E8D57u, c.z), l1 = 0xCD9E8D57u * c.z;
+        c = make_uint4(h1 ^ c.y ^ k.x, l1, h0 ^ c.w ^ k.y, l0);
+        k.x += 0x9E3779B9u;
+        k.y += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ void sh_basis_grad(int deg, double x, double y, double z, double *Y, double *gx,
+                                              double *gy, double *gz) {
+    for (int k = 0; k < 16; ++k) { gx[k] = 0; gy[k] = 0; gz[k] = 0; }
+    Y[0] = 0.28209479177387814;
+    if (deg < 1) return;
+    const double c1 = 0.4886025119029199;
+    Y[1] = -c1 * y; gy[1] = -c1;
+    Y[2] = c1 * z;  gz[2] = c1;
+    Y[3] = -c1 * x; gx[3] = -c1;
+    if (deg < 2) return;
+    const double a = 1.0925484305920792, b = 0.31539156525252005, c = 0.5462742152960396;
+    const double xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = a * x * y;                   gx[4] = a * y; gy[4] = a * x;
+    Y[5] = -a * y * z;                  gy[5] = -a * z; gz[5] = -a * y;
+    Y[6] = b * (2.0 * zz - xx - yy);    gx[6] = -2.0 * b * x; gy[6] = -2.0 * b * y; gz[6] = 4.0 * b * z;
+    Y[7] = -a * x * z;                  gx[7] = -a * z; gz[7] = -a * x;
+    Y[8] = c * (xx - yy);               gx[8] = 2.0 * c * x; gy[8] = -2.0 * c * y;
+    if (deg < 3) return;
+    const double e = 0.5900435899266435, f = 2.890611442640554, h = 0.4570457994644658;
+    const double m = 0.3731763325901154, n = 1.445305721320277;
+    Y[9] = -e * y * (3.0 * xx - yy);    gx[9] = -6.0 * e * x * y; gy[9] = -3.0 * e * (xx - yy);
+    Y[10] = f * x * y * z;              gx[10] = f * y * z; gy[10] = f * x * z; gz[10] = f * x * y;
+    Y[11] = -h * y * (4.0 * zz - xx - yy);
+    gx[11] = 2.0 * h * x * y; gy[11] = -h * (4.0 * zz - xx - 3.0 * yy); gz[11] = -8.0 * h * y * z;
+    Y[12] = m * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+    gx[12] = -6.0 * m * x * z; gy[12] = -6.0 * m * y * z; gz[12] = m * (6.0 * zz - 3.0 * xx - 3.0 * yy);
+    Y[13] = -h * x * (4.0 * zz - xx - yy);
+    gx[13] = -h * (4.0 * zz - 3.0 * xx - yy); gy[13] = 2.0 * h * x * y; gz[13] = -8.0 * h * x * z;
+    Y[14] = n * z * (xx - yy);          gx[14] = 2.0 * n * x * z; gy[14] = -2.0 * n * y * z; gz[14] = n * (xx - yy);
+    Y[15] = -e * x * (xx - 3.0 * yy);   gx[15] = -3.0 * e * (xx - yy); gy[15] = 6.0 * e * x * y;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_preprocess_bwd(const float *__restrict__ params, int n_slots, int num_gs, int deg,
+                 const uint32_t *__restrict__ listA, uint32_t nA, const GroupDev *__restrict__ groups,
+                 int n_groups, const int32_t *__restrict__ group_views, const ViewDev *__restrict__ views,
+                 const int32_t *__restrict__ pos_of, const uint32_t *__restrict__ depth_key,
+                 const float *__restrict__ rec_grad, size_t R, float *__restrict__ grads, int add_reg,
+                 double reg_o, double reg_s, double *__restrict__ reg_part) {
+    const uint32_t a = blockIdx.x * kBlock + threadIdx.x;
+    double rsig = 0.0, rscale = 0.0;
+    if (a < nA) {
+        const size_t S = (size_t)n_slots, NG = (size_t)num_gs;
+        const uint32_t slot = listA[a];
+        const double mx = params[slot], my = params[S + slot], mz = params[2 * S + slot];
+        const double q0r = params[6 * S + slot], q1r = params[7 * S + slot], q2r = params[8 * S + slot],
+                     q3r = params[9 * S + slot];
+        const double qn = sqrt(q0r * q0r + q1r * q1r + q2r * q2r + q3r * q3r);
+        const double w = q0r / qn, x = q1r / qn, y = q2r / qn, z = q3r / qn;
+        const double sc[3] = {exp((double)params[3 * S + slot]), exp((double)params[4 * S + slot]),
+                              exp((double)params[5 * S + slot])};
+        const double Rq[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
+                              2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
+                              2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)};
+        double M[9];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) M[3 * r + c] = Rq[3 * r + c] * sc[c];
+        double Sg[9];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) Sg[3 * r + c] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
+        const double lg = params[10 * S + slot];
+        const double op = 1.0 / (1.0 + exp(-lg));
+        const int nk = (deg + 1) * (deg + 1);
+
+        float dsh[48];
+        for (int i = 0; i < 3 * nk; ++i) dsh[i] = 0.0f;
+        double dmu[3] = {0, 0, 0}, H[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, dlogit = 0.0;
+
+        for (int g = 0; g < n_groups; ++g) {
+            const int32_t j = pos_of[(size_t)g * NG + slot];
+            if (j < 0) continue;
+            const GroupDev G = groups[g];
+            for (int kv = 0; kv < G.n_views; ++kv) {
+                const ViewDev &V = views[group_views[G.view_first + kv]];
+                const uint32_t r = V.rec_base + (uint32_t)j;
+                if (depth_key[r] == 0xFFFFFFFFu) continue;      // culled in this view
+                double d[9];
+                for (int c = 0; c < 9; ++c) d[c] = rec_grad[c * R + r];
+                // forward intermediates
+                const double px = V.R[0] * mx + V.R[1] * my + V.R[2] * mz + V.t[0];
+                const double py = V.R[3] * mx + V.R[4] * my + V.R[5] * mz + V.t[1];
+                const double pz = V.R[6] * mx + V.R[7] * my + V.R[8] * mz + V.t[2];
+                const double iz = 1.0 / pz;
+                const double txr = px * iz, tyr = py * iz;
+                const bool clx = txr < -V.limx || txr > V.limx, cly = tyr < -V.limy || tyr > V.limy;
+                const double tx = clx ? (txr < 0 ? -V.limx : V.limx) : txr;
+                const double ty = cly ? (tyr < 0 ? -V.limy : V.limy) : tyr;
+                const double J00 = V.fx * iz, J02 = -V.fx * tx * iz, J11 = V.fy * iz, J12 = -V.fy * ty * iz;
+                double T0[3], T1[3];
+                for (int c = 0; c < 3; ++c) {
+                    T0[c] = J00 * V.R[c] + J02 * V.R[6 + c];
+                    T1[c] = J11 * V.R[3 + c] + J12 * V.R[6 + c];
+                }
+                double A0[3], B0[3];
+                for (int r2 = 0; r2 < 3; ++r2) {
+                    A0[r2] = Sg[3 * r2] * T0[0] + Sg[3 * r2 + 1] * T0[1] + Sg[3 * r2 + 2] * T0[2];
+                    B0[r2] = Sg[3 * r2] * T1[0] + Sg[3 * r2 + 1] * T1[1] + Sg[3 * r2 + 2] * T1[2];
+                }
+                const double ca = T0[0] * A0[0] + T0[1] * A0[1] + T0[2] * A0[2] + 0.3;
+                const double cb = T0[0] * B0[0] + T0[1] * B0[1] + T0[2] * B0[2];
+                const double cc = T1[0] * B0[0] + T1[1] * B0[1] + T1[2] * B0[2] + 0.3;
+                const double det = ca * cc - cb * cb;
+
+                // colour
+                double dxv = mx - V.campos[0], dyv = my - V.campos[1], dzv = mz - V.campos[2];
+                const double dl = sqrt(dxv * dxv + dyv * dyv + dzv * dzv);
+                const double hx = dxv / dl, hy = dyv / dl, hz = dzv / dl;
+                double Y[16], gx[16], gy[16], gz[16];
+                sh_basis_grad(deg, hx, hy, hz, Y, gx, gy, gz);
+                double ddx = 0, ddy = 0, ddz = 0;
+                for (int ch = 0; ch < 3; ++ch) {
+                    double s = 0.5;
+                    for (int k = 0; k < nk; ++k) s += Y[k] * (double)params[(11 + 3 * k + ch) * S + slot];
+                    if (s <= 0.0) continue;
+                    const double gc = d[6 + ch];
+                    for (int k = 0; k < nk; ++k) {
+                        dsh[3 * k + ch] += (float)(Y[k] * gc);
+                        const double f = (double)params[(11 + 3 * k + ch) * S + slot] * gc;
+                        ddx += f * gx[k];
+                        ddy += f * gy[k];
+                        ddz += f * gz[k];
+                    }
+                }
+                const double dot = ddx * hx + ddy * hy + ddz * hz;
+                dmu[0] += (ddx - hx * dot) / dl;
+                dmu[1] += (ddy - hy * dot) / dl;
+                dmu[2] += (ddz - hz * dot) / dl;
+
+                dlogit += d[5] * op * (1.0 - op);
+
+                // conic (A, B, C) = (c, -b, a) / det
+                const double i2 = 1.0 / (det * det);
+                const double gA = d[2], gB = d[3], gC = d[4];
+                const double dca = (-cc * cc * gA + cb * cc * gB - cb * cb * gC) * i2;
+                const double dcb = (2.0 * cb * cc * gA - (ca * cc + cb * cb) * gB + 2.0 * ca * cb * gC) * i2;
+                const double dcc = (-cb * cb * gA + ca * cb * gB - ca * ca * gC) * i2;
+                // symmetric part of dL/dSigma, summed over views
+                for (int r2 = 0; r2 < 3; ++r2)
+                    for (int c = 0; c < 3; ++c)
+                        H[3 * r2 + c] += 2.0 * dca * T0[r2] * T0[c] + dcb * (T0[r2] * T1[c] + T1[r2] * T0[c]) +
+                                         2.0 * dcc * T1[r2] * T1[c];
+                double dT0[3], dT1[3];
+                for (int c = 0; c < 3; ++c) {
+                    dT0[c] = 2.0 * dca * A0[c] + dcb * B0[c];
+                    dT1[c] = dcb * A0[c] + 2.0 * dcc * B0[c];
+                }
+                // T = J R: dJ_rk = sum_c dT_rc R_kc
+                const double dJ00 = dT0[0] * V.R[0] + dT0[1] * V.R[1] + dT0[2] * V.R[2];
+                const double dJ02 = dT0[0] * V.R[6] + dT0[1] * V.R[7] + dT0[2] * V.R[8];
+                const double dJ11 = dT1[0] * V.R[3] + dT1[1] * V.R[4] + dT1[2] * V.R[5];
+                const double dJ12 = dT1[0] * V.R[6] + dT1[1] * V.R[7] + dT1[2] * V.R[8];
+                double dpx = 0, dpy = 0, dpz = 0;
+                dpz += -dJ00 * V.fx * iz * iz + dJ02 * V.fx * tx * iz * iz - dJ11 * V.fy * iz * iz +
+                       dJ12 * V.fy * ty * iz * iz;
+                const double dtx = -dJ02 * V.fx * iz, dty = -dJ12 * V.fy * iz;
+                if (!clx) { dpx += dtx * iz; dpz -= dtx * px * iz * iz; }
+                if (!cly) { dpy += dty * iz; dpz -= dty * py * iz * iz; }
+                // projected mean
+                dpx += d[0] * V.fx * iz;
+                dpz -= d[0] * V.fx * px * iz * iz;
+                dpy += d[1] * V.fy * iz;
+                dpz -= d[1] * V.fy * py * iz * iz;
+                dmu[0] += V.R[0] * dpx + V.R[3] * dpy + V.R[6] * dpz;
+                dmu[1] += V.R[1] * dpx + V.R[4] * dpy + V.R[7] * dpz;
+                dmu[2] += V.R[2] * dpx + V.R[5] * dpy + V.R[8] * dpz;
+            }
+        }
+        // Sigma = M M^T: dM = H M; M = Rq diag(sc)
+        double dRq[9], ds[3];
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0.0;
+            for (int r2 = 0; r2 < 3; ++r2) {
+                const double dm = H[3 * r2] * M[c] + H[3 * r2 + 1] * M[3 + c] + H[3 * r2 + 2] * M[6 + c];
+                dRq[3 * r2 + c] = dm * sc[c];
+                acc += dm * Rq[3 * r2 + c];
+            }
+            ds[c] = acc * sc[c];
+        }
+        double dq[4];
+        dq[0] = 2.0 * (-z * dRq[1] + y * dRq[2] + z * dRq[3] - x * dRq[5] - y * dRq[6] + x * dRq[7]);
+        dq[1] = 2.0 * (y * dRq[1] + z * dRq[2] + y * dRq[3] - 2.0 * x * dRq[4] - w * dRq[5] + z * dRq[6] +
+                       w * dRq[7] - 2.0 * x * dRq[8]);
+        dq[2] = 2.0 * (-2.0 * y * dRq[0] + x * dRq[1] + w * dRq[2] + x * dRq[3] + z * dRq[5] - w * dRq[6] +
+                       z * dRq[7] - 2.0 * y * dRq[8]);
+        dq[3] = 2.0 * (-2.0 * z * dRq[0] - w * dRq[1] + x * dRq[2] + w * dRq[3] - 2.0 * z * dRq[4] + y * dRq[5] +
+                       x * dRq[6] + y * dRq[7]);
+        const double qd = dq[0] * w + dq[1] * x + dq[2] * y + dq[3] * z;
+        const double qh[4] = {w, x, y, z};
+        if (add_reg) {
+            dlogit += reg_o * op * (1.0 - op);
+            for (int c = 0; c < 3; ++c) ds[c] += reg_s * sc[c];
+        }
+        rsig = op;
+        rscale = sc[0] + sc[1] + sc[2];
+        for (int c = 0; c < 3; ++c) grads[c * NG + slot] = (float)dmu[c];
+        for (int c = 0; c < 3; ++c) grads[(3 + c) * NG + slot] = (float)ds[c];
+        for (int k = 0; k < 4; ++k) grads[(6 + k) * NG + slot] = (float)((dq[k] - qh[k] * qd) / qn);
+        grads[10 * NG + slot] = (float)dlogit;
+        for (int i = 0; i < 3 * nk; ++i) grads[(11 + i) * NG + slot] = dsh[i];
+    }
+    // regulariser sums (for the reported loss)
+    __shared__ double red[2][kBlock / 64];
+    for (int o = 32; o > 0; o >>= 1) {
+        rsig += __shfl_xor(rsig, o, 64);
+        rscale += __shfl_xor(rscale, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = rsig;
+        red[1][threadIdx.x >> 6] = rscale;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s0 = 0, s1 = 0;
+        for (int w2 = 0; w2 < kBlock / 64; ++w2) { s0 += red[0][w2]; s1 += red[1][w2]; }
+        reg_part[2 * blockIdx.x] = s0;
+        reg_part[2 * blockIdx.x + 1] = s1;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_reg_reduce(const double *__restrict__ part, int nparts, double lo, double ls, double invA,
+             const uint32_t *__restrict__ pair_count, double *__restrict__ stats) {
+    __shared__ double sa[256], sb[256];
+    double a = 0, b = 0;
+    for (int i = threadIdx.x; i < nparts; i += 256) { a += part[2 * i]; b += part[2 * i + 1]; }
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) { sa[threadIdx.x] += sa[threadIdx.x + s]; sb[threadIdx.x] += sb[threadIdx.x + s]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        stats[2] = lo * sa[0] * invA + ls * sb[0] * invA;
+        stats[3] = stats[0] + stats[2];
+        stats[4] = (double)pair_count[0];
+        stats[6] = (double)pair_count[1];
+    }
+}
+
+// --------------------------------------------------------------- Adam + SGLD
+__global__ void __launch_bounds__(kBlock)
+k_adam_sgld(float *__restrict__ params, int n_slots, const float *__restrict__ grads, float *__restrict__ m,
+            float *__restrict__ v, int num_gs, int F, const uint32_t *__restrict__ listA, uint32_t nA,
+            const int32_t *__restrict__ start, swgs_step_cfg cfg, int swin, const StepDev *__restrict__ sd,
+            const float *__restrict__ eta) {
+    const uint32_t a = blockIdx.x * kBlock + threadIdx.x;
+    if (a >= nA) return;
+    const size_t S = (size_t)n_slots, NG = (size_t)num_gs;
+    const uint32_t slot = listA[a];
+    const StepDev st = *sd;
+    const double t = (double)st.adam_t;
+    const float bc1 = (float)(1.0 - pow((double)cfg.beta1, t));
+    const float bc2 = (float)(1.0 - pow((double)cfg.beta2, t));
+    float gscale = 1.0f;
+    if (cfg.grad_scale_base > 0.0f) {
+        int wtr = cfg.window_start - start[slot] + swin - 1;
+        wtr = wtr < 0 ? 0 : (wtr > swin - 1 ? swin - 1 : wtr);
+        gscale = (float)pow((double)cfg.grad_scale_base, (double)wtr / (double)swin);
+    }
+    for (int r = 0; r < F; ++r) {
+        const float lr = r < 3 ? cfg.lr_mean
+                       : r < 6 ? cfg.lr_scale
+                       : r < 10 ? cfg.lr_quat
+                       : r == 10 ? cfg.lr_logit
+                       : r < 14 ? cfg.lr_sh_dc : cfg.lr_sh_rest;
+        float g = grads[r * NG + slot];
+        if (r < 3) g *= gscale;
+        const float mm = cfg.beta1 * m[r * NG + slot] + (1.0f - cfg.beta1) * g;
+        const float vv = cfg.beta2 * v[r * NG + slot] + (1.0f - cfg.beta2) * g * g;
+        m[r * NG + slot] = mm;
+        v[r * NG + slot] = vv;
+        const float mh = mm / bc1, vh = vv / bc2;
+        params[r * S + slot] -= lr * mh / (sqrtf(vh) + cfg.eps);
+    }
+    if (cfg.noise_lr == 0.0f) return;
+    // SGLD noise with the updated covariance and opacity
+    float e0, e1, e2;
+    if (eta) {
+        e0 = eta[slot];
+        e1 = eta[NG + slot];
+        e2 = eta[2 * NG + slot];
+    } else {
+        const uint4 x = philox(make_uint4(slot, (uint32_t)st.step, (uint32_t)(st.step >> 32), 0x4E4F4953u),
+                               make_uint2((uint32_t)st.seed, (uint32_t)(st.seed >> 32)));
+        const float u1 = (float)((x.x >> 8) + 1u) * 5.9604644775390625e-8f;
+        const float u2 = (float)(x.y >> 8) * 5.9604644775390625e-8f;
+        const float u3 = (float)((x.z >> 8) + 1u) * 5.9604644775390625e-8f;
+        const float u4 = (float)(x.w >> 8) * 5.9604644775390625e-8f;
+        const float r1 = sqrtf(-2.0f * logf(u1)), r2 = sqrtf(-2.0f * logf(u3));
+        const float twopi = 6.283185307179586f;
+        e0 = r1 * cosf(twopi * u2);
+        e1 = r1 * sinf(twopi * u2);
+        e2 = r2 * cosf(twopi * u4);
+    }
+    float qw = params[6 * S + slot], qx = params[7 * S + slot], qy = params[8 * S + slot], qz = params[9 * S + slot];
+    const float qi = rsqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw *= qi; qx *= qi; qy *= qi; qz *= qi;
+    const float s0 = expf(params[3 * S + slot]), s1 = expf(params[4 * S + slot]), s2 = expf(params[5 * S + slot]);
+    const float R[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
+                        2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
+                        2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)};
+    // Sigma eta = R S^2 R^T eta
+    const float w0 = s0 * s0 * (R[0] * e0 + R[3] * e1 + R[6] * e2);
+    const float w1 = s1 * s1 * (R[1] * e0 + R[4] * e1 + R[7] * e2);
+    const float w2 = s2 * s2 * (R[2] * e0 + R[5] * e1 + R[8] * e2);
+    const float o = 1.0f / (1.0f + expf(-params[10 * S + slot]));
+    const float gate = 1.0f / (1.0f + expf(cfg.noise_k * (o - cfg.noise_t0)));
+    const float coef = cfg.noise_lr * cfg.lr_mean * gate;
+    params[0 * S + slot] += coef * (R[0] * w0 + R[1] * w1 + R[2] * w2);
+    params[1 * S + slot] += coef * (R[3] * w0 + R[4] * w1 + R[5] * w2);
+    params[2 * S + slot] += coef * (R[6] * w0 + R[7] * w1 + R[8] * w2);
+}
+
+__global__ void k_set_step(StepDev *sd, int64_t adam_t, uint64_t step, uint64_t seed) {
+    sd->adam_t = adam_t;
+    sd->step = step;
+    sd->seed = seed;
+}
+__global__ void k_advance_step(StepDev *sd) {
+    sd->adam_t += 1;
+    sd->step += 1;
+}
+
+// ------------------------------------------------------------------ relocation
+__device__ __forceinline__ double softplus(double x) { return x > 0 ? x + log1p(exp(-x)) : log1p(exp(x)); }
+
+// S_N(a) = sum_{i=1..N} sum_{k<i} C(i-1,k) (-1)^k a^{k+1}/sqrt(k+1); summing
+// over i first (sum_{i=k+1..N} C(i-1,k) = C(N,k+1)) gives the single sum
+// sum_{m=1..N} (-1)^{m-1} C(N,m) a^m / sqrt(m).
+__device__ double reloc_SN(int N, double a) {
+    double s = 0.0, binom = 1.0, ap = 1.0;
+    for (int mm = 1; mm <= N; ++mm) {
+        binom = binom * (double)(N - mm + 1) / (double)mm;
+        ap *= a;
+        const double term = binom * ap / sqrt((double)mm);
+        s += (mm & 1) ? term : -term;
+    }
+    return s;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_reloc_flags(const float *__restrict__ params, int n_slots, const uint32_t *__restrict__ listA, uint32_t nA,
+              const StepDev *__restrict__ sd, int period, uint32_t *__restrict__ dead, uint64_t *__restrict__ w) {
+    const uint32_t a = blockIdx.x * kBlock + threadIdx.x;
+    if (a >= nA) return;
+    const bool on = period > 0 && (sd->step % (uint64_t)period) == 0;
+    const float lg = params[10 * (size_t)n_slots + listA[a]];
+    const float Ls = -5.293304824724492f;   // fl32(ln(0.005/0.995))
+    const bool d = on && lg < Ls;
+    dead[a] = d ? 1u : 0u;
+    w[a] = (!on || d) ? 0ull : (uint64_t)floor(16777216.0 / (1.0 + exp(-(double)lg)));
+}
+
+// inclusive u64 scan, single pass per 2048-chunk + carry chain over chunks
+constexpr int kU64Chunk = 2048;
+__global__ void __launch_bounds__(kBlock)
+k_u64_reduce(const uint64_t *__restrict__ in, uint32_t n, uint64_t *__restrict__ sums) {
+    __shared__ uint64_t ws[kBlock / 64];
+    uint64_t s = 0;
+    const uint32_t lo = blockIdx.x * kU64Chunk;
+    for (uint32_t i = lo + threadIdx.x; i < min(n, lo + kU64Chunk); i += kBlock) s += in[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) sums[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+__global__ void k_u64_carry(uint64_t *sums, uint32_t nb, uint64_t *total) {
+    if (threadIdx.x != 0) return;
+    uint64_t c = 0;
+    for (uint32_t i = 0; i < nb; ++i) { uint64_t v = sums[i]; sums[i] = c; c += v; }
+    *total = c;
+}
+__global__ void __launch_bounds__(kBlock)
+k_u64_write(uint64_t *__restrict__ io, uint32_t n, const uint64_t *__restrict__ sums) {
+    __shared__ uint64_t ws[kBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint64_t carry = sums[blockIdx.x];
+    const uint32_t lo = blockIdx.x * kU64Chunk;
+    for (uint32_t t0 = lo; t0 < min(n, lo + kU64Chunk); t0 += kBlock) {
+        const uint32_t i = t0 + threadIdx.x;
+        uint64_t x = i < n ? io[i] : 0;
+        for (int o = 1; o < 64; o <<= 1) {
+            uint64_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) ws[wave] = x;
+        __syncthreads();
+        uint64_t before = carry;
+        for (int w = 0; w < wave; ++w) before += ws[w];
+        if (i < n) io[i] = before + x;          // inclusive
+        const uint64_t tot = ws[0] + ws[1] + ws[2] + ws[3];
+        __syncthreads();
+        carry += tot;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_reloc_dst(const uint32_t *__restrict__ dead, const uint32_t *__restrict__ dpos, const uint32_t *__restrict__ listA,
+            uint32_t nA, int32_t *__restrict__ dst) {
+    const uint32_t a = blockIdx.x * kBlock + threadIdx.x;
+    if (a < nA && dead[a]) dst[dpos[a]] = (int32_t)listA[a];
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_reloc_draw(const uint64_t *__restrict__ pref, uint32_t nA, const uint64_t *__restrict__ Wtot,
+             const uint32_t *__restrict__ nD, const StepDev *__restrict__ sd, const uint32_t *__restrict__ listA,
+             int32_t *__restrict__ src, uint32_t *__restrict__ src_a, uint32_t *__restrict__ cnt) {
+    const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t W = *Wtot;
+    if (j >= *nD || W == 0) return;
+    const StepDev st = *sd;
+    const uint4 x = philox(make_uint4(j, (uint32_t)st.step, (uint32_t)(st.step >> 32), 0x52454C4Fu),
+                           make_uint2((uint32_t)st.seed, (uint32_t)(st.seed >> 32)));
+    const uint64_t r = (uint64_t)x.x | ((uint64_t)x.y << 32);
+    const uint64_t u = __umul64hi(r, W);
+    // first a with pref[a] > u
+    uint32_t lo = 0, hi = nA;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pref[mid] > u) hi = mid; else lo = mid + 1;
+    }
+    src_a[j] = lo;
+    src[j] = (int32_t)listA[lo];
+    atomicAdd(cnt + lo, 1u);
+}
+
+__device__ __forceinline__ void reloc_new(double lg, int N, double &newlogit, double &dscale) {
+    const double l1m = -softplus(lg) / (double)N;      // ln(1 - o')
+    const double on = -expm1(l1m);                     // o'
+    newlogit = log(on) - l1m;
+    dscale = -softplus(-lg) - log(reloc_SN(N, on));
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_reloc_copies(float *__restrict__ params, int n_slots, float *__restrict__ m, float *__restrict__ v, int num_gs,
+               int F, const int32_t *__restrict__ dst, const int32_t *__restrict__ src,
+               const uint32_t *__restrict__ src_a, const uint32_t *__restrict__ cnt, const uint32_t *__restrict__ nD,
+               const uint64_t *__restrict__ Wtot, int n_max) {
+    const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= *nD || *Wtot == 0) return;
+    const size_t S = (size_t)n_slots, NG = (size_t)num_gs;
+    const int d = dst[j], s = src[j];
+    int N = 1 + (int)cnt[src_a[j]];
+    if (N > n_max) N = n_max;
+    double nl, dsc;
+    reloc_new((double)params[10 * S + s], N, nl, dsc);
+    for (int r = 0; r < F; ++r) params[r * S + d] = params[r * S + s];
+    params[10 * S + d] = (float)nl;
+    for (int c = 0; c < 3; ++c) params[(3 + c) * S + d] = (float)((double)params[(3 + c) * S + s] + dsc);
+    for (int r = 0; r < F; ++r) { m[r * NG + d] = 0.0f; v[r * NG + d] = 0.0f; }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_reloc_sources(float *__restrict__ params, int n_slots, float *__restrict__ m, float *__restrict__ v, int num_gs,
+                int F, const uint32_t *__restrict__ listA, uint32_t nA, const uint32_t *__restrict__ cnt, int n_max) {
+    const uint32_t a = blockIdx.x * kBlock + threadIdx.x;
+    if (a >= nA || cnt[a] == 0) return;
+    const size_t S = (size_t)n_slots, NG = (size_t)num_gs;
+    const uint32_t s = listA[a];
+    int N = 1 + (int)cnt[a];
+    if (N > n_max) N = n_max;
+    double nl, dsc;
+    reloc_new((double)params[10 * S + s], N, nl, dsc);
+    params[10 * S + s] = (float)nl;
+    for (int c = 0; c < 3; ++c) params[(3 + c) * S + s] = (float)((double)params[(3 + c) * S + s] + dsc);
+    for (int r = 0; r < F; ++r) { m[r * NG + s] = 0.0f; v[r * NG + s] = 0.0f; }
+}
+
+__global__ void k_reloc_finish(const uint32_t *nD, const uint64_t *Wtot, int32_t *count_out, double *stats) {
+    const int32_t c = (*Wtot == 0) ? 0 : (int32_t)*nD;
+    if (count_out) *count_out = c;
+    if (stats) stats[5] = (double)c;
+}
+
+__global__ void k_stats_out(const double *in, const uint32_t *pc, const uint32_t *nA, double *out) {
+    for (int i = 0; i < 8; ++i) out[i] = in[i];
+    out[4] = (double)pc[0];
+    out[6] = (double)pc[1];
+    if (nA) out[7] = (double)nA[0];
+}
+
+// -------------------------------------------------------------------- mature
+__global__ void __launch_bounds__(kBlock)
+k_mature_flags(const int32_t *__restrict__ start, int num_gs, int st, uint32_t *__restrict__ flag) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < num_gs) flag[i] = start[i] < st ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_mature_pack(float *__restrict__ params, int n_slots, int num_gs, int F, int swin, int sh_degree, int st,
+              int32_t *__restrict__ birth, int32_t *__restrict__ start, int32_t *__restrict__ expire,
+              const uint32_t *__restrict__ flag, const uint32_t *__restrict__ pos, const uint32_t *__restrict__ count,
+              uint8_t *__restrict__ record) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t n = *count;
+    if (i == 0) {
+        int32_t *h = reinterpret_cast<int32_t *>(record);
+        h[0] = 0x53475753; h[1] = 1; h[2] = st; h[3] = (int32_t)n;
+        h[4] = sh_degree; h[5] = F; h[6] = swin; h[7] = 0;
+    }
+    if (i >= num_gs || !flag[i]) return;
+    const size_t S = (size_t)n_slots;
+    const uint32_t k = pos[i];
+    uint32_t *slots = reinterpret_cast<uint32_t *>(record + 32);
+    int32_t *lb = reinterpret_cast<int32_t *>(record + 32 + 4 * (size_t)n);
+    float *pr = reinterpret_cast<float *>(record + 32 + 16 * (size_t)n);
+    slots[k] = (uint32_t)i;
+    const int32_t b = birth[i], s = start[i], e = expire[i];
+    lb[k] = b;
+    lb[n + k] = s;
+    lb[2 * (size_t)n + k] = e;
+    for (int r = 0; r < F; ++r) {
+        const float x = params[r * S + i];
+        pr[(size_t)r * n + k] = x;
+        params[r * S + num_gs + i] = x;
+    }
+    birth[num_gs + i] = b;
+    start[num_gs + i] = s;
+    expire[num_gs + i] = e;
+    birth[i] = e;
+    start[i] = e;
+    expire[i] = e + swin;
+}
+
+}  // namespace
+
+void launch_preprocess_backward(hipStream_t s, const swgs_plan &p, uint8_t *ws, int add_reg,
+                                float lambda_o, float lambda_s) {
+    const uint32_t nA = p.n_A;
+    const int nb = (int)((nA + kBlock - 1) / kBlock);
+    if (nb == 0) return;
+    const double inv = nA ? 1.0 / (double)nA : 0.0;
+    hipLaunchKernelGGL(k_preprocess_bwd, dim3(nb), dim3(kBlock), 0, s, p.pool.params, p.pool.n_slots,
+                       p.pool.num_gs, p.sh_degree, wsp<uint32_t>(ws, p, WB_ACTIVE_LIST) + p.list_A_base, nA,
+                       wsp<GroupDev>(ws, p, WB_GROUPS), (int)p.groups.size(), wsp<int32_t>(ws, p, WB_GROUP_VIEWS),
+                       wsp<ViewDev>(ws, p, WB_VIEWS), wsp<int32_t>(ws, p, WB_POS_OF),
+                       wsp<uint32_t>(ws, p, WB_DEPTH_KEY), wsp<float>(ws, p, WB_REC_GRAD), (size_t)p.R,
+                       p.pool.grads, add_reg, (double)lambda_o * inv, (double)lambda_s * inv,
+                       wsp<double>(ws, p, WB_REG_PART));
+    hipLaunchKernelGGL(k_reg_reduce, dim3(1), dim3(256), 0, s, wsp<double>(ws, p, WB_REG_PART), nb,
+                       (double)lambda_o, (double)lambda_s, inv, wsp<uint32_t>(ws, p, WB_PAIR_COUNT),
+                       wsp<double>(ws, p, WB_STATS));
+}
+
+void launch_adam_sgld(hipStream_t s, const swgs_plan &p, uint8_t *ws, const swgs_step_cfg &cfg,
+                      const float *eta) {
+    const uint32_t nA = p.n_A;
+    if (!nA) return;
+    hipLaunchKernelGGL(k_adam_sgld, dim3((nA + kBlock - 1) / kBlock), dim3(kBlock), 0, s, p.pool.params,
+                       p.pool.n_slots, p.pool.grads, p.pool.adam_m, p.pool.adam_v, p.pool.num_gs, p.F,
+                       wsp<uint32_t>(ws, p, WB_ACTIVE_LIST) + p.list_A_base, nA, p.pool.start, cfg, p.pool.swin,
+                       wsp<StepDev>(ws, p, WB_STEP), eta);
+}
+
+void launch_relocate(hipStream_t s, const swgs_plan &p, uint8_t *ws, const swgs_step_cfg &cfg,
+                     int32_t *dst_out, int32_t *src_out, int32_t *count_out) {
+    const uint32_t nA = p.n_A;
+    const uint32_t *listA = wsp<uint32_t>(ws, p, WB_ACTIVE_LIST) + p.list_A_base;
+    uint64_t *w = wsp<uint64_t>(ws, p, WB_RELOC_W);
+    uint32_t *dead = wsp<uint32_t>(ws, p, WB_RELOC_FLAG);
+    uint32_t *dpos = dead + nA + 1;
+    uint32_t *cnt = wsp<uint32_t>(ws, p, WB_RELOC_CNT);
+    uint32_t *src_a = cnt + nA + 1;
+    uint32_t *nD = wsp<uint32_t>(ws, p, WB_RELOC_SCAN);
+    uint32_t *scan_scratch = nD + 4;
+    uint64_t *sums = wsp<uint64_t>(ws, p, WB_RELOC_W) + nA + 1;
+    uint64_t *Wtot = sums + (nA + kU64Chunk - 1) / kU64Chunk + 1;
+    int32_t *dst = dst_out ? dst_out : wsp<int32_t>(ws, p, WB_RELOC_DST);
+    int32_t *src = src_out ? src_out : wsp<int32_t>(ws, p, WB_RELOC_SRC);
+    const StepDev *sd = wsp<StepDev>(ws, p, WB_STEP);
+    double *stats = wsp<double>(ws, p, WB_STATS);
+    if (nA == 0) {
+        launch_fill_u32(s, nD, 0, 1);
+        hipLaunchKernelGGL(k_u64_carry, dim3(1), dim3(1), 0, s, sums, 0u, Wtot);
+        hipLaunchKernelGGL(k_reloc_finish, dim3(1), dim3(1), 0, s, nD, Wtot, count_out, stats);
+        return;
+    }
+    const int nb = (int)((nA + kBlock - 1) / kBlock);
+    launch_fill_u32(s, cnt, 0, nA);
+    hipLaunchKernelGGL(k_reloc_flags, dim3(nb), dim3(kBlock), 0, s, p.pool.params, p.pool.n_slots, listA, nA, sd,
+                       cfg.relocate_period, dead, w);
+    exclusive_scan_u32(s, dead, dpos, nA, nD, scan_scratch);
+    const uint32_t nbu = (nA + kU64Chunk - 1) / kU64Chunk;
+    hipLaunchKernelGGL(k_u64_reduce, dim3(nbu), dim3(kBlock), 0, s, w, nA, sums);
+    hipLaunchKernelGGL(k_u64_carry, dim3(1), dim3(1), 0, s, sums, nbu, Wtot);
+    hipLaunchKernelGGL(k_u64_write, dim3(nbu), dim3(kBlock), 0, s, w, nA, sums);
+    hipLaunchKernelGGL(k_reloc_dst, dim3(nb), dim3(kBlock), 0, s, dead, dpos, listA, nA, dst);
+    hipLaunchKernelGGL(k_reloc_draw, dim3(nb), dim3(kBlock), 0, s, w, nA, Wtot, nD, sd, listA, src, src_a, cnt);
+    hipLaunchKernelGGL(k_reloc_copies, dim3(nb), dim3(kBlock), 0, s, p.pool.params, p.pool.n_slots, p.pool.adam_m,
+                       p.pool.adam_v, p.pool.num_gs, p.F, dst, src, src_a, cnt, nD, Wtot, cfg.reloc_n_max);
+    hipLaunchKernelGGL(k_reloc_sources, dim3(nb), dim3(kBlock), 0, s, p.pool.params, p.pool.n_slots, p.pool.adam_m,
+                       p.pool.adam_v, p.pool.num_gs, p.F, listA, nA, cnt, cfg.reloc_n_max);
+    hipLaunchKernelGGL(k_reloc_finish, dim3(1), dim3(1), 0, s, nD, Wtot, count_out, stats);
+}
+
+void launch_set_step(hipStream_t s, uint8_t *ws_step, int64_t adam_t, uint64_t step, uint64_t seed) {
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, reinterpret_cast<StepDev *>(ws_step), adam_t, step, seed);
+}
+
+void launch_advance_step(hipStream_t s, uint8_t *ws_step) {
+    hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(1), 0, s, reinterpret_cast<StepDev *>(ws_step));
+}
+
+void launch_stats_out(hipStream_t s, const double *stats, const uint32_t *pair_count, const uint32_t *nA,
+                      double *out) {
+    hipLaunchKernelGGL(k_stats_out, dim3(1), dim3(1), 0, s, stats, pair_count, nA, out);
+}
+
+void launch_mature(hipStream_t s, const swgs_pool &pool, int F, int st, uint8_t *record, uint32_t *scratch,
+                   uint32_t *d_count) {
+    const int n = pool.num_gs;
+    uint32_t *flag = scratch;
+    uint32_t *pos = scratch + n + 1;
+    uint32_t *scan_scratch = pos + n + 1;
+    const int nb = (n + kBlock - 1) / kBlock;
+    if (nb == 0) {
+        launch_fill_u32(s, d_count, 0, 1);
+        return;
+    }
+    hipLaunchKernelGGL(k_mature_flags, dim3(nb), dim3(kBlock), 0, s, pool.start, n, st, flag);
+    exclusive_scan_u32(s, flag, pos, (uint32_t)n, d_count, scan_scratch);
+    hipLaunchKernelGGL(k_mature_pack, dim3(nb), dim3(kBlock), 0, s, pool.params, pool.n_slots, n, F, pool.swin,
+                       pool.sh_degree, st, pool.birth, pool.start, pool.expire, flag, pos, d_count, record);
+}
+
+}  // namespace swgs

@@ -1,0 +1,187 @@
+// Internal declarations shared by the translation units of libswgs.so.
+// Nothing here is part of the public ABI (include/swgs.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/swgs.h"
+
+namespace swgs {
+
+// ----------------------------------------------------------------- limits
+constexpr int kMaxShDegree = 3;
+constexpr int kMaxRows = 11 + 3 * 16;      // F at SH degree 3
+constexpr int kGateChunk = 2048;           // slots per gating block
+constexpr int kSortBlocks = 1024;          // fixed grid of the radix-sort passes
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kSplatFloats = 12;           // floats per splat record
+
+inline int rows_for(int sh_degree) { return 11 + 3 * (sh_degree + 1) * (sh_degree + 1); }
+
+// A view as the kernels see it: camera in FP64 plus its place in the plan.
+struct ViewDev {
+    double R[9];
+    double t[3];
+    double fx, fy, cx, cy;
+    double campos[3];          // camera centre in world coordinates
+    double limx, limy;         // 1.3 * tan(half FoV) per axis
+    float bg[3];
+    int32_t frame;
+    int32_t width, height;
+    int32_t tiles_x, tiles_y;
+    int32_t group;             // distinct-frame group
+    uint32_t rec_base;         // first record of this view
+    uint32_t tile_base;        // first global tile id of this view
+    int64_t pix_base;          // first pixel of this view in the image buffers
+    float inv_norm;            // 1 / (V * 3 * H * W): L1 gradient scale
+    int32_t pad;
+};
+
+struct GroupDev {
+    int32_t frame;
+    int32_t n_views;
+    int32_t view_first;        // index into the plan's group-ordered view list
+    uint32_t list_base;        // first entry of this group's live list
+    uint32_t n_live;           // live slots (known at plan time)
+    uint32_t pad;
+};
+
+// Byte offsets of every workspace buffer.
+struct Layout {
+    size_t off[64];
+    size_t size[64];
+    size_t total = 0;
+};
+
+enum WsBuf {
+    WB_ACTIVE_LIST = 0, WB_ACTIVE_COUNT, WB_REC_VIEW_BASE, WB_DEPTH_KEY, WB_TILE_COUNT,
+    WB_RECT, WB_SPLAT, WB_PAIR_KEY, WB_PAIR_VAL, WB_PAIR_COUNT, WB_TILE_RANGE, WB_T_FINAL,
+    WB_DLDC, WB_REC_GRAD,
+    // internal
+    WB_GATE_BLK, WB_POS_OF, WB_REC_IDX, WB_KEY_ALT, WB_IDX_ALT, WB_PAIR_KEY_ALT, WB_PAIR_VAL_ALT,
+    WB_PAIR_OFFSET, WB_SORT_HIST, WB_SORT_TOTAL, WB_LAST, WB_LOSS_PART, WB_STATS, WB_STEP,
+    WB_VIEWS, WB_GROUPS, WB_GROUP_VIEWS,
+    WB_RELOC_W, WB_RELOC_FLAG, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_CNT, WB_RELOC_SCAN, WB_REG_PART, WB_COUNTERS,
+    WB_COUNT
+};
+
+}  // namespace swgs
+
+struct swgs_context {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+};
+
+struct swgs_plan {
+    swgs_pool pool{};
+    int sh_degree = 0;
+    int F = 0;
+    int tile_w = 16, tile_h = 16;
+    int lds_batch = 256;
+    int64_t pair_cap = 0;
+    std::vector<swgs_view> views;                 // caller order
+    std::vector<swgs::ViewDev> vdev;              // caller order
+    std::vector<swgs::GroupDev> groups;           // distinct frames
+    std::vector<int32_t> group_views;             // view indices ordered by group
+    uint32_t n_A = 0;                             // |A|
+    uint32_t list_A_base = 0;
+    int64_t R = 0, P = 0, T = 0;
+    int depth_key_bits = 32, tile_key_bits = 1;
+    int loss_blocks = 0;
+    swgs::Layout lay;
+    // graph mode
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    void *graph_ws = nullptr;
+    const void *graph_targets = nullptr;
+    void *graph_images = nullptr;
+    double *graph_stats = nullptr;
+    swgs_step_cfg graph_cfg{};
+    void *consts_host = nullptr;                  // pinned copy of the constant block
+    size_t consts_bytes = 0;
+    // event timing of kernel classes (off unless enabled; never inside a graph)
+    bool timing = false;
+    std::vector<hipEvent_t> ev[8];
+    size_t ev_used[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+};
+
+namespace swgs {
+
+// ----------------------------------------------------------- launchers
+// Gating / compaction (kernels_gate.hip)
+void launch_gate(hipStream_t s, const swgs_plan &p, uint8_t *ws);
+void launch_count_live(hipStream_t s, const int32_t *start, const int32_t *expire, int n_slots,
+                       int num_gs, const int32_t *frames, int n_frames, uint32_t *out_counts);
+
+// Preprocess and binning (kernels_preprocess.hip)
+void launch_preprocess(hipStream_t s, const swgs_plan &p, uint8_t *ws, int view_lo, int view_hi);
+void launch_pair_offsets(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi);
+void launch_emit_pairs(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi);
+void launch_tile_ranges(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t tile_lo, uint32_t tile_hi);
+
+// Radix sort (kernels_sort.hip): stable LSD sort of (key, val) uint32 pairs,
+// n given on the device (*d_n, clamped to cap) over bits [0, bits).
+// On return the sorted data is in (keys, vals); alt buffers are scratch.
+void radix_sort_pairs(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
+                      uint32_t *vals_alt, const uint32_t *d_n, uint32_t n_fixed, uint32_t cap,
+                      int bits, uint32_t *hist, uint32_t *totals);
+void exclusive_scan_u32(hipStream_t s, const uint32_t *in, uint32_t *out, uint32_t n,
+                        uint32_t *total_out, uint32_t *scratch);
+// same over in[idx[i]]
+void exclusive_scan_gather_u32(hipStream_t s, const uint32_t *in, const uint32_t *idx, uint32_t *out,
+                               uint32_t n, uint32_t *total_out, uint32_t *scratch);
+
+// Blend (kernels_blend.hip)
+// counters (nullable): [0] pixel x list entries evaluated by the forward,
+// [1] by the backward
+void launch_blend_forward(hipStream_t s, const swgs_plan &p, uint8_t *ws, float *images,
+                          const float *targets, uint32_t tile_lo, uint32_t tile_hi,
+                          unsigned long long *counters);
+void launch_blend_backward(hipStream_t s, const swgs_plan &p, uint8_t *ws, const float *dLdC,
+                           uint32_t tile_lo, uint32_t tile_hi, unsigned long long *counters);
+void launch_loss_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, const swgs_step_cfg *cfg,
+                        bool with_reg);
+
+// Backward preprocess, step, relocation, mature (kernels_step.hip)
+void launch_preprocess_backward(hipStream_t s, const swgs_plan &p, uint8_t *ws, int add_reg,
+                                float lambda_o, float lambda_s);
+void launch_adam_sgld(hipStream_t s, const swgs_plan &p, uint8_t *ws, const swgs_step_cfg &cfg,
+                      const float *eta);
+void launch_relocate(hipStream_t s, const swgs_plan &p, uint8_t *ws, const swgs_step_cfg &cfg,
+                     int32_t *dst_out, int32_t *src_out, int32_t *count_out);
+void launch_set_step(hipStream_t s, uint8_t *ws_step, int64_t adam_t, uint64_t step, uint64_t seed);
+void launch_advance_step(hipStream_t s, uint8_t *ws_step);
+void launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, size_t n);
+void launch_fill_f32(hipStream_t s, float *p, float v, size_t n);
+void launch_fill_f64(hipStream_t s, double *p, double v, size_t n);
+
+// stats[0..7] -> out, with out[4] = pairs, out[6] = overflow, out[7] = |A| (if nA)
+void launch_stats_out(hipStream_t s, const double *stats, const uint32_t *pair_count, const uint32_t *nA,
+                      double *out);
+
+// Mature (kernels_step.hip)
+void launch_mature(hipStream_t s, const swgs_pool &pool, int F, int st, uint8_t *record,
+                   uint32_t *scratch, uint32_t *d_count);
+
+// Device step parameters (kept in the workspace so a captured graph can
+// advance them on the device).
+struct StepDev {
+    int64_t adam_t;
+    uint64_t step;
+    uint64_t seed;
+    uint64_t pad;
+};
+
+template <typename T>
+inline T *wsp(uint8_t *ws, const swgs_plan &p, int which) {
+    return reinterpret_cast<T *>(ws + p.lay.off[which]);
+}
+
+}  // namespace swgs

@@ -1,0 +1,365 @@
+"""ctypes binding of libswgs.so (include/swgs.h).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+the library.  The raw entry points keep the C names (swgs_plan_create,
+swgs_window_step, ...); the classes below hold the torch tensors that own the
+device memory and call those entry points.  Importing this module raises if
+the library has not been built -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswgs.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "swgs.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+SWGS_OK, SWGS_ERR_INVALID_ARG, SWGS_ERR_UNSUPPORTED, SWGS_ERR_WORKSPACE_TOO_SMALL, SWGS_ERR_CAPACITY, SWGS_ERR_HIP = range(6)
+SWGS_MODE_PLAIN, SWGS_MODE_BATCHED, SWGS_MODE_GRAPH = range(3)
+(SWGS_BUF_ACTIVE_LIST, SWGS_BUF_ACTIVE_COUNT, SWGS_BUF_RECORD_VIEW_BASE, SWGS_BUF_DEPTH_KEY, SWGS_BUF_TILE_COUNT,
+ SWGS_BUF_RECT, SWGS_BUF_SPLAT, SWGS_BUF_PAIR_KEY, SWGS_BUF_PAIR_VAL, SWGS_BUF_PAIR_COUNT, SWGS_BUF_TILE_RANGE,
+ SWGS_BUF_T_FINAL, SWGS_BUF_DLDC, SWGS_BUF_RECORD_GRAD, SWGS_BUF_DEPTH_ORDER) = range(15)
+
+
+class SwgsPool(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t), ("num_gs", ctypes.c_int32), ("n_slots", ctypes.c_int32),
+                ("swin", ctypes.c_int32), ("sh_degree", ctypes.c_int32),
+                ("params", ctypes.c_void_p), ("grads", ctypes.c_void_p), ("adam_m", ctypes.c_void_p),
+                ("adam_v", ctypes.c_void_p), ("birth", ctypes.c_void_p), ("start", ctypes.c_void_p),
+                ("expire", ctypes.c_void_p)]
+
+
+class SwgsView(ctypes.Structure):
+    _fields_ = [("frame", ctypes.c_int32), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("R", ctypes.c_double * 9), ("t", ctypes.c_double * 3),
+                ("fx", ctypes.c_double), ("fy", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+                ("bg", ctypes.c_float * 3), ("reserved2", ctypes.c_float)]
+
+
+class SwgsPlanOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("lds_batch", ctypes.c_int32), ("reserved", ctypes.c_int32), ("pair_capacity", ctypes.c_int64)]
+
+
+class SwgsStepCfg(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t)] + [(n, ctypes.c_float) for n in (
+        "lr_mean", "lr_scale", "lr_quat", "lr_logit", "lr_sh_dc", "lr_sh_rest", "beta1", "beta2", "eps",
+        "noise_lr", "noise_k", "noise_t0", "lambda_opacity", "lambda_scale", "grad_scale_base")] + [
+        (n, ctypes.c_int32) for n in ("window_start", "relocate_period", "reloc_n_max", "mode", "reserved")]
+
+
+P, I32, I64, U64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
+_sigs = {
+    "swgs_version": ([], ctypes.c_int),
+    "swgs_context_create": ([ctypes.c_int, P, P], ctypes.c_int),
+    "swgs_context_set_stream": ([P, P], ctypes.c_int),
+    "swgs_context_destroy": ([P], ctypes.c_int),
+    "swgs_last_error": ([P], ctypes.c_char_p),
+    "swgs_plan_create": ([P, P, P, I32, P, P, P], ctypes.c_int),
+    "swgs_plan_destroy": ([P], ctypes.c_int),
+    "swgs_plan_measure": ([P, P, P, SZ, P, P], ctypes.c_int),
+    "swgs_plan_buffer": ([P, I32, P, P], ctypes.c_int),
+    "swgs_plan_info": ([P, P, P, P, P], ctypes.c_int),
+    "swgs_render_forward": ([P, P, P, SZ, P, P, P], ctypes.c_int),
+    "swgs_render_backward": ([P, P, P, SZ, P, I32, P], ctypes.c_int),
+    "swgs_step_cfg_default": ([P], None),
+    "swgs_step": ([P, P, P, SZ, P, I64, U64, U64, P], ctypes.c_int),
+    "swgs_relocate": ([P, P, P, SZ, P, U64, U64, P, P, P], ctypes.c_int),
+    "swgs_window_step": ([P, P, P, SZ, P, P, P, I64, U64, U64, P], ctypes.c_int),
+    "swgs_mature": ([P, P, I32, P, SZ, P, P], ctypes.c_int),
+    "swgs_record_bytes": ([I64, I32], SZ),
+    "swgs_plan_set_timing": ([P, P, P, SZ, I32], ctypes.c_int),
+    "swgs_plan_timing": ([P, P, P, SZ, P, P, P], ctypes.c_int),
+}
+TIMING_CLASSES = ("gate", "preprocess", "sort", "blend_fwd", "blend_bwd", "preprocess_bwd", "adam_sgld", "relocate")
+for _n, (_a, _r) in _sigs.items():
+    _f = getattr(_lib, _n)
+    _f.argtypes = _a
+    _f.restype = _r
+    globals()[_n] = _f
+
+
+def header_functions(path: str = HEADER):
+    """Names of every function the public header declares."""
+    txt = open(path).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(swgs_[a-z0-9_]+)\s*\(", txt)))
+
+
+class SwgsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"swgs status {status}: {msg}")
+        self.status = status
+
+
+def ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A device binding plus the (non-default, default-priority) stream all
+    library work runs on; calls are ordered after torch's current stream and
+    torch's current stream waits for them."""
+
+    def __init__(self, device: int = 0):
+        self.device = torch.device("cuda", device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        h = ctypes.c_void_p()
+        st = swgs_context_create(device, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != SWGS_OK:
+            raise SwgsError(st, "context create failed")
+        self.h = h
+
+    def check(self, st):
+        if st != SWGS_OK:
+            raise SwgsError(st, swgs_last_error(self.h).decode())
+
+    def __enter__(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        return self
+
+    def __exit__(self, *exc):
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return False
+
+    def close(self):
+        if self.h:
+            self.stream.synchronize()
+            swgs_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pool:
+    """Device tensors of a slot pool (planar rows [F, n_slots])."""
+
+    def __init__(self, params, birth, start, expire, num_gs, swin, sh_degree, device, train=True):
+        dev = torch.device(device)
+        self.params = torch.as_tensor(np.ascontiguousarray(params, np.float32)).to(dev)
+        self.birth = torch.as_tensor(np.ascontiguousarray(birth, np.int32)).to(dev)
+        self.start = torch.as_tensor(np.ascontiguousarray(start, np.int32)).to(dev)
+        self.expire = torch.as_tensor(np.ascontiguousarray(expire, np.int32)).to(dev)
+        self.num_gs, self.swin, self.sh_degree = int(num_gs), int(swin), int(sh_degree)
+        F = self.params.shape[0]
+        n = max(self.num_gs, 1)
+        if train:
+            self.grads = torch.zeros((F, n), dtype=torch.float32, device=dev)
+            self.adam_m = torch.zeros((F, n), dtype=torch.float32, device=dev)
+            self.adam_v = torch.zeros((F, n), dtype=torch.float32, device=dev)
+        else:
+            self.grads = self.adam_m = self.adam_v = None
+
+    @classmethod
+    def from_synth(cls, pool, device="cuda", train=True):
+        return cls(pool.params, pool.birth, pool.start, pool.expire, pool.num_gs, pool.swin, pool.sh_degree,
+                   device, train)
+
+    def c(self) -> SwgsPool:
+        return SwgsPool(ctypes.sizeof(SwgsPool), self.num_gs, self.params.shape[1], self.swin, self.sh_degree,
+                        self.params.data_ptr(), self.grads.data_ptr() if self.grads is not None else None,
+                        self.adam_m.data_ptr() if self.adam_m is not None else None,
+                        self.adam_v.data_ptr() if self.adam_v is not None else None,
+                        self.birth.data_ptr(), self.start.data_ptr(), self.expire.data_ptr())
+
+
+def c_views(views):
+    arr = (SwgsView * len(views))()
+    for i, v in enumerate(views):
+        arr[i].frame = int(v.frame)
+        arr[i].width = int(v.width)
+        arr[i].height = int(v.height)
+        R = np.asarray(v.R, np.float64).reshape(-1)
+        t = np.asarray(v.t, np.float64).reshape(-1)
+        for k in range(9):
+            arr[i].R[k] = float(R[k])
+        for k in range(3):
+            arr[i].t[k] = float(t[k])
+            arr[i].bg[k] = float(v.bg[k])
+        arr[i].fx, arr[i].fy, arr[i].cx, arr[i].cy = float(v.fx), float(v.fy), float(v.cx), float(v.cy)
+    return arr
+
+
+def step_cfg(**kw) -> SwgsStepCfg:
+    c = SwgsStepCfg()
+    swgs_step_cfg_default(ctypes.byref(c))
+    for k, v in kw.items():
+        if not hasattr(c, k):
+            raise KeyError(k)
+        setattr(c, k, v)
+    return c
+
+
+class Plan:
+    """A plan over a pool and a list of views, with its workspace."""
+
+    def __init__(self, ctx: Context, pool: Pool, views, tile=(16, 16), lds_batch=0, pair_capacity=None,
+                 headroom=1.3):
+        self.ctx, self.pool, self.views = ctx, pool, list(views)
+        self.cviews = c_views(self.views)
+        self.tile, self.lds_batch = tile, lds_batch
+        self.h = None
+        self._cpool = pool.c()
+        cap = int(pair_capacity) if pair_capacity else 1 << 16
+        self._create(cap)
+        if pair_capacity is None:
+            k = self.measure()
+            self._create(int(k * headroom) + 65536)
+
+    def _create(self, cap):
+        if self.h:
+            swgs_plan_destroy(self.h)
+            self.h = None
+        opts = SwgsPlanOpts(ctypes.sizeof(SwgsPlanOpts), self.tile[0], self.tile[1], self.lds_batch, 0, cap)
+        h = ctypes.c_void_p()
+        nb = ctypes.c_size_t()
+        with self.ctx:
+            self.ctx.check(swgs_plan_create(self.ctx.h, ctypes.byref(self._cpool), self.cviews, len(self.views),
+                                            ctypes.byref(opts), ctypes.byref(h), ctypes.byref(nb)))
+        self.h = h
+        self.cap = cap
+        self.ws_bytes = nb.value
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.ctx.device)
+        ng, nr, npx, nt = (ctypes.c_int64() for _ in range(4))
+        swgs_plan_info(self.h, ctypes.byref(ng), ctypes.byref(nr), ctypes.byref(npx), ctypes.byref(nt))
+        self.n_groups, self.n_records, self.n_pixels, self.n_tiles = ng.value, nr.value, npx.value, nt.value
+
+    def measure(self):
+        k, r = ctypes.c_int64(), ctypes.c_int64()
+        with self.ctx:
+            self.ctx.check(swgs_plan_measure(self.ctx.h, self.h, ptr(self.ws), self.ws_bytes, ctypes.byref(k),
+                                             ctypes.byref(r)))
+        return k.value
+
+    def buffer(self, which, dtype=torch.uint32):
+        off, nb = ctypes.c_size_t(), ctypes.c_size_t()
+        self.ctx.check(swgs_plan_buffer(self.h, which, ctypes.byref(off), ctypes.byref(nb)))
+        b = self.ws[off.value:off.value + nb.value]
+        return b.view(dtype)
+
+    def image_buffer(self):
+        return torch.empty(3 * self.n_pixels, dtype=torch.float32, device=self.ctx.device)
+
+    def forward(self, images=None, targets=None, stats=None):
+        images = self.image_buffer() if images is None else images
+        with self.ctx:
+            self.ctx.check(swgs_render_forward(self.ctx.h, self.h, ptr(self.ws), self.ws_bytes, ptr(images),
+                                               ptr(targets), ptr(stats)))
+        return images
+
+    def backward(self, dL=None, add_reg=0, cfg=None):
+        with self.ctx:
+            self.ctx.check(swgs_render_backward(self.ctx.h, self.h, ptr(self.ws), self.ws_bytes, ptr(dL),
+                                                int(add_reg), ctypes.byref(cfg) if cfg is not None else None))
+
+    def step(self, cfg, adam_t, step, seed, eta=None):
+        with self.ctx:
+            self.ctx.check(swgs_step(self.ctx.h, self.h, ptr(self.ws), self.ws_bytes, ctypes.byref(cfg),
+                                     int(adam_t), int(step), int(seed), ptr(eta)))
+
+    def relocate(self, cfg, step, seed):
+        n = max(self.pool.num_gs, 1)
+        dst = torch.empty(n, dtype=torch.int32, device=self.ctx.device)
+        src = torch.empty(n, dtype=torch.int32, device=self.ctx.device)
+        cnt = torch.zeros(1, dtype=torch.int32, device=self.ctx.device)
+        with self.ctx:
+            self.ctx.check(swgs_relocate(self.ctx.h, self.h, ptr(self.ws), self.ws_bytes, ctypes.byref(cfg),
+                                         int(step), int(seed), ptr(dst), ptr(src), ptr(cnt)))
+        c = int(cnt.item())
+        return dst[:c], src[:c]
+
+    def window_step(self, cfg, targets, adam_t, step, seed, images=None, stats=None):
+        with self.ctx:
+            self.ctx.check(swgs_window_step(self.ctx.h, self.h, ptr(self.ws), self.ws_bytes, ctypes.byref(cfg),
+                                            ptr(targets), ptr(images), int(adam_t), int(step), int(seed),
+                                            ptr(stats)))
+
+    def set_timing(self, on: bool):
+        with self.ctx:
+            self.ctx.check(swgs_plan_set_timing(self.ctx.h, self.h, ptr(self.ws), self.ws_bytes, int(bool(on))))
+
+    def timing(self):
+        """{class: (total ms, launches)} and evaluated pairs (fwd, bwd) since the last reset."""
+        ms = (ctypes.c_double * 8)()
+        n = (ctypes.c_int64 * 8)()
+        ev = (ctypes.c_uint64 * 2)()
+        with self.ctx:
+            self.ctx.check(swgs_plan_timing(self.ctx.h, self.h, ptr(self.ws), self.ws_bytes, ms, n, ev))
+        return {k: (ms[i], n[i]) for i, k in enumerate(TIMING_CLASSES)}, (ev[0], ev[1])
+
+    def close(self):
+        if self.h:
+            self.ctx.stream.synchronize()
+            swgs_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mature(ctx: Context, pool: Pool, st: int):
+    """Algorithm 1's mature(st) on the device; returns the packed record
+    (uint8 device tensor) and the number of Gaussians it holds."""
+    cap = swgs_record_bytes(pool.num_gs, pool.sh_degree)
+    rec = torch.empty(cap, dtype=torch.uint8, device=ctx.device)
+    cnt, nb = ctypes.c_int64(), ctypes.c_size_t()
+    cp = pool.c()
+    with ctx:
+        ctx.check(swgs_mature(ctx.h, ctypes.byref(cp), int(st), ptr(rec), cap, ctypes.byref(cnt), ctypes.byref(nb)))
+    return rec[:nb.value], cnt.value
+
+
+def parse_record(rec: np.ndarray):
+    """Decode a packed mature record (host bytes) into a dict."""
+    h = np.frombuffer(rec[:32].tobytes(), np.int32)
+    assert h[0] == 0x53475753 and h[1] == 1
+    n, F = int(h[3]), int(h[5])
+    o = 32
+    slots = np.frombuffer(rec[o:o + 4 * n].tobytes(), np.uint32); o += 4 * n
+    lb = np.frombuffer(rec[o:o + 12 * n].tobytes(), np.int32).reshape(3, n); o += 12 * n
+    params = np.frombuffer(rec[o:o + 4 * F * n].tobytes(), np.float32).reshape(F, n)
+    return dict(st=int(h[2]), count=n, sh_degree=int(h[4]), F=F, swin=int(h[6]), slots=slots,
+                birth=lb[0], start=lb[1], expire=lb[2], params=params)
+
+
+class RenderFunction(torch.autograd.Function):
+    """images = render(params) over a plan's views; the backward runs the
+    library's adjoint kernels and returns dL/dparams for the optimisable
+    slots live in the plan's frames (zero elsewhere, frozen slots included)."""
+
+    @staticmethod
+    def forward(fctx, params, plan: Plan):
+        assert params.data_ptr() == plan.pool.params.data_ptr(), "params must be the plan's pool tensor"
+        images = plan.forward()
+        fctx.plan = plan
+        return images
+
+    @staticmethod
+    def backward(fctx, grad_images):
+        plan = fctx.plan
+        pool = plan.pool
+        pool.grads.zero_()
+        plan.backward(grad_images.contiguous())
+        g = torch.zeros_like(pool.params)
+        g[:, :pool.num_gs] = pool.grads[:, :pool.num_gs]
+        return g, None
+
+
+def render(params, plan: Plan):
+    return RenderFunction.apply(params, plan)

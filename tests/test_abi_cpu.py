@@ -1,0 +1,67 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every function
+include/swgs.h declares, and its host-only entry points behave.  No GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2409_07759_amd import swgs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_function():
+    names = swgs.header_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(swgs._lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_function():
+    names = swgs.header_functions()
+    assert sorted(n for n in names) == sorted(swgs._sigs)
+
+
+def test_version():
+    assert swgs.swgs_version() == 1
+
+
+def test_record_bytes():
+    assert swgs.swgs_record_bytes(0, 0) == 32
+    assert swgs.swgs_record_bytes(40000, 0) == 32 + 40000 * (16 + 4 * 14)
+    assert swgs.swgs_record_bytes(10, 3) == 32 + 10 * (16 + 4 * 59)
+    assert swgs.swgs_record_bytes(10, 4) == 0
+
+
+def test_step_cfg_defaults():
+    c = swgs.step_cfg()
+    assert c.struct_size == ctypes.sizeof(swgs.SwgsStepCfg)
+    assert c.noise_lr == 5e4 and c.lambda_opacity == pytest.approx(2e-2) and c.lambda_scale == pytest.approx(1e-2)
+    assert c.beta1 == pytest.approx(0.9) and c.eps == pytest.approx(1e-15) and c.reloc_n_max == 32
+    assert c.noise_k == 100.0 and c.noise_t0 == pytest.approx(0.005)
+
+
+def test_struct_sizes_match_the_header():
+    # swgs_view: 4 int32 + 16 doubles + 4 floats
+    assert ctypes.sizeof(swgs.SwgsView) == 16 + 16 * 8 + 16
+    assert ctypes.sizeof(swgs.SwgsPool) == 8 + 16 + 7 * 8
+    assert ctypes.sizeof(swgs.SwgsPlanOpts) == 8 + 16 + 8
+
+
+def test_buffer_enum_matches_the_header():
+    txt = open(os.path.join(ROOT, "include", "swgs.h")).read()
+    block = txt[txt.index("SWGS_BUF_ACTIVE_LIST = 0"):txt.index("SWGS_BUF_COUNT_")]
+    names = re.findall(r"(SWGS_BUF_[A-Z_]+)", block)
+    for i, n in enumerate(names):
+        assert getattr(swgs, n) == i, n
+
+
+def test_no_cpu_fallback_in_the_product_path():
+    """The package never imports the oracle."""
+    pkg = os.path.join(ROOT, "paper_2409_07759_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src, f
