@@ -31,7 +31,15 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP32_NONPACKED = 78.6     # TFLOP/s: 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, no packed FP32
-FLOPS_PER_EVAL = 15.0          # FP32 flops of one (pixel, splat) evaluation: offsets 4, quadratic 7, exp 1, o*g 1, min 1, test 1
+# Algorithmic FP32 work of the blend kernels, counted from the math (FMA = 2):
+#  every evaluated (pixel, splat) pair: offsets 4, quadratic form 7, exp 1,
+#    o*g 1, min 1, alpha test 1                                        = 15
+#  forward, per blended pair: 1-alpha 1, T(1-alpha) 1, stop test 1,
+#    w = alpha T 1, colour 3 FMA 6                                     = 10
+#  backward, per blended pair: T recovery (rcp, mul) 2, dC/dalpha 3 x 5,
+#    colour grads 4, U update 3 x 3, prod 1, dQ 2, opacity 1, conic and
+#    offset terms 5                                                    = 40
+FLOPS_EVAL, FLOPS_FWD_BLEND, FLOPS_BWD_BLEND = 15.0, 10.0, 40.0
 
 
 def log(*a):
@@ -49,7 +57,7 @@ def parse():
     ap.add_argument("--width", type=int, default=1352)
     ap.add_argument("--height", type=int, default=1014)
     ap.add_argument("--sh-degree", type=int, default=3)
-    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--tile", default="auto", help="auto (autotuner) or WxH")
     ap.add_argument("--lds-batch", type=int, default=0)
     ap.add_argument("--modes", default="graph,batched,plain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -69,8 +77,9 @@ def main():
     from paper_2409_07759_amd import swgs
     from paper_2409_07759_amd import synth as S
 
+    from paper_2409_07759_amd import autotune
+
     dev = torch.device("cuda", 0)
-    tw, th = (int(x) for x in args.tile.split("x"))
     st0 = args.swin
     frames = list(range(st0, st0 + args.swin))
     t0 = time.time()
@@ -82,13 +91,23 @@ def main():
     ctx = swgs.Context(0)
     # targets: teacher renders (forward only)
     tpool = swgs.Pool.from_synth(teacher, train=False)
-    tplan = swgs.Plan(ctx, tpool, views, tile=(tw, th))
+    tplan = swgs.Plan(ctx, tpool, views)
     targets = tplan.forward()
     torch.cuda.synchronize()
     tplan.close()
     del tpool
     log("targets rendered")
 
+    tune_table = None
+    if args.tile == "auto":
+        dp = swgs.Pool.from_synth(student)
+        (tw, th), lds, tune_table = autotune.tune(ctx, dp, views, use_cache=False, log=log)
+        del dp
+        if args.lds_batch == 0:
+            args.lds_batch = lds
+        log(f"autotuned: {tw}x{th}, lds batch {args.lds_batch}")
+    else:
+        tw, th = (int(x) for x in args.tile.split("x"))
     cfg_base = dict(window_start=st0, relocate_period=1)
     results = {}
     pool_for = {}
@@ -154,7 +173,7 @@ def main():
             "workload": f"paper-scale window step: {args.num_gs} optimisable + {args.num_gs} frozen Gaussians, "
                         f"SH degree {args.sh_degree}, W={args.swin} frames x {args.cams} cameras at "
                         f"{args.width}x{args.height}, Adam+SGLD+relocation every step",
-            "views": len(views), "tile": args.tile, "form": chosen,
+            "views": len(views), "tile": f"{tw}x{th}", "lds_batch": args.lds_batch, "form": chosen,
         },
         "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items() if kk != "timing"}
                   for k, v in results.items()},
@@ -162,19 +181,24 @@ def main():
     if "plain" in results:
         out["speedup_vs_plain"] = round(results[chosen]["steps_per_s"] / results["plain"]["steps_per_s"], 3)
         out["psnr_delta_vs_plain_db"] = round(results[chosen]["psnr"] - results["plain"]["psnr"], 4)
+    if tune_table:
+        out["autotune_ms_fwd_bwd"] = {f"{t[0]}x{t[1]}/lds{l}": ms for t, l, ms in tune_table}
     if "batched" in results and results["batched"]["timing"]:
-        tm, (ev_f, ev_b) = results["batched"]["timing"]
+        tm, (ev_f, ev_b, n_bl) = results["batched"]["timing"]
         per_step = {k: round(v[0] / max(1, args.steps), 4) for k, v in tm.items()}
         out["kernel_ms_per_step"] = per_step
         dom = max(tm, key=lambda k: tm[k][0])
         n_launch = max(1, tm[dom][1])
         avg_s = tm[dom][0] / n_launch / 1e3
+        blend_work = {"blend_fwd": (ev_f * FLOPS_EVAL + n_bl * FLOPS_FWD_BLEND) / max(1, tm["blend_fwd"][1]),
+                      "blend_bwd": (ev_b * FLOPS_EVAL + n_bl * FLOPS_BWD_BLEND) / max(1, tm["blend_bwd"][1])}
+        out["blend_pairs_per_step"] = {"fwd_evaluated": ev_f // args.steps, "bwd_evaluated": ev_b // args.steps,
+                                       "blended": n_bl // args.steps}
         if dom in ("blend_fwd", "blend_bwd"):
-            evals = (ev_f if dom == "blend_fwd" else ev_b) / n_launch
-            ach = evals * FLOPS_PER_EVAL / avg_s / 1e12
+            ach = blend_work[dom] / avg_s / 1e12
             out["roofline"] = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": PEAK_FP32_NONPACKED,
                                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_NONPACKED, 4), "traffic": None,
-                               "evaluated_pairs_per_launch": int(evals), "avg_launch_ms": round(avg_s * 1e3, 4)}
+                               "flops_per_launch": int(blend_work[dom]), "avg_launch_ms": round(avg_s * 1e3, 4)}
         else:
             out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                "frac": None, "traffic": None, "avg_launch_ms": round(avg_s * 1e3, 4)}

@@ -242,8 +242,10 @@ swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *plan, void *workspace
  * synchronises, resets the records and switches timing on (on != 0) or off.
  * swgs_plan_timing synchronises, returns per class the summed kernel time
  * (ms[8], host) and the number of bracketed launches (launches[8], host),
- * and, if evals (host uint64[2]) is not NULL, the pairs evaluated by the
- * forward [0] and backward [1] blends; then resets.  Classes: 0 gating,
+ * and, if evals (host uint64[3]) is not NULL, the (pixel, list entry) pairs
+ * evaluated by the forward [0] and the backward [1] blend and the pairs the
+ * forward blended [2] (the backward differentiates exactly those); then
+ * resets.  Classes: 0 gating,
  * 1 preprocess, 2 depth sort + pair emission + tile sort + ranges,
  * 3 forward blend, 4 backward blend, 5 backward preprocess, 6 Adam + SGLD,
  * 7 relocation. */

@@ -130,7 +130,8 @@ void build_layout(swgs_plan &p) {
     sz[WB_RELOC_DST] = (nA + 1) * 4;
     sz[WB_RELOC_SCAN] = (4 + nA / 4096 + 4) * 4;
     sz[WB_REG_PART] = 2 * ((nA + 255) / 256 + 1) * 8;
-    sz[WB_COUNTERS] = 8 * 8;
+    sz[WB_COUNTERS] = 256 * 4 * 8;
+    sz[WB_CFLAGS] = R + 16;   // 256 slots x {fwd evals, bwd evals, blended, pad}
     // order: constant block, then the rest
     const int order_first[] = {WB_VIEWS, WB_GROUPS, WB_GROUP_VIEWS, WB_REC_VIEW_BASE};
     size_t off = 0;
@@ -691,8 +692,8 @@ swgs_status swgs_plan_set_timing(swgs_context *ctx, swgs_plan *p, void *workspac
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     p->timing = on != 0;
     for (int k = 0; k < TK_N; ++k) p->ev_used[k] = 0;
-    launch_fill_u32(ctx->stream, reinterpret_cast<uint32_t *>(wsp<unsigned long long>(static_cast<uint8_t *>(workspace), *p, WB_COUNTERS)), 0, 16);
-    HIP_TRY(ctx, hipGetLastError());
+    launch_fill_u32(ctx->stream, reinterpret_cast<uint32_t *>(wsp<unsigned long long>(static_cast<uint8_t *>(workspace), *p, WB_COUNTERS)), 0, 2 * 1024);
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     return SWGS_OK;
 }
 
@@ -715,10 +716,14 @@ swgs_status swgs_plan_timing(swgs_context *ctx, swgs_plan *p, void *workspace, s
         p->ev_used[k] = 0;
     }
     if (evals) {
-        HIP_TRY(ctx, hipMemcpy(evals, wsp<unsigned long long>(static_cast<uint8_t *>(workspace), *p, WB_COUNTERS),
-                               16, hipMemcpyDeviceToHost));
+        std::vector<uint64_t> c(256 * 4);
+        HIP_TRY(ctx, hipMemcpy(c.data(), wsp<unsigned long long>(static_cast<uint8_t *>(workspace), *p, WB_COUNTERS),
+                               c.size() * 8, hipMemcpyDeviceToHost));
+        evals[0] = evals[1] = evals[2] = 0;
+        for (int i = 0; i < 256; ++i)
+            for (int k = 0; k < 3; ++k) evals[k] += c[4 * i + k];
     }
-    launch_fill_u32(ctx->stream, reinterpret_cast<uint32_t *>(wsp<unsigned long long>(static_cast<uint8_t *>(workspace), *p, WB_COUNTERS)), 0, 16);
+    launch_fill_u32(ctx->stream, reinterpret_cast<uint32_t *>(wsp<unsigned long long>(static_cast<uint8_t *>(workspace), *p, WB_COUNTERS)), 0, 2 * 1024);
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     return SWGS_OK;
 }

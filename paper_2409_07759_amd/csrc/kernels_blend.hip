@@ -14,15 +14,16 @@
 // T <- T / (1 - alpha) (nothing per pair is stored), and keeping the colour
 // behind the splat U and the product of (1 - alpha) behind it, so that
 //     dC/dalpha_k = T_k (c_k - U_k - prod_k bg).
-// Per-splat gradients are summed over the wave with DPP row/bcast adds,
-// accumulated per batch in LDS across the waves of the tile, and flushed
-// with one global float atomic per component per (tile, splat).
+// Per-splat gradient terms are summed over each 16-lane row with DPP adds,
+// the row sums of all waves are combined per batch through LDS, and flushed
+// with one global float atomic per term per (tile, splat).
 #include "swgs_internal.h"
 
 namespace swgs {
 namespace {
 
-constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;      // 1 / log2(e)
+constexpr int kCounterSlots = 256;
 
 // alpha of a staged splat at a pixel; identical instruction sequence in the
 // forward and the backward so both take the same skip/stop decisions.
@@ -43,19 +44,72 @@ __device__ __forceinline__ Px eval_splat(float fx, float fy, const float4 a, con
 }
 #pragma clang fp contract(fast)
 
-// full-wave sum with DPP; the result is valid in lane 63
+// DPP move (row-level lane permutation), as float
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_f(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, false));
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, true));
 }
-__device__ __forceinline__ float wave_sum_to_63(float x) {
-    x += dpp_f<0xB1, 0xf>(x);   // quad_perm [1,0,3,2]
-    x += dpp_f<0x4E, 0xf>(x);   // quad_perm [2,3,0,1]
-    x += dpp_f<0x124, 0xf>(x);  // row_ror:4
-    x += dpp_f<0x128, 0xf>(x);  // row_ror:8   -> every lane holds its row sum
-    x += dpp_f<0x142, 0xa>(x);  // row_bcast:15 into rows 1, 3
-    x += dpp_f<0x143, 0xc>(x);  // row_bcast:31 into rows 2, 3
-    return x;
+
+// Pixel of a thread: each wave covers an 8x8 block of the tile (a 16x16
+// tile is 2x2 blocks, 32x8 is 4x1), lanes row-major inside the block.
+template <int TW, int TH>
+__device__ __forceinline__ void lane_pixel(int tid, int &px, int &py) {
+    if (TW == 8 && TH == 8) {
+        px = tid & 7;
+        py = tid >> 3;
+    } else {
+        const int w = tid >> 6, l = tid & 63;
+        px = (w % (TW / 8)) * 8 + (l & 7);
+        py = (w / (TW / 8)) * 8 + (l >> 3);
+    }
+}
+
+// Support box of a staged splat in pixel units: centre and half-extents of
+// {alpha >= 1/255} padded by one pixel (the same exact-support argument as
+// the tile ranges), from the FP32 record.
+__device__ __forceinline__ float4 cull_box(const float4 a, const float4 b) {
+    const float A = -2.0f * kLn2 * b.x, B = -kLn2 * b.y, C = -2.0f * kLn2 * b.z;
+    const float det = A * C - B * B;
+    const float kappa = fmaxf(0.0f, 2.0f * kLn2 * __log2f(255.0f * b.w));
+    // a nearly singular FP32 conic (very elongated splat) is never culled
+    if (!(det > 1e-3f * A * C)) return make_float4(0.0f, 0.0f, 3.0e38f, 3.0e38f);
+    const float rx = sqrtf(kappa * C / det) + 1.0f;
+    const float ry = sqrtf(kappa * A / det) + 1.0f;
+    return make_float4(a.x + 0.5f - a.z, a.y + 0.5f - a.w, rx, ry);
+}
+
+// true if the box can reach a pixel centre of the wave's 8x8 block
+__device__ __forceinline__ bool box_hits(const float4 bx, float wx0, float wy0) {
+    return (bx.x + bx.z >= wx0) & (bx.x - bx.z <= wx0 + 7.0f) & (bx.y + bx.w >= wy0) & (bx.y - bx.w <= wy0 + 7.0f);
+}
+
+// Bit w set if the box reaches wave w's 8x8 block of the tile at (tx0, ty0).
+template <int TW, int TH>
+__device__ __forceinline__ uint32_t box_wave_mask(const float4 bx, int tx0, int ty0) {
+    uint32_t m = 0;
+    constexpr int NWX = TW / 8, NW = (TW * TH) / 64;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const float wx0 = (float)(tx0 + (w % NWX) * 8) + 0.5f, wy0 = (float)(ty0 + (w / NWX) * 8) + 0.5f;
+        m |= box_hits(bx, wx0, wy0) ? (1u << w) : 0u;
+    }
+    return m;
+}
+
+// Each wave compacts, in ascending order, the batch entries whose mask has
+// its bit set; returns the count (wave-uniform).
+template <int CAP>
+__device__ __forceinline__ int wave_list(const uint32_t *smask, int m, int wave, int lane, uint8_t *list) {
+    int cnt = 0;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int c = 0; c < m; c += 64) {
+        const int k = c + lane;
+        const bool hit = k < m && ((smask[k] >> wave) & 1u);
+        const uint64_t b = __ballot(hit);
+        if (hit) list[cnt + __popcll(b & lt)] = (uint8_t)k;
+        cnt += __popcll(b);
+    }
+    return cnt;
 }
 
 // view owning a global tile id: last view whose tile_base <= tile
@@ -77,18 +131,26 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             const float *__restrict__ targets, float *__restrict__ dLdC, double *__restrict__ loss_part,
             unsigned long long *__restrict__ counters) {
     constexpr int NT = TW * TH;
+    constexpr bool CULL = NT > 64;        // per-wave support-box lists
+    constexpr int NW = NT / 64;
     __shared__ float4 sa[BATCH], sb[BATCH], sc[BATCH];
+    __shared__ uint32_t smask[CULL ? BATCH : 1];
+    __shared__ uint8_t slist[CULL ? NW : 1][CULL ? BATCH : 1];
     __shared__ float red[2][NT / 64];
-    __shared__ unsigned long long cnt_evals;
+    __shared__ unsigned long long cnt_evals, cnt_blend;
     const uint32_t tile = tile_lo + blockIdx.x;
     const ViewDev &V = views[view_of_tile(views, n_views, tile)];
     const uint32_t lt = tile - V.tile_base;
     const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
-    const int x = tx * TW + (threadIdx.x % TW), y = ty * TH + (threadIdx.x / TW);
+    int lx, ly;
+    lane_pixel<TW, TH>(threadIdx.x, lx, ly);
+    const int x = tx * TW + lx, y = ty * TH + ly;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const bool inside = x < V.width && y < V.height;
     const float fx = (float)x, fy = (float)y;
     const uint2 rg = ranges[tile];
     const uint32_t n = rg.y - rg.x;
+    uint32_t nblend = 0;
 
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
     uint32_t last = 0;
@@ -99,28 +161,37 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         for (int k = threadIdx.x; k < BATCH; k += NT) {
             if (b0 + k < n) {
                 const uint32_t r = pair_val[rg.x + b0 + k];
-                sa[k] = splat[3 * (size_t)r];
-                sb[k] = splat[3 * (size_t)r + 1];
+                const float4 a = splat[3 * (size_t)r], b = splat[3 * (size_t)r + 1];
+                sa[k] = a;
+                sb[k] = b;
                 sc[k] = splat[3 * (size_t)r + 2];
+                if (CULL) smask[k] = box_wave_mask<TW, TH>(cull_box(a, b), tx * TW, ty * TH);
             }
         }
         __syncthreads();
         const int m = (int)min((uint32_t)BATCH, n - b0);
-        if (!done) {
-            for (int k = 0; k < m; ++k) {
-                const Px e = eval_splat(fx, fy, sa[k], sb[k]);
-                const float alpha = fminf(0.99f, e.og);
-                if (alpha < (1.0f / 255.0f)) continue;
-                const float Tn = T * (1.0f - alpha);
-                if (Tn < 1e-4f) { done = true; stop_at = b0 + (uint32_t)k + 1; break; }
-                const float w = alpha * T;
-                const float4 c = sc[k];
-                c0 = fmaf(c.x, w, c0);
-                c1 = fmaf(c.y, w, c1);
-                c2 = fmaf(c.z, w, c2);
-                T = Tn;
-                last = b0 + (uint32_t)k + 1;
-            }
+        const int cnt = CULL ? wave_list<BATCH>(smask, m, wave, lane, slist[CULL ? wave : 0]) : m;
+        // branch-free per lane: a splat is blended when alpha >= 1/255 and
+        // the pixel has not stopped; the stop test fires on the splat that
+        // would take T below 1e-4 (that splat is not blended)
+        for (int i = 0; i < cnt; ++i) {
+            const int k = CULL ? (int)slist[CULL ? wave : 0][i] : i;
+            const Px e = eval_splat(fx, fy, sa[k], sb[k]);
+            const float alpha = fminf(0.99f, e.og);
+            const float Tn = T * (1.0f - alpha);
+            const bool pass = !done && alpha >= (1.0f / 255.0f);
+            const bool stop = pass && Tn < 1e-4f;
+            const bool use = pass && !stop;
+            const float w = use ? alpha * T : 0.0f;
+            const float4 c = sc[k];
+            c0 = fmaf(c.x, w, c0);
+            c1 = fmaf(c.y, w, c1);
+            c2 = fmaf(c.z, w, c2);
+            T = use ? Tn : T;
+            last = use ? b0 + (uint32_t)k + 1 : last;
+            nblend += use ? 1u : 0u;
+            stop_at = stop ? b0 + (uint32_t)k + 1 : stop_at;
+            done = done || stop;
         }
     }
     float l1 = 0.0f, sq = 0.0f;
@@ -147,11 +218,17 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         }
     }
     if (counters) {
-        if (threadIdx.x == 0) cnt_evals = 0;
+        if (threadIdx.x == 0) { cnt_evals = 0; cnt_blend = 0; }
         __syncthreads();
         atomicAdd(&cnt_evals, (unsigned long long)stop_at);
+        atomicAdd(&cnt_blend, (unsigned long long)nblend);
         __syncthreads();
-        if (threadIdx.x == 0) atomicAdd(counters, cnt_evals);
+        if (threadIdx.x == 0) {
+            // spread over kCounterSlots slots: one address per block would serialise
+            unsigned long long *c = counters + 4 * (blockIdx.x % kCounterSlots);
+            atomicAdd(c, cnt_evals);
+            atomicAdd(c + 2, cnt_blend);
+        }
     }
     if (targets) {
         for (int o = 32; o > 0; o >>= 1) {
@@ -172,6 +249,21 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     }
 }
 
+// sum over the 16 lanes of each DPP row; every lane of a row holds its row sum
+__device__ __forceinline__ float row_sum16(float x) {
+    x += dpp_f<0xB1, 0xf>(x);   // quad_perm [1,0,3,2]
+    x += dpp_f<0x4E, 0xf>(x);   // quad_perm [2,3,0,1]
+    x += dpp_f<0x124, 0xf>(x);  // row_ror:4
+    x += dpp_f<0x128, 0xf>(x);  // row_ror:8
+    return x;
+}
+
+// Backward batches are BB splats; per splat each wave reduces its 9
+// gradient terms to one value per 16-lane row (4 DPP adds each) and the four
+// row leaders store them to LDS, so a splat costs 36 DPP adds and 3 LDS
+// stores per wave instead of a full 64-lane reduction per term.
+constexpr int kTerm = 12;                 // 9 terms padded to 3 x float4
+
 template <int TW, int TH, int BATCH>
 __global__ void __launch_bounds__(TW *TH)
 k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_val,
@@ -180,15 +272,24 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             const uint32_t *__restrict__ last_in, const float *__restrict__ dLdC,
             float *__restrict__ rec_grad, size_t R, unsigned long long *__restrict__ counters) {
     constexpr int NT = TW * TH;
-    __shared__ float4 sa[BATCH], sb[BATCH], sc[BATCH];
-    __shared__ uint32_t srec[BATCH];
-    __shared__ float acc[9][BATCH];
+    constexpr int NW = NT / 64;           // waves
+    constexpr int NP = 4 * NW;            // row partials per splat
+    constexpr int BB = NW == 1 ? 64 : 32; // splats per LDS batch (partials: BB x NP x 48 B)
+    constexpr bool CULL = NW > 1;
+    __shared__ float4 sa[BB], sb[BB], sc[BB];
+    __shared__ uint32_t smask[BB];
+    __shared__ uint8_t slist[CULL ? NW : 1][CULL ? BB : 1];
+    __shared__ uint32_t srec[BB];
+    __shared__ float4 part[BB][NP][kTerm / 4];
     __shared__ uint32_t smax;
+    __shared__ unsigned long long cnt_evals;
     const uint32_t tile = tile_lo + blockIdx.x;
     const ViewDev &V = views[view_of_tile(views, n_views, tile)];
     const uint32_t lt = tile - V.tile_base;
     const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
-    const int x = tx * TW + (threadIdx.x % TW), y = ty * TH + (threadIdx.x / TW);
+    int lx, ly;
+    lane_pixel<TW, TH>(threadIdx.x, lx, ly);
+    const int x = tx * TW + lx, y = ty * TH + ly;
     const bool inside = x < V.width && y < V.height;
     const float fx = (float)x, fy = (float)y;
     const uint2 rg = ranges[tile];
@@ -205,117 +306,110 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         g1 = dLdC[o3 + HW];
         g2 = dLdC[o3 + 2 * HW];
     }
-    if (threadIdx.x == 0) smax = 0;
-    for (int k = threadIdx.x; k < BATCH; k += NT)
-        for (int c = 0; c < 9; ++c) acc[c][k] = 0.0f;
+    if (threadIdx.x == 0) { smax = 0; cnt_evals = 0; }
     __syncthreads();
     atomicMax(&smax, lst);
+    if (counters) atomicAdd(&cnt_evals, (unsigned long long)lst);
     __syncthreads();
     const uint32_t nmax = smax;
-    if (counters) {
-        // pixel x list entries this tile's backward evaluates (timing runs only)
-        __shared__ unsigned long long cnt_evals;
-        if (threadIdx.x == 0) cnt_evals = 0;
-        __syncthreads();
-        atomicAdd(&cnt_evals, (unsigned long long)lst);
-        __syncthreads();
-        if (threadIdx.x == 0) atomicAdd(counters + 1, cnt_evals);
-    }
+    if (counters && threadIdx.x == 0) atomicAdd(counters + 4 * (blockIdx.x % kCounterSlots) + 1, cnt_evals);
     const float bg0 = V.bg[0], bg1 = V.bg[1], bg2 = V.bg[2];
     float U0 = 0.0f, U1 = 0.0f, U2 = 0.0f, Rr = 1.0f;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool row_leader = (lane & 15) == 15;
+    const int prow = wave * 4 + (lane >> 4);
 
     for (uint32_t b_end = nmax; b_end > 0;) {
-        const uint32_t b_start = b_end > (uint32_t)BATCH ? b_end - BATCH : 0;
+        const uint32_t b_start = b_end > (uint32_t)BB ? b_end - BB : 0;
         const int m = (int)(b_end - b_start);
         for (int k = threadIdx.x; k < m; k += NT) {
             const uint32_t r = pair_val[rg.x + b_start + k];
             srec[k] = r;
-            sa[k] = splat[3 * (size_t)r];
-            sb[k] = splat[3 * (size_t)r + 1];
+            const float4 a = splat[3 * (size_t)r], b = splat[3 * (size_t)r + 1];
+            sa[k] = a;
+            sb[k] = b;
             sc[k] = splat[3 * (size_t)r + 2];
+            smask[k] = CULL ? box_wave_mask<TW, TH>(cull_box(a, b), tx * TW, ty * TH) : 1u;
         }
         __syncthreads();
-        for (int k = m - 1; k >= 0; --k) {
+        const int cnt = CULL ? wave_list<BB>(smask, m, wave, lane, slist[CULL ? wave : 0]) : m;
+        for (int i = cnt - 1; i >= 0; --i) {
+            const int k = CULL ? (int)slist[CULL ? wave : 0][i] : i;
             const uint32_t idx = b_start + (uint32_t)k;
-            float v0 = 0, v1 = 0, v2 = 0, v3 = 0, v4 = 0, v5 = 0, v6 = 0, v7 = 0, v8 = 0;
-            bool contrib = false;
-            if (idx < lst) {
-                const Px e = eval_splat(fx, fy, sa[k], sb[k]);
-                const float alpha = fminf(0.99f, e.og);
-                if (alpha >= (1.0f / 255.0f)) {
-                    contrib = true;
-                    const float om = 1.0f - alpha;
-                    T = T / om;                        // transmittance in front of k
-                    const float4 c = sc[k];
-                    const float da = T * (g0 * (c.x - U0 - Rr * bg0) + g1 * (c.y - U1 - Rr * bg1) +
-                                          g2 * (c.z - U2 - Rr * bg2));
-                    const float w = alpha * T;
-                    v0 = g0 * w;
-                    v1 = g1 * w;
-                    v2 = g2 * w;
-                    U0 = fmaf(c.x, alpha, om * U0);
-                    U1 = fmaf(c.y, alpha, om * U1);
-                    U2 = fmaf(c.z, alpha, om * U2);
-                    Rr *= om;
-                    if (e.og < 0.99f) {
-                        // alpha = o g, g = exp(-Q/2): dQ = -alpha/2 dalpha
-                        const float dQ = -0.5f * e.og * da;
-                        v3 = e.g * da;
-                        v4 = dQ * e.dx * e.dx;
-                        v5 = dQ * e.dx * e.dy;
-                        v6 = dQ * e.dy * e.dy;
-                        v7 = dQ * e.dx;
-                        v8 = dQ * e.dy;
-                    }
-                }
-            }
+            // branch-free per lane: contrib = the forward blended this splat here
+            const Px e = eval_splat(fx, fy, sa[k], sb[k]);
+            const float alpha = fminf(0.99f, e.og);
+            const bool contrib = idx < lst && alpha >= (1.0f / 255.0f);
+            const float om = 1.0f - alpha;
+            const float Tk = T * __builtin_amdgcn_rcpf(om);     // transmittance in front of k
+            const float4 c = sc[k];
+            const float da = Tk * (g0 * (c.x - U0 - Rr * bg0) + g1 * (c.y - U1 - Rr * bg1) +
+                                   g2 * (c.z - U2 - Rr * bg2));
+            const float w = contrib ? alpha * Tk : 0.0f;
+            float v0 = g0 * w, v1 = g1 * w, v2 = g2 * w;
+            // alpha = o g, g = exp(-Q/2): dQ = -alpha/2 dalpha (zero when clamped)
+            const float dQ = (contrib && e.og < 0.99f) ? -0.5f * e.og * da : 0.0f;
+            float v3 = (contrib && e.og < 0.99f) ? e.g * da : 0.0f;
+            float v7 = dQ * e.dx, v8 = dQ * e.dy;
+            float v4 = v7 * e.dx, v5 = v7 * e.dy, v6 = v8 * e.dy;
+            T = contrib ? Tk : T;
+            U0 = contrib ? fmaf(c.x, alpha, om * U0) : U0;
+            U1 = contrib ? fmaf(c.y, alpha, om * U1) : U1;
+            U2 = contrib ? fmaf(c.z, alpha, om * U2) : U2;
+            Rr = contrib ? Rr * om : Rr;
             if (__ballot(contrib) != 0) {
-                v0 = wave_sum_to_63(v0);
-                v1 = wave_sum_to_63(v1);
-                v2 = wave_sum_to_63(v2);
-                v3 = wave_sum_to_63(v3);
-                v4 = wave_sum_to_63(v4);
-                v5 = wave_sum_to_63(v5);
-                v6 = wave_sum_to_63(v6);
-                v7 = wave_sum_to_63(v7);
-                v8 = wave_sum_to_63(v8);
-                if (lane == 63) {
-                    if (NT == 64) {
-                        acc[0][k] += v0; acc[1][k] += v1; acc[2][k] += v2;
-                        acc[3][k] += v3; acc[4][k] += v4; acc[5][k] += v5;
-                        acc[6][k] += v6; acc[7][k] += v7; acc[8][k] += v8;
-                    } else {
-                        atomicAdd(&acc[0][k], v0); atomicAdd(&acc[1][k], v1); atomicAdd(&acc[2][k], v2);
-                        atomicAdd(&acc[3][k], v3); atomicAdd(&acc[4][k], v4); atomicAdd(&acc[5][k], v5);
-                        atomicAdd(&acc[6][k], v6); atomicAdd(&acc[7][k], v7); atomicAdd(&acc[8][k], v8);
-                    }
+                v0 = row_sum16(v0); v1 = row_sum16(v1); v2 = row_sum16(v2);
+                v3 = row_sum16(v3); v4 = row_sum16(v4); v5 = row_sum16(v5);
+                v6 = row_sum16(v6); v7 = row_sum16(v7); v8 = row_sum16(v8);
+                if (row_leader) {
+                    part[k][prow][0] = make_float4(v0, v1, v2, v3);
+                    part[k][prow][1] = make_float4(v4, v5, v6, v7);
+                    part[k][prow][2] = make_float4(v8, 0.0f, 0.0f, 0.0f);
                 }
+            } else if (row_leader) {
+                part[k][prow][0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                part[k][prow][1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                part[k][prow][2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
         }
         __syncthreads();
-        // flush: record gradients d/d(u, v, A, B, C, o, r, g, b) with the
-        // conic unscaled (A = -2 A'/log2 e, B = -B'/log2 e, C = -2 C'/log2 e)
+        // flush: the row partials of each splat (only from the waves whose
+        // block it reaches) are summed per term group (3 float4 groups, one
+        // thread per (splat, group)), then one thread per splat issues the
+        // record gradients d/d(u, v, A, B, C, o, r, g, b) with the conic
+        // unscaled (A = -2 A' ln2, B = -B' ln2, C = -2 C' ln2)
+        for (int t = threadIdx.x; t < 3 * m; t += NT) {
+            const int k = t % m, j = t / m;
+            const uint32_t wm = smask[k];
+            float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            for (int q = 0; q < NP; ++q) {
+                if (!((wm >> (q >> 2)) & 1u)) continue;
+                const float4 a = part[k][q][j];
+                acc.x += a.x; acc.y += a.y; acc.z += a.z; acc.w += a.w;
+            }
+            part[k][0][j] = acc;
+        }
+        __syncthreads();
         for (int k = threadIdx.x; k < m; k += NT) {
-            const float s4 = acc[4][k], s5 = acc[5][k], s6 = acc[6][k], s7 = acc[7][k], s8 = acc[8][k];
-            const float s3 = acc[3][k], s0 = acc[0][k], s1 = acc[1][k], s2 = acc[2][k];
-            for (int c = 0; c < 9; ++c) acc[c][k] = 0.0f;
-            if (s0 == 0.0f && s1 == 0.0f && s2 == 0.0f && s3 == 0.0f && s4 == 0.0f && s5 == 0.0f &&
-                s6 == 0.0f && s7 == 0.0f && s8 == 0.0f)
+            const float4 s0 = part[k][0][0], s1 = part[k][0][1];
+            const float s8 = part[k][0][2].x;
+            if (s0.x == 0.0f && s0.y == 0.0f && s0.z == 0.0f && s0.w == 0.0f && s1.x == 0.0f &&
+                s1.y == 0.0f && s1.z == 0.0f && s1.w == 0.0f && s8 == 0.0f)
                 continue;
             const float4 b = sb[k];
-            const float A = -2.0f * b.x / kLog2e, B = -b.y / kLog2e, C = -2.0f * b.z / kLog2e;
+            const float A = -2.0f * kLn2 * b.x, B = -kLn2 * b.y, C = -2.0f * kLn2 * b.z;
             const uint32_t r = srec[k];
+            const float s7 = s1.w;
             // dQ/ddx = 2(A dx + B dy), ddx/du = -1
             atomicAdd(rec_grad + 0 * R + r, -2.0f * (A * s7 + B * s8));
             atomicAdd(rec_grad + 1 * R + r, -2.0f * (B * s7 + C * s8));
-            atomicAdd(rec_grad + 2 * R + r, s4);
-            atomicAdd(rec_grad + 3 * R + r, 2.0f * s5);
-            atomicAdd(rec_grad + 4 * R + r, s6);
-            atomicAdd(rec_grad + 5 * R + r, s3);
-            atomicAdd(rec_grad + 6 * R + r, s0);
-            atomicAdd(rec_grad + 7 * R + r, s1);
-            atomicAdd(rec_grad + 8 * R + r, s2);
+            atomicAdd(rec_grad + 2 * R + r, s1.x);
+            atomicAdd(rec_grad + 3 * R + r, 2.0f * s1.y);
+            atomicAdd(rec_grad + 4 * R + r, s1.z);
+            atomicAdd(rec_grad + 5 * R + r, s0.w);
+            atomicAdd(rec_grad + 6 * R + r, s0.x);
+            atomicAdd(rec_grad + 7 * R + r, s0.y);
+            atomicAdd(rec_grad + 8 * R + r, s0.z);
         }
         __syncthreads();
         b_end = b_start;

@@ -55,7 +55,7 @@ k_preprocess(const float *__restrict__ params, int n_slots, int deg, const Group
              const int32_t *__restrict__ group_views, const ViewDev *__restrict__ views,
              const uint32_t *__restrict__ lists, int g_lo, int only_view, int tile_w, int tile_h,
              float4 *__restrict__ splat, uint32_t *__restrict__ depth_key, uint32_t *__restrict__ tile_count,
-             uint2 *__restrict__ rect, uint32_t *__restrict__ rec_idx) {
+             uint2 *__restrict__ rect, uint32_t *__restrict__ rec_idx, uint8_t *__restrict__ cflags) {
     const GroupDev G = groups[g_lo + blockIdx.y];
     const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= G.n_live) return;
@@ -102,11 +102,14 @@ k_preprocess(const float *__restrict__ params, int n_slots, int deg, const Group
         vis = vis && pz > 0.2;
         double u = 0, v = 0, A = 0, B = 0, C = 0;
         int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
+        uint32_t flags = 0;   // bits 0-2: rgb channel clamped at 0; bit 3/4: FoV clamp in x/y
         if (vis) {
             const double iz = 1.0 / pz;
             u = V.fx * px * iz + V.cx;
             v = V.fy * py * iz + V.cy;
             double tx = px * iz, ty = py * iz;
+            flags |= (tx < -V.limx || tx > V.limx) ? 8u : 0u;
+            flags |= (ty < -V.limy || ty > V.limy) ? 16u : 0u;
             tx = tx < -V.limx ? -V.limx : (tx > V.limx ? V.limx : tx);
             ty = ty < -V.limy ? -V.limy : (ty > V.limy ? V.limy : ty);
             // T = J R_view, J = [[fx/z, 0, -fx tx/z], [0, fy/z, -fy ty/z]]
@@ -164,7 +167,9 @@ k_preprocess(const float *__restrict__ params, int n_slots, int deg, const Group
             for (int kk = 0; kk < nk; ++kk) acc += Y[kk] * (double)params[(11 + 3 * kk + ch) * S + slot];
             acc += 0.5;
             col[ch] = acc > 0.0 ? acc : 0.0;
+            flags |= acc > 0.0 ? 0u : (1u << ch);
         }
+        cflags[r] = (uint8_t)flags;
         const float zf = (float)pz;
         const double ui = floor(u), vi_ = floor(v);
         splat[3 * (size_t)r + 0] = make_float4((float)ui, (float)vi_, (float)(0.5 - (u - ui)), (float)(0.5 - (v - vi_)));
@@ -276,7 +281,7 @@ void launch_preprocess(hipStream_t s, const swgs_plan &p, uint8_t *ws, int view_
                        wsp<ViewDev>(ws, p, WB_VIEWS), wsp<uint32_t>(ws, p, WB_ACTIVE_LIST), g_lo, only,
                        p.tile_w, p.tile_h, wsp<float4>(ws, p, WB_SPLAT), wsp<uint32_t>(ws, p, WB_DEPTH_KEY),
                        wsp<uint32_t>(ws, p, WB_TILE_COUNT), wsp<uint2>(ws, p, WB_RECT),
-                       wsp<uint32_t>(ws, p, WB_REC_IDX));
+                       wsp<uint32_t>(ws, p, WB_REC_IDX), wsp<uint8_t>(ws, p, WB_CFLAGS));
 }
 
 void launch_pair_offsets(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi) {

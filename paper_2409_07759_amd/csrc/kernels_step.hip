@@ -38,73 +38,162 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint2 k) {
     return c;
 }
 
-__device__ __forceinline__ void sh_basis_grad(int deg, double x, double y, double z, double *Y, double *gx,
-                                              double *gy, double *gz) {
-    for (int k = 0; k < 16; ++k) { gx[k] = 0; gy[k] = 0; gz[k] = 0; }
-    Y[0] = 0.28209479177387814;
+// Real SH basis (degree <= 3, 3DGS sign/order) in FP32 at a unit direction.
+__device__ __forceinline__ void sh_basis32(int deg, float x, float y, float z, float *Y) {
+    Y[0] = 0.28209479177387814f;
     if (deg < 1) return;
-    const double c1 = 0.4886025119029199;
-    Y[1] = -c1 * y; gy[1] = -c1;
-    Y[2] = c1 * z;  gz[2] = c1;
-    Y[3] = -c1 * x; gx[3] = -c1;
+    const float c1 = 0.4886025119029199f;
+    Y[1] = -c1 * y;
+    Y[2] = c1 * z;
+    Y[3] = -c1 * x;
     if (deg < 2) return;
-    const double a = 1.0925484305920792, b = 0.31539156525252005, c = 0.5462742152960396;
-    const double xx = x * x, yy = y * y, zz = z * z;
-    Y[4] = a * x * y;                   gx[4] = a * y; gy[4] = a * x;
-    Y[5] = -a * y * z;                  gy[5] = -a * z; gz[5] = -a * y;
-    Y[6] = b * (2.0 * zz - xx - yy);    gx[6] = -2.0 * b * x; gy[6] = -2.0 * b * y; gz[6] = 4.0 * b * z;
-    Y[7] = -a * x * z;                  gx[7] = -a * z; gz[7] = -a * x;
-    Y[8] = c * (xx - yy);               gx[8] = 2.0 * c * x; gy[8] = -2.0 * c * y;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = 1.0925484305920792f * x * y;
+    Y[5] = -1.0925484305920792f * y * z;
+    Y[6] = 0.31539156525252005f * (2.0f * zz - xx - yy);
+    Y[7] = -1.0925484305920792f * x * z;
+    Y[8] = 0.5462742152960396f * (xx - yy);
     if (deg < 3) return;
-    const double e = 0.5900435899266435, f = 2.890611442640554, h = 0.4570457994644658;
-    const double m = 0.3731763325901154, n = 1.445305721320277;
-    Y[9] = -e * y * (3.0 * xx - yy);    gx[9] = -6.0 * e * x * y; gy[9] = -3.0 * e * (xx - yy);
-    Y[10] = f * x * y * z;              gx[10] = f * y * z; gy[10] = f * x * z; gz[10] = f * x * y;
-    Y[11] = -h * y * (4.0 * zz - xx - yy);
-    gx[11] = 2.0 * h * x * y; gy[11] = -h * (4.0 * zz - xx - 3.0 * yy); gz[11] = -8.0 * h * y * z;
-    Y[12] = m * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
-    gx[12] = -6.0 * m * x * z; gy[12] = -6.0 * m * y * z; gz[12] = m * (6.0 * zz - 3.0 * xx - 3.0 * yy);
-    Y[13] = -h * x * (4.0 * zz - xx - yy);
-    gx[13] = -h * (4.0 * zz - 3.0 * xx - yy); gy[13] = 2.0 * h * x * y; gz[13] = -8.0 * h * x * z;
-    Y[14] = n * z * (xx - yy);          gx[14] = 2.0 * n * x * z; gy[14] = -2.0 * n * y * z; gz[14] = n * (xx - yy);
-    Y[15] = -e * x * (xx - 3.0 * yy);   gx[15] = -3.0 * e * (xx - yy); gy[15] = 6.0 * e * x * y;
+    Y[9] = -0.5900435899266435f * y * (3.0f * xx - yy);
+    Y[10] = 2.890611442640554f * x * y * z;
+    Y[11] = -0.4570457994644658f * y * (4.0f * zz - xx - yy);
+    Y[12] = 0.3731763325901154f * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+    Y[13] = -0.4570457994644658f * x * (4.0f * zz - xx - yy);
+    Y[14] = 1.445305721320277f * z * (xx - yy);
+    Y[15] = -0.5900435899266435f * x * (xx - 3.0f * yy);
 }
 
+// Gradient w.r.t. (x, y, z) (components independent) of sum_k w[k] Y_k.
+__device__ __forceinline__ void sh_weighted_grad(int deg, float x, float y, float z, const float *w, float &gx,
+                                                 float &gy, float &gz) {
+    gx = gy = gz = 0.0f;
+    if (deg < 1) return;
+    const float c1 = 0.4886025119029199f;
+    gy -= c1 * w[1];
+    gz += c1 * w[2];
+    gx -= c1 * w[3];
+    if (deg < 2) return;
+    const float a = 1.0925484305920792f, b = 0.31539156525252005f, c = 0.5462742152960396f;
+    gx += a * y * w[4];                gy += a * x * w[4];
+    gy -= a * z * w[5];                gz -= a * y * w[5];
+    gx -= 2.0f * b * x * w[6];         gy -= 2.0f * b * y * w[6];        gz += 4.0f * b * z * w[6];
+    gx -= a * z * w[7];                gz -= a * x * w[7];
+    gx += 2.0f * c * x * w[8];         gy -= 2.0f * c * y * w[8];
+    if (deg < 3) return;
+    const float e = 0.5900435899266435f, f = 2.890611442640554f, h = 0.4570457994644658f;
+    const float m = 0.3731763325901154f, n = 1.445305721320277f;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    gx -= 6.0f * e * x * y * w[9];     gy -= 3.0f * e * (xx - yy) * w[9];
+    gx += f * y * z * w[10];           gy += f * x * z * w[10];          gz += f * x * y * w[10];
+    gx += 2.0f * h * x * y * w[11];    gy -= h * (4.0f * zz - xx - 3.0f * yy) * w[11];  gz -= 8.0f * h * y * z * w[11];
+    gx -= 6.0f * m * x * z * w[12];    gy -= 6.0f * m * y * z * w[12];   gz += m * (6.0f * zz - 3.0f * xx - 3.0f * yy) * w[12];
+    gx -= h * (4.0f * zz - 3.0f * xx - yy) * w[13];  gy += 2.0f * h * x * y * w[13];  gz -= 8.0f * h * x * z * w[13];
+    gx += 2.0f * n * x * z * w[14];    gy -= 2.0f * n * y * z * w[14];   gz += n * (xx - yy) * w[14];
+    gx -= 3.0f * e * (xx - yy) * w[15]; gy += 6.0f * e * x * y * w[15];
+}
+
+// Colour part of the backward preprocess (FP32): SH coefficient gradients
+// and the view-direction contribution to the mean gradient, summed over the
+// views where the slot is live; runs after k_prebwd_geom and adds to its
+// mean gradient.
+template <int DEG>
 __global__ void __launch_bounds__(kBlock)
-k_preprocess_bwd(const float *__restrict__ params, int n_slots, int num_gs, int deg,
-                 const uint32_t *__restrict__ listA, uint32_t nA, const GroupDev *__restrict__ groups,
-                 int n_groups, const int32_t *__restrict__ group_views, const ViewDev *__restrict__ views,
-                 const int32_t *__restrict__ pos_of, const uint32_t *__restrict__ depth_key,
-                 const float *__restrict__ rec_grad, size_t R, float *__restrict__ grads, int add_reg,
-                 double reg_o, double reg_s, double *__restrict__ reg_part) {
+k_prebwd_color(const float *__restrict__ params, int n_slots, int num_gs, const uint32_t *__restrict__ listA,
+               uint32_t nA, const GroupDev *__restrict__ groups, int n_groups,
+               const int32_t *__restrict__ group_views, const ViewDev *__restrict__ views,
+               const int32_t *__restrict__ pos_of, const uint32_t *__restrict__ tile_count,
+               const uint8_t *__restrict__ cflags, const float *__restrict__ rec_grad, size_t R,
+               float *__restrict__ grads) {
+    constexpr int nk = (DEG + 1) * (DEG + 1);
+    const uint32_t a = blockIdx.x * kBlock + threadIdx.x;
+    if (a >= nA) return;
+    const size_t S = (size_t)n_slots, NG = (size_t)num_gs;
+    const uint32_t slot = listA[a];
+    const float mx = params[slot], my = params[S + slot], mz = params[2 * S + slot];
+    float dsh[3 * nk];
+#pragma unroll
+    for (int i = 0; i < 3 * nk; ++i) dsh[i] = 0.0f;
+    float dm0 = 0.0f, dm1 = 0.0f, dm2 = 0.0f;
+    for (int g = 0; g < n_groups; ++g) {
+        const int32_t j = pos_of[(size_t)g * NG + slot];
+        if (j < 0) continue;
+        const GroupDev G = groups[g];
+        for (int kv = 0; kv < G.n_views; ++kv) {
+            const ViewDev &V = views[group_views[G.view_first + kv]];
+            const uint32_t r = V.rec_base + (uint32_t)j;
+            if (tile_count[r] == 0) continue;                 // culled in this view
+            const uint32_t fl = cflags[r];
+            // rgb_c = max(0, sum_k Y_k f_kc + 1/2); clamped channels pass nothing
+            const float gc0 = (fl & 1u) ? 0.0f : rec_grad[6 * R + r];
+            const float gc1 = (fl & 2u) ? 0.0f : rec_grad[7 * R + r];
+            const float gc2 = (fl & 4u) ? 0.0f : rec_grad[8 * R + r];
+            const float dxv = mx - (float)V.campos[0], dyv = my - (float)V.campos[1], dzv = mz - (float)V.campos[2];
+            const float il = rsqrtf(dxv * dxv + dyv * dyv + dzv * dzv);
+            const float hx = dxv * il, hy = dyv * il, hz = dzv * il;
+            float Y[16], wk[16];
+            sh_basis32(DEG, hx, hy, hz, Y);
+#pragma unroll
+            for (int k = 0; k < nk; ++k) {
+                dsh[3 * k] += Y[k] * gc0;
+                dsh[3 * k + 1] += Y[k] * gc1;
+                dsh[3 * k + 2] += Y[k] * gc2;
+                wk[k] = params[(11 + 3 * k) * S + slot] * gc0 + params[(12 + 3 * k) * S + slot] * gc1 +
+                        params[(13 + 3 * k) * S + slot] * gc2;
+            }
+            float gx, gy, gz;
+            sh_weighted_grad(DEG, hx, hy, hz, wk, gx, gy, gz);
+            // d = dir / |dir|: d dir = (I - d d^T) g / |dir|
+            const float dot = gx * hx + gy * hy + gz * hz;
+            dm0 += (gx - hx * dot) * il;
+            dm1 += (gy - hy * dot) * il;
+            dm2 += (gz - hz * dot) * il;
+        }
+    }
+    grads[slot] += dm0;
+    grads[NG + slot] += dm1;
+    grads[2 * NG + slot] += dm2;
+#pragma unroll
+    for (int i = 0; i < 3 * nk; ++i) grads[(11 + i) * NG + slot] = dsh[i];
+}
+
+// Geometry part of the backward preprocess (FP64): projected mean, conic
+// and opacity gradients of every live view chained to mean, log-scale,
+// quaternion and opacity logit; plus the regulariser and its sums.
+__global__ void __launch_bounds__(kBlock)
+k_prebwd_geom(const float *__restrict__ params, int n_slots, int num_gs, const uint32_t *__restrict__ listA,
+              uint32_t nA, const GroupDev *__restrict__ groups, int n_groups,
+              const int32_t *__restrict__ group_views, const ViewDev *__restrict__ views,
+              const int32_t *__restrict__ pos_of, const uint32_t *__restrict__ tile_count,
+              const uint8_t *__restrict__ cflags, const float *__restrict__ rec_grad, size_t R,
+              float *__restrict__ grads, int add_reg, double reg_o, double reg_s, double *__restrict__ reg_part) {
     const uint32_t a = blockIdx.x * kBlock + threadIdx.x;
     double rsig = 0.0, rscale = 0.0;
     if (a < nA) {
         const size_t S = (size_t)n_slots, NG = (size_t)num_gs;
         const uint32_t slot = listA[a];
         const double mx = params[slot], my = params[S + slot], mz = params[2 * S + slot];
-        const double q0r = params[6 * S + slot], q1r = params[7 * S + slot], q2r = params[8 * S + slot],
-                     q3r = params[9 * S + slot];
-        const double qn = sqrt(q0r * q0r + q1r * q1r + q2r * q2r + q3r * q3r);
-        const double w = q0r / qn, x = q1r / qn, y = q2r / qn, z = q3r / qn;
-        const double sc[3] = {exp((double)params[3 * S + slot]), exp((double)params[4 * S + slot]),
-                              exp((double)params[5 * S + slot])};
-        const double Rq[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
-                              2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
-                              2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)};
-        double M[9];
-        for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) M[3 * r + c] = Rq[3 * r + c] * sc[c];
-        double Sg[9];
-        for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) Sg[3 * r + c] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
-        const double lg = params[10 * S + slot];
-        const double op = 1.0 / (1.0 + exp(-lg));
-        const int nk = (deg + 1) * (deg + 1);
-
-        float dsh[48];
-        for (int i = 0; i < 3 * nk; ++i) dsh[i] = 0.0f;
-        double dmu[3] = {0, 0, 0}, H[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, dlogit = 0.0;
+        // Sigma = M M^T, M = R(q) diag(e^s)
+        double M[9], Sg[6];   // Sg: 00 01 02 11 12 22
+        {
+            const double q0 = params[6 * S + slot], q1 = params[7 * S + slot], q2 = params[8 * S + slot],
+                         q3 = params[9 * S + slot];
+            const double qi = 1.0 / sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+            const double w = q0 * qi, x = q1 * qi, y = q2 * qi, z = q3 * qi;
+            const double s0 = exp((double)params[3 * S + slot]), s1 = exp((double)params[4 * S + slot]),
+                         s2 = exp((double)params[5 * S + slot]);
+            M[0] = (1.0 - 2.0 * (y * y + z * z)) * s0; M[1] = 2.0 * (x * y - w * z) * s1; M[2] = 2.0 * (x * z + w * y) * s2;
+            M[3] = 2.0 * (x * y + w * z) * s0; M[4] = (1.0 - 2.0 * (x * x + z * z)) * s1; M[5] = 2.0 * (y * z - w * x) * s2;
+            M[6] = 2.0 * (x * z - w * y) * s0; M[7] = 2.0 * (y * z + w * x) * s1; M[8] = (1.0 - 2.0 * (x * x + y * y)) * s2;
+            Sg[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+            Sg[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+            Sg[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+            Sg[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+            Sg[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+            Sg[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+        }
+        const double op = 1.0 / (1.0 + exp(-(double)params[10 * S + slot]));
+        double dmu0 = 0, dmu1 = 0, dmu2 = 0, dlogit = 0.0;
+        double H[6] = {0, 0, 0, 0, 0, 0};   // symmetric dL/dSigma
 
         for (int g = 0; g < n_groups; ++g) {
             const int32_t j = pos_of[(size_t)g * NG + slot];
@@ -113,16 +202,15 @@ k_preprocess_bwd(const float *__restrict__ params, int n_slots, int num_gs, int 
             for (int kv = 0; kv < G.n_views; ++kv) {
                 const ViewDev &V = views[group_views[G.view_first + kv]];
                 const uint32_t r = V.rec_base + (uint32_t)j;
-                if (depth_key[r] == 0xFFFFFFFFu) continue;      // culled in this view
-                double d[9];
-                for (int c = 0; c < 9; ++c) d[c] = rec_grad[c * R + r];
-                // forward intermediates
+                if (tile_count[r] == 0) continue;                 // culled in this view
+                const uint32_t fl = cflags[r];
+                dlogit += (double)rec_grad[5 * R + r] * op * (1.0 - op);
                 const double px = V.R[0] * mx + V.R[1] * my + V.R[2] * mz + V.t[0];
                 const double py = V.R[3] * mx + V.R[4] * my + V.R[5] * mz + V.t[1];
                 const double pz = V.R[6] * mx + V.R[7] * my + V.R[8] * mz + V.t[2];
                 const double iz = 1.0 / pz;
+                const bool clx = (fl & 8u) != 0, cly = (fl & 16u) != 0;
                 const double txr = px * iz, tyr = py * iz;
-                const bool clx = txr < -V.limx || txr > V.limx, cly = tyr < -V.limy || tyr > V.limy;
                 const double tx = clx ? (txr < 0 ? -V.limx : V.limx) : txr;
                 const double ty = cly ? (tyr < 0 ? -V.limy : V.limy) : tyr;
                 const double J00 = V.fx * iz, J02 = -V.fx * tx * iz, J11 = V.fy * iz, J12 = -V.fy * ty * iz;
@@ -131,54 +219,29 @@ k_preprocess_bwd(const float *__restrict__ params, int n_slots, int num_gs, int 
                     T0[c] = J00 * V.R[c] + J02 * V.R[6 + c];
                     T1[c] = J11 * V.R[3 + c] + J12 * V.R[6 + c];
                 }
-                double A0[3], B0[3];
-                for (int r2 = 0; r2 < 3; ++r2) {
-                    A0[r2] = Sg[3 * r2] * T0[0] + Sg[3 * r2 + 1] * T0[1] + Sg[3 * r2 + 2] * T0[2];
-                    B0[r2] = Sg[3 * r2] * T1[0] + Sg[3 * r2 + 1] * T1[1] + Sg[3 * r2 + 2] * T1[2];
-                }
+                const double A0[3] = {Sg[0] * T0[0] + Sg[1] * T0[1] + Sg[2] * T0[2],
+                                      Sg[1] * T0[0] + Sg[3] * T0[1] + Sg[4] * T0[2],
+                                      Sg[2] * T0[0] + Sg[4] * T0[1] + Sg[5] * T0[2]};
+                const double B0[3] = {Sg[0] * T1[0] + Sg[1] * T1[1] + Sg[2] * T1[2],
+                                      Sg[1] * T1[0] + Sg[3] * T1[1] + Sg[4] * T1[2],
+                                      Sg[2] * T1[0] + Sg[4] * T1[1] + Sg[5] * T1[2]};
                 const double ca = T0[0] * A0[0] + T0[1] * A0[1] + T0[2] * A0[2] + 0.3;
                 const double cb = T0[0] * B0[0] + T0[1] * B0[1] + T0[2] * B0[2];
                 const double cc = T1[0] * B0[0] + T1[1] * B0[1] + T1[2] * B0[2] + 0.3;
                 const double det = ca * cc - cb * cb;
-
-                // colour
-                double dxv = mx - V.campos[0], dyv = my - V.campos[1], dzv = mz - V.campos[2];
-                const double dl = sqrt(dxv * dxv + dyv * dyv + dzv * dzv);
-                const double hx = dxv / dl, hy = dyv / dl, hz = dzv / dl;
-                double Y[16], gx[16], gy[16], gz[16];
-                sh_basis_grad(deg, hx, hy, hz, Y, gx, gy, gz);
-                double ddx = 0, ddy = 0, ddz = 0;
-                for (int ch = 0; ch < 3; ++ch) {
-                    double s = 0.5;
-                    for (int k = 0; k < nk; ++k) s += Y[k] * (double)params[(11 + 3 * k + ch) * S + slot];
-                    if (s <= 0.0) continue;
-                    const double gc = d[6 + ch];
-                    for (int k = 0; k < nk; ++k) {
-                        dsh[3 * k + ch] += (float)(Y[k] * gc);
-                        const double f = (double)params[(11 + 3 * k + ch) * S + slot] * gc;
-                        ddx += f * gx[k];
-                        ddy += f * gy[k];
-                        ddz += f * gz[k];
-                    }
-                }
-                const double dot = ddx * hx + ddy * hy + ddz * hz;
-                dmu[0] += (ddx - hx * dot) / dl;
-                dmu[1] += (ddy - hy * dot) / dl;
-                dmu[2] += (ddz - hz * dot) / dl;
-
-                dlogit += d[5] * op * (1.0 - op);
-
                 // conic (A, B, C) = (c, -b, a) / det
                 const double i2 = 1.0 / (det * det);
-                const double gA = d[2], gB = d[3], gC = d[4];
+                const double gA = rec_grad[2 * R + r], gB = rec_grad[3 * R + r], gC = rec_grad[4 * R + r];
                 const double dca = (-cc * cc * gA + cb * cc * gB - cb * cb * gC) * i2;
                 const double dcb = (2.0 * cb * cc * gA - (ca * cc + cb * cb) * gB + 2.0 * ca * cb * gC) * i2;
                 const double dcc = (-cb * cb * gA + ca * cb * gB - ca * ca * gC) * i2;
-                // symmetric part of dL/dSigma, summed over views
-                for (int r2 = 0; r2 < 3; ++r2)
-                    for (int c = 0; c < 3; ++c)
-                        H[3 * r2 + c] += 2.0 * dca * T0[r2] * T0[c] + dcb * (T0[r2] * T1[c] + T1[r2] * T0[c]) +
-                                         2.0 * dcc * T1[r2] * T1[c];
+                // dL/dSigma summed over views: 2 dca T0 T0^T + dcb (T0 T1^T + T1 T0^T) + 2 dcc T1 T1^T
+                H[0] += 2.0 * (dca * T0[0] * T0[0] + dcb * T0[0] * T1[0] + dcc * T1[0] * T1[0]);
+                H[1] += 2.0 * dca * T0[0] * T0[1] + dcb * (T0[0] * T1[1] + T1[0] * T0[1]) + 2.0 * dcc * T1[0] * T1[1];
+                H[2] += 2.0 * dca * T0[0] * T0[2] + dcb * (T0[0] * T1[2] + T1[0] * T0[2]) + 2.0 * dcc * T1[0] * T1[2];
+                H[3] += 2.0 * (dca * T0[1] * T0[1] + dcb * T0[1] * T1[1] + dcc * T1[1] * T1[1]);
+                H[4] += 2.0 * dca * T0[1] * T0[2] + dcb * (T0[1] * T1[2] + T1[1] * T0[2]) + 2.0 * dcc * T1[1] * T1[2];
+                H[5] += 2.0 * (dca * T0[2] * T0[2] + dcb * T0[2] * T1[2] + dcc * T1[2] * T1[2]);
                 double dT0[3], dT1[3];
                 for (int c = 0; c < 3; ++c) {
                     dT0[c] = 2.0 * dca * A0[c] + dcb * B0[c];
@@ -190,29 +253,36 @@ k_preprocess_bwd(const float *__restrict__ params, int n_slots, int num_gs, int 
                 const double dJ11 = dT1[0] * V.R[3] + dT1[1] * V.R[4] + dT1[2] * V.R[5];
                 const double dJ12 = dT1[0] * V.R[6] + dT1[1] * V.R[7] + dT1[2] * V.R[8];
                 double dpx = 0, dpy = 0, dpz = 0;
-                dpz += -dJ00 * V.fx * iz * iz + dJ02 * V.fx * tx * iz * iz - dJ11 * V.fy * iz * iz +
-                       dJ12 * V.fy * ty * iz * iz;
+                dpz += (-dJ00 * V.fx + dJ02 * V.fx * tx - dJ11 * V.fy + dJ12 * V.fy * ty) * iz * iz;
                 const double dtx = -dJ02 * V.fx * iz, dty = -dJ12 * V.fy * iz;
                 if (!clx) { dpx += dtx * iz; dpz -= dtx * px * iz * iz; }
                 if (!cly) { dpy += dty * iz; dpz -= dty * py * iz * iz; }
                 // projected mean
-                dpx += d[0] * V.fx * iz;
-                dpz -= d[0] * V.fx * px * iz * iz;
-                dpy += d[1] * V.fy * iz;
-                dpz -= d[1] * V.fy * py * iz * iz;
-                dmu[0] += V.R[0] * dpx + V.R[3] * dpy + V.R[6] * dpz;
-                dmu[1] += V.R[1] * dpx + V.R[4] * dpy + V.R[7] * dpz;
-                dmu[2] += V.R[2] * dpx + V.R[5] * dpy + V.R[8] * dpz;
+                const double gu = rec_grad[r], gv = rec_grad[R + r];
+                dpx += gu * V.fx * iz;
+                dpz -= gu * V.fx * px * iz * iz;
+                dpy += gv * V.fy * iz;
+                dpz -= gv * V.fy * py * iz * iz;
+                dmu0 += V.R[0] * dpx + V.R[3] * dpy + V.R[6] * dpz;
+                dmu1 += V.R[1] * dpx + V.R[4] * dpy + V.R[7] * dpz;
+                dmu2 += V.R[2] * dpx + V.R[5] * dpy + V.R[8] * dpz;
             }
         }
-        // Sigma = M M^T: dM = H M; M = Rq diag(sc)
+        // Sigma = M M^T: dM = Hs M with Hs the symmetric matrix of H; M = R(q) diag(sc)
+        const double q0 = params[6 * S + slot], q1 = params[7 * S + slot], q2 = params[8 * S + slot],
+                     q3 = params[9 * S + slot];
+        const double qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+        const double w = q0 / qn, x = q1 / qn, y = q2 / qn, z = q3 / qn;
+        const double sc[3] = {exp((double)params[3 * S + slot]), exp((double)params[4 * S + slot]),
+                              exp((double)params[5 * S + slot])};
+        const double Hs[9] = {H[0], H[1], H[2], H[1], H[3], H[4], H[2], H[4], H[5]};
         double dRq[9], ds[3];
         for (int c = 0; c < 3; ++c) {
             double acc = 0.0;
             for (int r2 = 0; r2 < 3; ++r2) {
-                const double dm = H[3 * r2] * M[c] + H[3 * r2 + 1] * M[3 + c] + H[3 * r2 + 2] * M[6 + c];
+                const double dm = Hs[3 * r2] * M[c] + Hs[3 * r2 + 1] * M[3 + c] + Hs[3 * r2 + 2] * M[6 + c];
                 dRq[3 * r2 + c] = dm * sc[c];
-                acc += dm * Rq[3 * r2 + c];
+                acc += dm * M[3 * r2 + c] / sc[c];     // Rq = M / sc
             }
             ds[c] = acc * sc[c];
         }
@@ -232,11 +302,12 @@ k_preprocess_bwd(const float *__restrict__ params, int n_slots, int num_gs, int 
         }
         rsig = op;
         rscale = sc[0] + sc[1] + sc[2];
-        for (int c = 0; c < 3; ++c) grads[c * NG + slot] = (float)dmu[c];
+        grads[slot] = (float)dmu0;
+        grads[NG + slot] = (float)dmu1;
+        grads[2 * NG + slot] = (float)dmu2;
         for (int c = 0; c < 3; ++c) grads[(3 + c) * NG + slot] = (float)ds[c];
         for (int k = 0; k < 4; ++k) grads[(6 + k) * NG + slot] = (float)((dq[k] - qh[k] * qd) / qn);
         grads[10 * NG + slot] = (float)dlogit;
-        for (int i = 0; i < 3 * nk; ++i) grads[(11 + i) * NG + slot] = dsh[i];
     }
     // regulariser sums (for the reported loss)
     __shared__ double red[2][kBlock / 64];
@@ -571,13 +642,21 @@ void launch_preprocess_backward(hipStream_t s, const swgs_plan &p, uint8_t *ws, 
     const int nb = (int)((nA + kBlock - 1) / kBlock);
     if (nb == 0) return;
     const double inv = nA ? 1.0 / (double)nA : 0.0;
-    hipLaunchKernelGGL(k_preprocess_bwd, dim3(nb), dim3(kBlock), 0, s, p.pool.params, p.pool.n_slots,
-                       p.pool.num_gs, p.sh_degree, wsp<uint32_t>(ws, p, WB_ACTIVE_LIST) + p.list_A_base, nA,
-                       wsp<GroupDev>(ws, p, WB_GROUPS), (int)p.groups.size(), wsp<int32_t>(ws, p, WB_GROUP_VIEWS),
-                       wsp<ViewDev>(ws, p, WB_VIEWS), wsp<int32_t>(ws, p, WB_POS_OF),
-                       wsp<uint32_t>(ws, p, WB_DEPTH_KEY), wsp<float>(ws, p, WB_REC_GRAD), (size_t)p.R,
-                       p.pool.grads, add_reg, (double)lambda_o * inv, (double)lambda_s * inv,
+#define SWGS_PREBWD_COMMON                                                                                \
+    dim3(nb), dim3(kBlock), 0, s, p.pool.params, p.pool.n_slots, p.pool.num_gs,                           \
+        wsp<uint32_t>(ws, p, WB_ACTIVE_LIST) + p.list_A_base, nA, wsp<GroupDev>(ws, p, WB_GROUPS),        \
+        (int)p.groups.size(), wsp<int32_t>(ws, p, WB_GROUP_VIEWS), wsp<ViewDev>(ws, p, WB_VIEWS),         \
+        wsp<int32_t>(ws, p, WB_POS_OF), wsp<uint32_t>(ws, p, WB_TILE_COUNT), wsp<uint8_t>(ws, p, WB_CFLAGS), \
+        wsp<float>(ws, p, WB_REC_GRAD), (size_t)p.R, p.pool.grads
+    hipLaunchKernelGGL(k_prebwd_geom, SWGS_PREBWD_COMMON, add_reg, (double)lambda_o * inv, (double)lambda_s * inv,
                        wsp<double>(ws, p, WB_REG_PART));
+    switch (p.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_prebwd_color<0>, SWGS_PREBWD_COMMON); break;
+    case 1: hipLaunchKernelGGL(k_prebwd_color<1>, SWGS_PREBWD_COMMON); break;
+    case 2: hipLaunchKernelGGL(k_prebwd_color<2>, SWGS_PREBWD_COMMON); break;
+    default: hipLaunchKernelGGL(k_prebwd_color<3>, SWGS_PREBWD_COMMON); break;
+    }
+#undef SWGS_PREBWD_COMMON
     hipLaunchKernelGGL(k_reg_reduce, dim3(1), dim3(256), 0, s, wsp<double>(ws, p, WB_REG_PART), nb,
                        (double)lambda_o, (double)lambda_s, inv, wsp<uint32_t>(ws, p, WB_PAIR_COUNT),
                        wsp<double>(ws, p, WB_STATS));

@@ -67,7 +67,7 @@ enum WsBuf {
     WB_GATE_BLK, WB_POS_OF, WB_REC_IDX, WB_KEY_ALT, WB_IDX_ALT, WB_PAIR_KEY_ALT, WB_PAIR_VAL_ALT,
     WB_PAIR_OFFSET, WB_SORT_HIST, WB_SORT_TOTAL, WB_LAST, WB_LOSS_PART, WB_STATS, WB_STEP,
     WB_VIEWS, WB_GROUPS, WB_GROUP_VIEWS,
-    WB_RELOC_W, WB_RELOC_FLAG, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_CNT, WB_RELOC_SCAN, WB_REG_PART, WB_COUNTERS,
+    WB_RELOC_W, WB_RELOC_FLAG, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_CNT, WB_RELOC_SCAN, WB_REG_PART, WB_COUNTERS, WB_CFLAGS,
     WB_COUNT
 };
 

@@ -292,13 +292,13 @@ class Plan:
             self.ctx.check(swgs_plan_set_timing(self.ctx.h, self.h, ptr(self.ws), self.ws_bytes, int(bool(on))))
 
     def timing(self):
-        """{class: (total ms, launches)} and evaluated pairs (fwd, bwd) since the last reset."""
+        """{class: (total ms, launches)} and (fwd evaluated, bwd evaluated, blended) pairs since the last reset."""
         ms = (ctypes.c_double * 8)()
         n = (ctypes.c_int64 * 8)()
-        ev = (ctypes.c_uint64 * 2)()
+        ev = (ctypes.c_uint64 * 3)()
         with self.ctx:
             self.ctx.check(swgs_plan_timing(self.ctx.h, self.h, ptr(self.ws), self.ws_bytes, ms, n, ev))
-        return {k: (ms[i], n[i]) for i, k in enumerate(TIMING_CLASSES)}, (ev[0], ev[1])
+        return {k: (ms[i], n[i]) for i, k in enumerate(TIMING_CLASSES)}, (ev[0], ev[1], ev[2])
 
     def close(self):
         if self.h:

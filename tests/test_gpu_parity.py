@@ -550,3 +550,32 @@ def test_invalid_arguments_are_rejected(sw, ctx):
     with pytest.raises(sw.SwgsError) as e:
         sw.Plan(ctx, dp, views, tile=(4, 4))
     assert e.value.status == sw.SWGS_ERR_UNSUPPORTED
+
+
+def test_extreme_shapes_tile_invariant_and_match_oracle(sw, ctx):
+    """Needle-like, huge and sub-pixel splats: the per-wave support-box cull
+    and the tile ranges must never drop a contribution."""
+    say("extreme shapes")
+    rng = np.random.default_rng(21)
+    pool, views = tiny(n=400, width=90, height=70)
+    p = pool.params
+    k = np.arange(400)
+    p[3, k % 4 == 0] = -0.5                          # needles: one long axis
+    p[4:6, k % 4 == 0] = -6.5
+    p[3:6, k % 4 == 1] = rng.uniform(-1.0, -0.3, size=(3, (k % 4 == 1).sum()))   # huge
+    p[3:6, k % 4 == 2] = -7.5                        # far below a pixel
+    p[10, k % 4 == 1] = -3.0                         # faint huge ones
+    ref = None
+    for tile in [(16, 16), (8, 8), (32, 8)]:
+        img, T, _ = render_gpu(sw, ctx, pool, views, tile)
+        if ref is None:
+            ref = img
+        else:
+            assert np.array_equal(img.view(np.uint32), ref.view(np.uint32)), tile
+    o = 0
+    for v in views:
+        n = v.width * v.height
+        rgb, To, cnt, dm, cm = O.render_view(p, 0, pool.start, pool.expire, v)
+        keep = dm >= MARGIN_PIX
+        assert np.abs(ref[o:o + 3 * n].reshape(3, n) - rgb)[:, keep].max() <= IMG_TOL
+        o += 3 * n
