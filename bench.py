@@ -62,6 +62,13 @@ def parse():
     ap.add_argument("--modes", default="graph,batched,plain")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=1536)
+    ap.add_argument("--serve-rates", default="200,500,1000", help="Poisson request rates (req/s); empty: no serving")
+    ap.add_argument("--serve-seconds", type=float, default=5.0, help="measured seconds per rate (after 1 s warm-up)")
+    ap.add_argument("--serve-active", type=int, default=300_000)
+    ap.add_argument("--serve-frames", type=int, default=300)
+    ap.add_argument("--serve-lanes", type=int, default=3)
+    ap.add_argument("--serve-max-batch", type=int, default=16)
+    ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     return ap.parse_args()
 
 
@@ -202,9 +209,111 @@ def main():
         else:
             out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                "frac": None, "traffic": None, "avg_launch_ms": round(avg_s * 1e3, 4)}
+    if args.serve_rates.strip():
+        del student, teacher, targets
+        torch.cuda.empty_cache()
+        out["serving"] = run_serving(args, ctx, (tw, th), args.lds_batch)
+        out["metric"] = ("window train steps/s (batched hipGraph step vs plain per-frame launches, same PSNR); "
+                         "served frames/s at p99 ms (continuous batching vs plain FIFO, identical images)")
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(student, views, args)
+        out["cpu_baseline"] = cpu_baseline(S.steady_window_pool(args.num_gs, args.swin, args.sh_degree, st0, seed=0),
+                                           views, args)
     print(json.dumps(out), flush=True)
+
+
+RESOLUTIONS = [(640, 480), (1280, 720), (1920, 1080)]
+
+
+def serving_trace(rate, seconds, n_frames, seed):
+    """Poisson arrivals at `rate` req/s over 1 s of warm-up plus `seconds`;
+    each request: frame U{0..n_frames-1}, camera uniform on a sphere of
+    radius U[3, 5] looking at the origin, resolution uniform over
+    RESOLUTIONS."""
+    import numpy as np
+
+    from paper_2409_07759_amd import synth as S
+    rng = np.random.default_rng(seed)
+    arr = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > 1.0 + seconds:
+            break
+        arr.append(t)
+    views = []
+    for _ in arr:
+        W, H = RESOLUTIONS[int(rng.integers(0, len(RESOLUTIONS)))]
+        views.append(S.random_pose_view(rng, int(rng.integers(0, n_frames)), W, H))
+    return np.array(arr), views
+
+
+def latency_summary(arr, ready, status, t_lo):
+    import numpy as np
+    m = (arr >= t_lo) & (status == 0)
+    lat = (ready[m] - arr[m]) * 1e3
+    if lat.size == 0:
+        return dict(p50_ms=None, p99_ms=None, frames_per_s=0.0, completed=0)
+    span = ready[m].max() - arr[m].min()
+    return dict(p50_ms=round(float(np.percentile(lat, 50)), 3), p99_ms=round(float(np.percentile(lat, 99)), 3),
+                mean_ms=round(float(lat.mean()), 3), frames_per_s=round(float(m.sum() / span), 2),
+                completed=int(m.sum()), failed=int(((arr >= t_lo) & (status != 0)).sum()))
+
+
+def run_serving(args, ctx, tile, lds):
+    """Serving of a 300-frame clip from a resident pool (300k live per frame,
+    1-2% replaced per frame): continuous batching (lanes x batches of mixed
+    resolutions, admission by memory budget) against the plain form (FIFO,
+    one request per launch sequence, one in flight)."""
+    import numpy as np
+    import torch
+
+    from paper_2409_07759_amd import swgs
+    from paper_2409_07759_amd import synth as S
+    t0 = time.time()
+    pool = S.serving_pool(args.serve_active, args.serve_frames, args.sh_degree, seed=3)
+    dp = swgs.Pool.from_synth(pool, train=False)
+    n_slots = pool.params.shape[1]
+    del pool
+    log(f"serving pool: {n_slots} resident slots, {args.serve_frames} frames, built in {time.time() - t0:.1f}s")
+    budget = int(args.serve_budget_gb * (1 << 30))
+    forms = {"served": dict(lanes=args.serve_lanes, max_batch=args.serve_max_batch),
+             "plain": dict(lanes=1, max_batch=1)}
+    servers = {k: swgs.Server(ctx, dp, args.serve_frames, budget + (512 << 20), tile=tile, lds_batch=lds, **v)
+               for k, v in forms.items()}
+    # same images from both forms (sampled requests)
+    _, views = serving_trace(100.0, 0.1, args.serve_frames, seed=99)
+    views = views[:8]
+    imgs = {k: [torch.empty((3, v.height, v.width), device="cuda") for v in views] for k in forms}
+    for k, srv in servers.items():
+        srv.run(views, images=imgs[k])
+    diff = max(float((a - b).abs().max()) for a, b in zip(imgs["served"], imgs["plain"]))
+    del imgs
+    res = {"workload": f"{args.serve_frames}-frame clip, {args.serve_active} live Gaussians per frame, 1-2% "
+                       f"replaced per frame ({n_slots} resident slots), SH degree {args.sh_degree}; Poisson "
+                       f"arrivals, frame U{{0..{args.serve_frames - 1}}}, pose on a sphere of radius U[3,5], "
+                       f"resolution uniform over 640x480/1280x720/1920x1080; forward only, FP32",
+           "served_form": f"continuous batching: {args.serve_lanes} lanes, <= {args.serve_max_batch} requests per "
+                          f"batch, memory budget {args.serve_budget_gb} GB",
+           "plain_form": "FIFO, one request per launch sequence, one in flight",
+           "measured_seconds_per_rate": args.serve_seconds, "warmup_seconds": 1.0,
+           "served_vs_plain_max_abs_diff": diff, "rates": {}}
+    for rate in [float(r) for r in args.serve_rates.split(",") if r.strip()]:
+        arr, views = serving_trace(rate, args.serve_seconds, args.serve_frames, seed=int(rate))
+        row = {}
+        for k, srv in servers.items():
+            (a, ready, status, batch), st = srv.run(views, arrivals=arr, realtime=True)
+            summ = latency_summary(a, ready, status, 1.0)
+            summ.update(batches=st["batches"], mean_batch=round(st["mean_batch"], 2), redone=st["redone"],
+                        peak_gb=round(st["peak_bytes"] / 1e9, 3))
+            row[k] = summ
+            log(f"serve {rate:.0f} req/s {k}: p50 {summ['p50_ms']} ms, p99 {summ['p99_ms']} ms, "
+                f"{summ['frames_per_s']} frames/s, mean batch {summ['mean_batch']}, redone {st['redone']}")
+        if row["served"]["p99_ms"] and row["plain"]["p99_ms"]:
+            row["p99_speedup_vs_plain"] = round(row["plain"]["p99_ms"] / row["served"]["p99_ms"], 3)
+        res["rates"][str(int(rate))] = row
+    for srv in servers.values():
+        srv.close()
+    return res
 
 
 def cpu_baseline(student, views, args):

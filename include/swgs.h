@@ -270,6 +270,111 @@ swgs_status swgs_mature(swgs_context *ctx, const swgs_pool *pool, int32_t st,
 /* Bytes of a mature record for `count` Gaussians of SH degree d. */
 size_t swgs_record_bytes(int64_t count, int32_t sh_degree);
 
+/* ------------------------------------------------------------- update
+ * Algorithm 2's client-side update (Sec. 4.3): write the entries of a mature
+ * record (device memory, record_bytes bytes, the layout swgs_mature writes)
+ * into `pool`.  slot_base < 0: entry k goes to slot record.slot[k], the slot
+ * it was emitted from (Algorithm 2 replaces slice birth mod swin of the
+ * client buffer, which is that slot range); slot_base >= 0: entry k goes to
+ * slot slot_base + k (appending the update to a pool that keeps every frame
+ * resident).  Parameters, start and expire, and birth if pool->birth is not
+ * NULL, are overwritten.  Synchronises twice: to read and check the 32-byte
+ * header (magic, version, SH degree, size) and, after the scatter, to check
+ * that every entry's slot lies inside the pool (SWGS_ERR_INVALID_ARG names
+ * how many did not; those entries are skipped, the others written).
+ * *count_out (host, nullable) receives the entry count. */
+swgs_status swgs_apply_update(swgs_context *ctx, const swgs_pool *pool, const void *record,
+                              size_t record_bytes, int64_t slot_base, int64_t *count_out);
+
+/* ------------------------------------------------------------ serving
+ * A render server over a resident pool.  Sec. 4.3's client keeps the
+ * sliding pool on the device and renders, for a requested frame, the slots
+ * live at that frame; here every per-frame update of a clip stays resident
+ * (apply them with slot_base >= 0), so any frame can be served.
+ *
+ * Requests (frame, camera, resolution) wait in a FIFO queue.  Whenever one
+ * of `lanes` streams is free, requests are taken from the head of the queue
+ * into one batch while the batch's exact workspace fits the largest free
+ * block of the memory budget, and max_batch / max_batch_pixels allow
+ * (admission by memory; a request that cannot fit even an empty budget
+ * fails with SWGS_ERR_WORKSPACE_TOO_SMALL).  Batches of mixed resolutions
+ * and frames render forward only in one launch sequence (preprocess, depth
+ * sort, binning, tile sort, blend); batches on different lanes overlap on
+ * the device, and requests that arrive meanwhile queue for the next free
+ * lane.  Live lists per frame are built once at creation, so a batch runs no
+ * gating.  The pair capacity of a batch is estimated from the largest
+ * pairs-per-record ratio seen so far; a batch whose pairs overflowed is
+ * rendered again with the exact count (stats.redone).  An image never
+ * depends on the batch it was rendered in: it equals the image of the same
+ * request rendered alone, bit for bit. */
+typedef struct swgs_server swgs_server;
+
+typedef struct {
+    size_t struct_size;        /* sizeof(swgs_server_opts) */
+    int32_t n_frames;          /* frames 0 .. n_frames-1 may be requested (>= 1) */
+    int32_t lanes;             /* batches in flight, one stream each: 1..4 */
+    int32_t max_batch;         /* requests per batch: 1..1024 */
+    int32_t tile_w, tile_h;    /* as swgs_plan_opts (0,0 = 16x16) */
+    int32_t lds_batch;         /* as swgs_plan_opts (0 = tile pixels) */
+    int64_t max_batch_pixels;  /* pixels per batch (0: no limit; a single larger request still runs alone) */
+    double pair_ratio;         /* initial pairs-per-record estimate (<= 0: 4) */
+} swgs_server_opts;
+
+typedef struct {
+    swgs_view view;            /* frame, resolution, camera, background */
+    float *image;              /* device [3][height][width] output, or NULL: rendered, then dropped */
+    double arrival;            /* seconds on the server clock (see swgs_server_submit / _run) */
+    double ready;              /* out: seconds on the server clock when the image was complete */
+    int32_t status;            /* out: -1 while pending, then SWGS_OK or the reason it failed */
+    int32_t batch;             /* out: id of the batch that rendered it (-1 if none) */
+} swgs_request;
+
+typedef struct {
+    size_t struct_size;        /* sizeof(swgs_serve_stats) */
+    int64_t completed;         /* requests with status SWGS_OK */
+    int64_t failed;            /* requests with any other final status */
+    int64_t batches;           /* batches launched (redone ones counted once) */
+    int64_t redone;            /* batches rendered again after a pair overflow */
+    double wall_s;             /* first arrival to last ready, seconds */
+    double mean_batch;         /* requests per batch */
+    size_t peak_bytes;         /* high-water mark of the budget in use */
+    size_t budget_bytes;       /* memory budget for batches (arena minus resident lists) */
+    size_t resident_bytes;     /* per-frame live lists kept for the server's lifetime */
+} swgs_serve_stats;
+
+/* Create a server on `pool` (copied; only params, start, expire are used).
+ * `arena` (device, 256-byte aligned, arena_bytes, caller-owned) is carved
+ * up by the server: the per-frame live lists at its head for the server's
+ * lifetime, the rest as the memory budget of the batches in flight.
+ * Synchronises on the context stream (counts and builds the live lists);
+ * the pool must not change while the server exists. */
+swgs_status swgs_server_create(swgs_context *ctx, const swgs_pool *pool, const swgs_server_opts *opts,
+                               void *arena, size_t arena_bytes, swgs_server **out);
+/* Waits for the batches in flight, then releases the server's streams,
+ * events and pinned buffers (not the arena). */
+swgs_status swgs_server_destroy(swgs_server *srv);
+/* Queue n requests (host array).  Each struct must stay valid until its
+ * status is final: the server writes ready, status and batch into it.
+ * arrival is set to the current server-clock time.  Requests with a bad
+ * frame, size or focal length fail at once (SWGS_ERR_INVALID_ARG in their
+ * status); the call itself fails only on bad arguments. */
+swgs_status swgs_server_submit(swgs_server *srv, swgs_request *reqs, int32_t n);
+/* Drive the scheduler once: retire finished batches (setting ready/status),
+ * then launch batches on free lanes.  wait != 0: keep driving until at
+ * least one request became final or none is pending.  *pending (host,
+ * nullable) receives the number of requests not yet final. */
+swgs_status swgs_server_progress(swgs_server *srv, int32_t wait, int64_t *pending);
+/* Replay a request trace and return when every request is final.  The
+ * server clock restarts at 0 at the call.  realtime != 0: request i is
+ * queued once reqs[i].arrival seconds have passed (arrival values are kept);
+ * realtime == 0: all are queued at once with arrival 0.  Requests are queued
+ * in ascending arrival order (ties in array order).  *stats (host, nullable)
+ * receives the run's statistics. */
+swgs_status swgs_server_run(swgs_server *srv, swgs_request *reqs, int32_t n, int32_t realtime,
+                            swgs_serve_stats *stats);
+/* Statistics since the server (or its last swgs_server_run) started. */
+swgs_status swgs_server_stats(const swgs_server *srv, swgs_serve_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

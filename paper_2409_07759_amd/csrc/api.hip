@@ -80,13 +80,11 @@ swgs_status check_ws(swgs_context *ctx, const swgs_plan *p, const void *ws, size
     return SWGS_OK;
 }
 
-void build_layout(swgs_plan &p) {
-    const size_t G = p.groups.size(), V = p.views.size();
-    const size_t R = (size_t)p.R, T = (size_t)p.T, P = (size_t)p.P, cap = (size_t)p.pair_cap;
-    const size_t S = (size_t)p.pool.n_slots, NG = (size_t)p.pool.num_gs, nA = p.n_A;
-    size_t n_list = 0;
-    for (auto &g : p.groups) n_list += g.n_live;
-    n_list += nA;
+}  // namespace
+
+void swgs::compute_layout(const LayoutDims &d, Layout &lay, size_t &consts_bytes) {
+    const size_t G = d.G, V = d.V, R = d.R, T = d.T, P = d.P, cap = d.cap;
+    const size_t S = d.S, NG = d.NG, nA = d.nA, n_list = d.n_list;
     const size_t nblk = (S + kGateChunk - 1) / kGateChunk;
     const size_t nbu = (nA + 2047) / 2048;
     size_t sz[WB_COUNT];
@@ -130,38 +128,53 @@ void build_layout(swgs_plan &p) {
     sz[WB_RELOC_DST] = (nA + 1) * 4;
     sz[WB_RELOC_SCAN] = (4 + nA / 4096 + 4) * 4;
     sz[WB_REG_PART] = 2 * ((nA + 255) / 256 + 1) * 8;
-    sz[WB_COUNTERS] = 256 * 4 * 8;
-    sz[WB_CFLAGS] = R + 16;   // 256 slots x {fwd evals, bwd evals, blended, pad}
+    sz[WB_COUNTERS] = 256 * 4 * 8;   // 256 slots x {fwd evals, bwd evals, blended, pad}
+    sz[WB_CFLAGS] = R + 16;
+    if (d.forward_only) {
+        // serving: no gating (the live lists are resident), no gradients,
+        // no loss, no step; pair buffers may live outside (ext)
+        for (int b : {WB_ACTIVE_LIST, WB_GATE_BLK, WB_POS_OF, WB_DLDC, WB_REC_GRAD, WB_LOSS_PART, WB_RELOC_W,
+                      WB_RELOC_FLAG, WB_RELOC_CNT, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_SCAN, WB_REG_PART})
+            sz[b] = 0;
+    }
     // order: constant block, then the rest
     const int order_first[] = {WB_VIEWS, WB_GROUPS, WB_GROUP_VIEWS, WB_REC_VIEW_BASE};
     size_t off = 0;
     for (int b : order_first) {
-        p.lay.off[b] = off;
-        p.lay.size[b] = sz[b];
+        lay.off[b] = off;
+        lay.size[b] = sz[b];
         off = align_up(off + sz[b], 16);
     }
-    p.consts_bytes = off;
+    consts_bytes = off;
     off = align_up(off, 256);
     for (int b = 0; b < WB_COUNT; ++b) {
         if (b == WB_VIEWS || b == WB_GROUPS || b == WB_GROUP_VIEWS || b == WB_REC_VIEW_BASE) continue;
-        p.lay.off[b] = off;
-        p.lay.size[b] = sz[b];
+        lay.off[b] = off;
+        lay.size[b] = sz[b];
         off = align_up(off + sz[b], 256);
     }
-    p.lay.total = off;
+    lay.total = off;
 }
 
-void fill_consts(swgs_plan &p) {
-    uint8_t *h = static_cast<uint8_t *>(p.consts_host);
-    std::memset(h, 0, p.consts_bytes);
-    std::memcpy(h + p.lay.off[WB_VIEWS], p.vdev.data(), p.vdev.size() * sizeof(ViewDev));
-    std::memcpy(h + p.lay.off[WB_GROUPS], p.groups.data(), p.groups.size() * sizeof(GroupDev));
-    std::memcpy(h + p.lay.off[WB_GROUP_VIEWS], p.group_views.data(), p.group_views.size() * 4);
-    std::vector<uint32_t> rvb(p.views.size() + 1);
-    for (size_t v = 0; v < p.views.size(); ++v) rvb[v] = p.vdev[v].rec_base;
-    rvb[p.views.size()] = (uint32_t)p.R;
-    std::memcpy(h + p.lay.off[WB_REC_VIEW_BASE], rvb.data(), rvb.size() * 4);
+namespace {
+
+void build_layout(swgs_plan &p) {
+    LayoutDims d;
+    d.G = p.groups.size();
+    d.V = p.views.size();
+    d.R = (size_t)p.R;
+    d.T = (size_t)p.T;
+    d.P = (size_t)p.P;
+    d.cap = (size_t)p.pair_cap;
+    d.S = (size_t)p.pool.n_slots;
+    d.NG = (size_t)p.pool.num_gs;
+    d.nA = p.n_A;
+    d.n_list = p.n_A;
+    for (auto &g : p.groups) d.n_list += g.n_live;
+    d.forward_only = p.forward_only;
+    compute_layout(d, p.lay, p.consts_bytes);
 }
+
 
 // kernel classes timed with events when a plan's timing is on
 enum { TK_GATE = 0, TK_PREPROCESS, TK_SORT, TK_FWD, TK_BWD, TK_PREBWD, TK_ADAM, TK_RELOC, TK_N };
@@ -250,6 +263,100 @@ void seq_backward_blend(hipStream_t s, swgs_plan &p, uint8_t *ws, int view, cons
 
 }  // namespace
 
+
+std::string swgs::plan_geometry(swgs_plan &p, const swgs_view *views, int n_views, const std::vector<int32_t> &frames,
+                                const std::vector<int> &vgroup, const std::vector<uint32_t> &live, uint32_t n_A) {
+    const int G = (int)frames.size();
+    p.views.assign(views, views + n_views);
+    p.groups.clear();
+    p.group_views.clear();
+    // groups and the group-ordered view list
+    p.groups.resize(G);
+    uint32_t lb_acc = 0;
+    for (int g = 0; g < G; ++g) {
+        GroupDev &gd = p.groups[g];
+        std::memset(&gd, 0, sizeof gd);
+        gd.frame = frames[g];
+        gd.n_live = live[g];
+        gd.list_base = lb_acc;
+        lb_acc += live[g];
+    }
+    p.n_A = n_A;
+    p.list_A_base = lb_acc;
+    for (int g = 0; g < G; ++g) {
+        p.groups[g].view_first = (int32_t)p.group_views.size();
+        for (int v = 0; v < n_views; ++v)
+            if (vgroup[v] == g) p.group_views.push_back(v);
+        p.groups[g].n_views = (int32_t)p.group_views.size() - p.groups[g].view_first;
+    }
+    // per-view geometry in caller order
+    p.vdev.resize(n_views);
+    uint64_t rec = 0, tiles = 0;
+    int64_t pix = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const swgs_view &w = views[v];
+        ViewDev &d = p.vdev[v];
+        std::memset(&d, 0, sizeof d);
+        std::memcpy(d.R, w.R, sizeof d.R);
+        std::memcpy(d.t, w.t, sizeof d.t);
+        d.fx = w.fx; d.fy = w.fy; d.cx = w.cx; d.cy = w.cy;
+        for (int c = 0; c < 3; ++c) d.campos[c] = -(w.R[c] * w.t[0] + w.R[3 + c] * w.t[1] + w.R[6 + c] * w.t[2]);
+        d.limx = 1.3 * (0.5 * w.width / w.fx);
+        d.limy = 1.3 * (0.5 * w.height / w.fy);
+        for (int c = 0; c < 3; ++c) d.bg[c] = w.bg[c];
+        d.frame = w.frame;
+        d.width = w.width;
+        d.height = w.height;
+        d.tiles_x = (w.width + p.tile_w - 1) / p.tile_w;
+        d.tiles_y = (w.height + p.tile_h - 1) / p.tile_h;
+        d.group = vgroup[v];
+        d.rec_base = (uint32_t)rec;
+        d.tile_base = (uint32_t)tiles;
+        d.pix_base = pix;
+        d.inv_norm = (float)(1.0 / ((double)n_views * 3.0 * (double)w.width * (double)w.height));
+        rec += live[vgroup[v]];
+        tiles += (uint64_t)d.tiles_x * d.tiles_y;
+        pix += (int64_t)w.width * w.height;
+    }
+    if (rec >= 0xFFFFFFF0ull || tiles >= 0xFFFFFFF0ull) return "more than 2^32 records or tiles in one plan";
+    p.R = (int64_t)rec;
+    p.T = (int64_t)tiles;
+    p.P = pix;
+    p.tile_key_bits = tile_bits(p.T);
+    build_layout(p);
+    return std::string();
+}
+
+void swgs::fill_consts(swgs_plan &p) {
+    uint8_t *h = static_cast<uint8_t *>(p.consts_host);
+    std::memset(h, 0, p.consts_bytes);
+    std::memcpy(h + p.lay.off[WB_VIEWS], p.vdev.data(), p.vdev.size() * sizeof(ViewDev));
+    std::memcpy(h + p.lay.off[WB_GROUPS], p.groups.data(), p.groups.size() * sizeof(GroupDev));
+    std::memcpy(h + p.lay.off[WB_GROUP_VIEWS], p.group_views.data(), p.group_views.size() * 4);
+    std::vector<uint32_t> rvb(p.views.size() + 1);
+    for (size_t v = 0; v < p.views.size(); ++v) rvb[v] = p.vdev[v].rec_base;
+    rvb[p.views.size()] = (uint32_t)p.R;
+    std::memcpy(h + p.lay.off[WB_REC_VIEW_BASE], rvb.data(), rvb.size() * 4);
+}
+
+void swgs::seq_forward_all(hipStream_t s, swgs_plan &p, uint8_t *ws, float *images, const float *targets) {
+    seq_forward(s, p, ws, -1, images, targets);
+}
+
+std::string swgs::tile_opts(int tile_w, int tile_h, int lds_batch, int *tw, int *th, int *lb) {
+    int w = tile_w, h = tile_h;
+    if (w == 0 && h == 0) { w = 16; h = 16; }
+    if (!((w == 16 && h == 16) || (w == 8 && h == 8) || (w == 32 && h == 8)))
+        return "tile shape must be 8x8, 16x16 or 32x8";
+    const int b = lds_batch == 0 ? w * h : lds_batch;
+    if (!(b == 64 || b == 128 || b == 256)) return "lds_batch must be 64, 128 or 256";
+    if (b == 64 && !(w == 8 && h == 8)) return "lds_batch 64 needs 8x8 tiles";
+    *tw = w;
+    *th = h;
+    *lb = b;
+    return std::string();
+}
+
 // ============================================================== ABI
 extern "C" {
 
@@ -324,13 +431,9 @@ swgs_status swgs_plan_create(swgs_context *ctx, const swgs_pool *pool, const swg
     if (!views || n_views <= 0) return fail(ctx, SWGS_ERR_INVALID_ARG, "need at least one view");
     if (n_views > 65535) return fail(ctx, SWGS_ERR_UNSUPPORTED, "at most 65535 views per plan");
     if (!opts || opts->struct_size != sizeof(swgs_plan_opts)) return fail(ctx, SWGS_ERR_INVALID_ARG, "opts.struct_size mismatch");
-    int tw = opts->tile_w, th = opts->tile_h;
-    if (tw == 0 && th == 0) { tw = 16; th = 16; }
-    if (!((tw == 16 && th == 16) || (tw == 8 && th == 8) || (tw == 32 && th == 8)))
-        return fail(ctx, SWGS_ERR_UNSUPPORTED, "tile shape must be 8x8, 16x16 or 32x8");
-    int lb = opts->lds_batch == 0 ? tw * th : opts->lds_batch;
-    if (!(lb == 64 || lb == 128 || lb == 256)) return fail(ctx, SWGS_ERR_UNSUPPORTED, "lds_batch must be 64, 128 or 256");
-    if (lb == 64 && !(tw == 8 && th == 8)) return fail(ctx, SWGS_ERR_UNSUPPORTED, "lds_batch 64 needs 8x8 tiles");
+    int tw = 16, th = 16, lb = 256;
+    const std::string terr = tile_opts(opts->tile_w, opts->tile_h, opts->lds_batch, &tw, &th, &lb);
+    if (!terr.empty()) return fail(ctx, SWGS_ERR_UNSUPPORTED, terr);
     if (opts->pair_capacity <= 0 || opts->pair_capacity > 0xFFFFFFF0LL)
         return fail(ctx, SWGS_ERR_INVALID_ARG, "pair_capacity must be in (0, 2^32 - 16)");
     for (int v = 0; v < n_views; ++v) {
@@ -348,8 +451,6 @@ swgs_status swgs_plan_create(swgs_context *ctx, const swgs_pool *pool, const swg
     p->tile_h = th;
     p->lds_batch = lb;
     p->pair_cap = opts->pair_capacity;
-    p->views.assign(views, views + n_views);
-
     // distinct frames in order of appearance
     std::vector<int32_t> frames;
     std::vector<int> vgroup(n_views);
@@ -376,63 +477,12 @@ swgs_status swgs_plan_create(swgs_context *ctx, const swgs_pool *pool, const swg
         delete p;
         return fail(ctx, SWGS_ERR_HIP, std::string("live count failed: ") + hipGetErrorString(hipGetLastError()));
     }
-    // groups and the group-ordered view list
-    p->groups.resize(G);
-    uint32_t lb_acc = 0;
-    for (int g = 0; g < G; ++g) {
-        GroupDev &gd = p->groups[g];
-        std::memset(&gd, 0, sizeof gd);
-        gd.frame = frames[g];
-        gd.n_live = counts[g];
-        gd.list_base = lb_acc;
-        lb_acc += counts[g];
-    }
-    p->n_A = counts[G];
-    p->list_A_base = lb_acc;
-    for (int g = 0; g < G; ++g) {
-        p->groups[g].view_first = (int32_t)p->group_views.size();
-        for (int v = 0; v < n_views; ++v)
-            if (vgroup[v] == g) p->group_views.push_back(v);
-        p->groups[g].n_views = (int32_t)p->group_views.size() - p->groups[g].view_first;
-    }
-    // per-view geometry in caller order
-    p->vdev.resize(n_views);
-    uint64_t rec = 0, tiles = 0;
-    int64_t pix = 0;
-    for (int v = 0; v < n_views; ++v) {
-        const swgs_view &w = views[v];
-        ViewDev &d = p->vdev[v];
-        std::memset(&d, 0, sizeof d);
-        std::memcpy(d.R, w.R, sizeof d.R);
-        std::memcpy(d.t, w.t, sizeof d.t);
-        d.fx = w.fx; d.fy = w.fy; d.cx = w.cx; d.cy = w.cy;
-        for (int c = 0; c < 3; ++c) d.campos[c] = -(w.R[c] * w.t[0] + w.R[3 + c] * w.t[1] + w.R[6 + c] * w.t[2]);
-        d.limx = 1.3 * (0.5 * w.width / w.fx);
-        d.limy = 1.3 * (0.5 * w.height / w.fy);
-        for (int c = 0; c < 3; ++c) d.bg[c] = w.bg[c];
-        d.frame = w.frame;
-        d.width = w.width;
-        d.height = w.height;
-        d.tiles_x = (w.width + tw - 1) / tw;
-        d.tiles_y = (w.height + th - 1) / th;
-        d.group = vgroup[v];
-        d.rec_base = (uint32_t)rec;
-        d.tile_base = (uint32_t)tiles;
-        d.pix_base = pix;
-        d.inv_norm = (float)(1.0 / ((double)n_views * 3.0 * (double)w.width * (double)w.height));
-        rec += counts[vgroup[v]];
-        tiles += (uint64_t)d.tiles_x * d.tiles_y;
-        pix += (int64_t)w.width * w.height;
-    }
-    if (rec >= 0xFFFFFFF0ull || tiles >= 0xFFFFFFF0ull) {
+    std::vector<uint32_t> live(counts.begin(), counts.begin() + G);
+    const std::string gerr = plan_geometry(*p, views, n_views, frames, vgroup, live, counts[G]);
+    if (!gerr.empty()) {
         delete p;
-        return fail(ctx, SWGS_ERR_UNSUPPORTED, "more than 2^32 records or tiles in one plan");
+        return fail(ctx, SWGS_ERR_UNSUPPORTED, gerr);
     }
-    p->R = (int64_t)rec;
-    p->T = (int64_t)tiles;
-    p->P = pix;
-    p->tile_key_bits = tile_bits(p->T);
-    build_layout(*p);
     if (hipHostMalloc(&p->consts_host, p->consts_bytes) != hipSuccess) {
         delete p;
         return fail(ctx, SWGS_ERR_HIP, "pinned constant block alloc failed");
@@ -746,17 +796,13 @@ swgs_status swgs_mature(swgs_context *ctx, const swgs_pool *pool, int32_t st, vo
     HIP_TRY(ctx, ctx_scratch(ctx, words * 4, &scr));
     uint32_t *sc = static_cast<uint32_t *>(scr);
     uint32_t *d_count = sc + words - 2;
-    // count first: the record must fit before anything is written
+    // the count comes first (from start[] on the host): the record must be
+    // known to fit before anything is written
     hipStream_t s = ctx->stream;
     const int F = rows_for(pool->sh_degree);
-    // flags + scan only (pack is the second launch of launch_mature), so run
-    // the count on a copy of the pool with num_gs slots and no writes: the
-    // flags kernel is side-effect free
     swgs_pool q = *pool;
     uint32_t cnt = 0;
     {
-        // reuse launch_mature's first two steps by calling it with a NULL
-        // record is not possible; count on the host from the device start[]
         std::vector<int32_t> hs(n);
         HIP_TRY(ctx, hipMemcpyAsync(hs.data(), pool->start, 4 * (size_t)n, hipMemcpyDeviceToHost, s));
         HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -769,6 +815,38 @@ swgs_status swgs_mature(swgs_context *ctx, const swgs_pool *pool, int32_t st, vo
     HIP_TRY(ctx, hipStreamSynchronize(s));
     if (count_out) *count_out = cnt;
     if (bytes_out) *bytes_out = need;
+    return SWGS_OK;
+}
+
+swgs_status swgs_apply_update(swgs_context *ctx, const swgs_pool *pool, const void *record, size_t record_bytes,
+                              int64_t slot_base, int64_t *count_out) {
+    if (!ctx) return SWGS_ERR_INVALID_ARG;
+    std::string why;
+    if (!pool_ok(pool, false, why)) return fail(ctx, SWGS_ERR_INVALID_ARG, why);
+    if (!record || record_bytes < 32) return fail(ctx, SWGS_ERR_INVALID_ARG, "record is NULL or shorter than its header");
+    hipStream_t s = ctx->stream;
+    int32_t h[8];
+    HIP_TRY(ctx, hipMemcpyAsync(h, record, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (h[0] != 0x53475753 || h[1] != 1) return fail(ctx, SWGS_ERR_INVALID_ARG, "not a version-1 update record");
+    if (h[3] < 0) return fail(ctx, SWGS_ERR_INVALID_ARG, "negative entry count in the record");
+    if (h[4] != pool->sh_degree || h[5] != rows_for(pool->sh_degree))
+        return fail(ctx, SWGS_ERR_INVALID_ARG, "record SH degree " + std::to_string(h[4]) + " differs from the pool's");
+    const uint32_t n = (uint32_t)h[3];
+    if (record_bytes < swgs_record_bytes(n, pool->sh_degree))
+        return fail(ctx, SWGS_ERR_INVALID_ARG, "record_bytes smaller than the record's entries");
+    if (slot_base >= 0 && slot_base + (int64_t)n > (int64_t)pool->n_slots)
+        return fail(ctx, SWGS_ERR_INVALID_ARG, "slot_base + count exceeds n_slots");
+    void *scr = nullptr;
+    HIP_TRY(ctx, ctx_scratch(ctx, 256, &scr));
+    uint32_t *bad = static_cast<uint32_t *>(scr);
+    launch_fill_u32(s, bad, 0, 1);
+    launch_apply_update(s, *pool, rows_for(pool->sh_degree), static_cast<const uint8_t *>(record), n, slot_base, bad);
+    uint32_t nbad = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&nbad, bad, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (count_out) *count_out = n;
+    if (nbad) return fail(ctx, SWGS_ERR_INVALID_ARG, std::to_string(nbad) + " record entries name slots outside the pool");
     return SWGS_OK;
 }
 

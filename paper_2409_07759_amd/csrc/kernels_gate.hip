@@ -167,6 +167,19 @@ void launch_gate(hipStream_t s, const swgs_plan &p, uint8_t *ws) {
                        wsp<int32_t>(ws, p, WB_POS_OF));
 }
 
+void launch_frame_lists(hipStream_t s, const int32_t *start, const int32_t *expire, int n_slots,
+                        const GroupDev *groups, int n_groups, uint32_t *blk, uint32_t *totals, uint32_t *lists) {
+    // the gating kernels with no optimisable slots (num_gs = 0): the extra
+    // group row (window set) stays empty and pos_of is never written
+    const int nblk = (n_slots + kGateChunk - 1) / kGateChunk;
+    dim3 grid(nblk, n_groups + 1);
+    hipLaunchKernelGGL(k_gate_count, grid, dim3(kBlock), 0, s, start, expire, groups, n_groups, 0, n_slots, nblk,
+                       blk);
+    hipLaunchKernelGGL(k_gate_scan, dim3(n_groups + 1), dim3(kBlock), 0, s, blk, nblk, totals);
+    hipLaunchKernelGGL(k_gate_write, grid, dim3(kBlock), 0, s, start, expire, groups, n_groups, 0, n_slots, nblk,
+                       blk, 0u, 0u, lists, nullptr);
+}
+
 void launch_count_live(hipStream_t s, const int32_t *start, const int32_t *expire, int n_slots,
                        int num_gs, const int32_t *frames, int n_frames, uint32_t *out_counts) {
     int nb = (n_slots + kBlock - 1) / kBlock;

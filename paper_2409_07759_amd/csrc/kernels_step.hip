@@ -634,7 +634,39 @@ k_mature_pack(float *__restrict__ params, int n_slots, int num_gs, int F, int sw
     expire[i] = e + swin;
 }
 
+// Algorithm 2's update: entry k of a mature record goes to slot
+// record.slot[k] (slot_base < 0: the slice the record was emitted from) or
+// to slot_base + k; parameters and lifespan are overwritten.  Entries whose
+// slot is outside the pool are skipped and counted in *bad.
+__global__ void __launch_bounds__(kBlock)
+k_apply_update(float *__restrict__ params, int n_slots, int F, int32_t *__restrict__ birth,
+               int32_t *__restrict__ start, int32_t *__restrict__ expire, const uint8_t *__restrict__ record,
+               uint32_t n, int64_t slot_base, uint32_t *__restrict__ bad) {
+    const uint32_t k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const uint32_t *slots = reinterpret_cast<const uint32_t *>(record + 32);
+    const int32_t *lb = reinterpret_cast<const int32_t *>(record + 32 + 4 * (size_t)n);
+    const float *pr = reinterpret_cast<const float *>(record + 32 + 16 * (size_t)n);
+    const int64_t slot = slot_base < 0 ? (int64_t)slots[k] : slot_base + (int64_t)k;
+    if (slot < 0 || slot >= n_slots) {
+        atomicAdd(bad, 1u);
+        return;
+    }
+    const size_t S = (size_t)n_slots;
+    for (int r = 0; r < F; ++r) params[r * S + (size_t)slot] = pr[(size_t)r * n + k];
+    if (birth) birth[slot] = lb[k];
+    start[slot] = lb[n + k];
+    expire[slot] = lb[2 * (size_t)n + k];
+}
+
 }  // namespace
+
+void launch_apply_update(hipStream_t s, const swgs_pool &pool, int F, const uint8_t *record, uint32_t count,
+                         int64_t slot_base, uint32_t *bad_slots) {
+    if (count == 0) return;
+    hipLaunchKernelGGL(k_apply_update, dim3((count + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pool.params,
+                       pool.n_slots, F, pool.birth, pool.start, pool.expire, record, count, slot_base, bad_slots);
+}
 
 void launch_preprocess_backward(hipStream_t s, const swgs_plan &p, uint8_t *ws, int add_reg,
                                 float lambda_o, float lambda_s) {

@@ -59,6 +59,14 @@ struct Layout {
     size_t total = 0;
 };
 
+// What a workspace layout depends on: views, distinct frames, records,
+// tiles, pixels, pair capacity, pool slots, optimisable slots, window set,
+// live-list entries.
+struct LayoutDims {
+    size_t V = 0, G = 0, R = 0, T = 0, P = 0, cap = 0, S = 0, NG = 0, nA = 0, n_list = 0;
+    bool forward_only = false;
+};
+
 enum WsBuf {
     WB_ACTIVE_LIST = 0, WB_ACTIVE_COUNT, WB_REC_VIEW_BASE, WB_DEPTH_KEY, WB_TILE_COUNT,
     WB_RECT, WB_SPLAT, WB_PAIR_KEY, WB_PAIR_VAL, WB_PAIR_COUNT, WB_TILE_RANGE, WB_T_FINAL,
@@ -106,6 +114,11 @@ struct swgs_plan {
     swgs_step_cfg graph_cfg{};
     void *consts_host = nullptr;                  // pinned copy of the constant block
     size_t consts_bytes = 0;
+    // forward-only plans (serving) carry no training buffers
+    bool forward_only = false;
+    // buffers that live outside the workspace (absolute device pointers; a
+    // null entry means "at lay.off[] in the workspace")
+    uint8_t *ext[swgs::WB_COUNT] = {};
     // event timing of kernel classes (off unless enabled; never inside a graph)
     bool timing = false;
     std::vector<hipEvent_t> ev[8];
@@ -181,7 +194,42 @@ struct StepDev {
 
 template <typename T>
 inline T *wsp(uint8_t *ws, const swgs_plan &p, int which) {
-    return reinterpret_cast<T *>(ws + p.lay.off[which]);
+    return reinterpret_cast<T *>(p.ext[which] ? p.ext[which] : ws + p.lay.off[which]);
 }
+
+// Plan geometry shared by swgs_plan_create and the server: groups of
+// distinct frames (live counts given per group), per-view records, tiles
+// and pixels, the workspace layout and the pinned constant block.  Returns
+// an empty string or the reason for failure.
+std::string plan_geometry(swgs_plan &p, const swgs_view *views, int n_views, const std::vector<int32_t> &frames,
+                          const std::vector<int> &vgroup, const std::vector<uint32_t> &live, uint32_t n_A);
+// Checks a tile shape / LDS batch request (0,0 and 0 pick the defaults) and
+// returns the effective values; "" or the reason it is not supported.
+std::string tile_opts(int tile_w, int tile_h, int lds_batch, int *tw, int *th, int *lb);
+// Workspace layout for the given dimensions (offsets, sizes, total) and the
+// size of its leading constant block.
+void compute_layout(const LayoutDims &d, Layout &lay, size_t &consts_bytes);
+// Copy of the constant block (views, groups, group view list, record view
+// bases) into p.consts_host (consts_bytes, allocated by the caller).
+void fill_consts(swgs_plan &p);
+// Forward of every view of a plan in one launch sequence (gating not
+// included): preprocess, depth sort, pair offsets, emit, pair sort, tile
+// ranges, blend.
+void seq_forward_all(hipStream_t s, swgs_plan &p, uint8_t *ws, float *images, const float *targets);
+
+// Per-frame live lists of a resident pool (serving): for groups[g] (device,
+// frame and list_base set) the live slots in ascending order are written at
+// lists[list_base...]; blk is scratch of (n_groups + 1) * ceil(n_slots /
+// kGateChunk) uint32, totals of n_groups + 1.
+void launch_frame_lists(hipStream_t s, const int32_t *start, const int32_t *expire, int n_slots,
+                        const GroupDev *groups, int n_groups, uint32_t *blk, uint32_t *totals, uint32_t *lists);
+inline size_t frame_lists_scratch_words(int n_slots, int n_groups) {
+    return (size_t)(n_groups + 1) * (size_t)((n_slots + kGateChunk - 1) / kGateChunk) + (size_t)n_groups + 8;
+}
+
+// Scatter of a mature record into a pool (Algorithm 2's slice replacement
+// when slot_base < 0, else append at slot_base + k).
+void launch_apply_update(hipStream_t s, const swgs_pool &pool, int F, const uint8_t *record, uint32_t count,
+                         int64_t slot_base, uint32_t *bad_slots);
 
 }  // namespace swgs

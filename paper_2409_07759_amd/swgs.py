@@ -57,6 +57,24 @@ class SwgsStepCfg(ctypes.Structure):
         (n, ctypes.c_int32) for n in ("window_start", "relocate_period", "reloc_n_max", "mode", "reserved")]
 
 
+class SwgsServerOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t), ("n_frames", ctypes.c_int32), ("lanes", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("lds_batch", ctypes.c_int32), ("max_batch_pixels", ctypes.c_int64), ("pair_ratio", ctypes.c_double)]
+
+
+class SwgsRequest(ctypes.Structure):
+    _fields_ = [("view", SwgsView), ("image", ctypes.c_void_p), ("arrival", ctypes.c_double),
+                ("ready", ctypes.c_double), ("status", ctypes.c_int32), ("batch", ctypes.c_int32)]
+
+
+class SwgsServeStats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_size_t), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("redone", ctypes.c_int64), ("wall_s", ctypes.c_double),
+                ("mean_batch", ctypes.c_double), ("peak_bytes", ctypes.c_size_t), ("budget_bytes", ctypes.c_size_t),
+                ("resident_bytes", ctypes.c_size_t)]
+
+
 P, I32, I64, U64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
 _sigs = {
     "swgs_version": ([], ctypes.c_int),
@@ -79,6 +97,13 @@ _sigs = {
     "swgs_record_bytes": ([I64, I32], SZ),
     "swgs_plan_set_timing": ([P, P, P, SZ, I32], ctypes.c_int),
     "swgs_plan_timing": ([P, P, P, SZ, P, P, P], ctypes.c_int),
+    "swgs_apply_update": ([P, P, P, SZ, I64, P], ctypes.c_int),
+    "swgs_server_create": ([P, P, P, P, SZ, P], ctypes.c_int),
+    "swgs_server_destroy": ([P], ctypes.c_int),
+    "swgs_server_submit": ([P, P, I32], ctypes.c_int),
+    "swgs_server_progress": ([P, I32, P], ctypes.c_int),
+    "swgs_server_run": ([P, P, I32, I32, P], ctypes.c_int),
+    "swgs_server_stats": ([P, P], ctypes.c_int),
 }
 TIMING_CLASSES = ("gate", "preprocess", "sort", "blend_fwd", "blend_bwd", "preprocess_bwd", "adam_sgld", "relocate")
 for _n, (_a, _r) in _sigs.items():
@@ -363,3 +388,94 @@ class RenderFunction(torch.autograd.Function):
 
 def render(params, plan: Plan):
     return RenderFunction.apply(params, plan)
+
+
+def apply_update(ctx: Context, pool: Pool, record, slot_base: int = -1) -> int:
+    """Algorithm 2's update: scatter a mature record (uint8 device tensor)
+    into the pool, at the slots it was emitted from (slot_base < 0) or at
+    slot_base + k.  Returns the number of entries."""
+    cnt = ctypes.c_int64()
+    cp = pool.c()
+    with ctx:
+        ctx.check(swgs_apply_update(ctx.h, ctypes.byref(cp), ptr(record), int(record.numel()), int(slot_base),
+                                    ctypes.byref(cnt)))
+    return cnt.value
+
+
+def c_requests(views, images=None, arrivals=None):
+    arr = (SwgsRequest * len(views))()
+    cv = c_views(views)
+    for i in range(len(views)):
+        arr[i].view = cv[i]
+        arr[i].image = images[i].data_ptr() if images is not None and images[i] is not None else None
+        arr[i].arrival = float(arrivals[i]) if arrivals is not None else 0.0
+        arr[i].status = -1
+        arr[i].batch = -1
+    return arr
+
+
+class Server:
+    """Render server over a resident pool (forward only).  arena_bytes of
+    device memory are allocated here and handed to the library: per-frame
+    live lists at its head, the rest is the memory budget for batches."""
+
+    def __init__(self, ctx: Context, pool: Pool, n_frames: int, arena_bytes: int, lanes: int = 3,
+                 max_batch: int = 16, tile=(16, 16), lds_batch: int = 0, max_batch_pixels: int = 0,
+                 pair_ratio: float = 0.0):
+        self.ctx, self.pool = ctx, pool
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=ctx.device)
+        opts = SwgsServerOpts(ctypes.sizeof(SwgsServerOpts), int(n_frames), int(lanes), int(max_batch),
+                              int(tile[0]), int(tile[1]), int(lds_batch), int(max_batch_pixels), float(pair_ratio))
+        self._cpool = pool.c()
+        h = ctypes.c_void_p()
+        with ctx:
+            ctx.check(swgs_server_create(ctx.h, ctypes.byref(self._cpool), ctypes.byref(opts), ptr(self.arena),
+                                         int(arena_bytes), ctypes.byref(h)))
+        self.h = h
+        self._live = []          # request arrays the library may still write into
+
+    def run(self, views, arrivals=None, images=None, realtime=False):
+        """Replay requests (views with frame/resolution/camera); arrivals in
+        seconds (realtime) or all at once.  images: optional list of device
+        tensors [3, H, W] to receive each render.  Returns (arrival, ready,
+        status, batch) numpy arrays and the stats dict."""
+        reqs = c_requests(views, images, arrivals)
+        st = SwgsServeStats()
+        st.struct_size = ctypes.sizeof(SwgsServeStats)
+        torch.cuda.synchronize(self.ctx.device)
+        self.ctx.check(swgs_server_run(self.h, reqs, len(views), int(bool(realtime)), ctypes.byref(st)))
+        out = (np.array([r.arrival for r in reqs]), np.array([r.ready for r in reqs]),
+               np.array([r.status for r in reqs], np.int32), np.array([r.batch for r in reqs], np.int32))
+        return out, {k: getattr(st, k) for k, _ in SwgsServeStats._fields_ if k != "struct_size"}
+
+    def submit(self, views, images=None):
+        reqs = c_requests(views, images)
+        torch.cuda.synchronize(self.ctx.device)
+        self.ctx.check(swgs_server_submit(self.h, reqs, len(views)))
+        self._live.append(reqs)
+        return reqs
+
+    def progress(self, wait=False) -> int:
+        n = ctypes.c_int64()
+        self.ctx.check(swgs_server_progress(self.h, int(bool(wait)), ctypes.byref(n)))
+        if n.value == 0:
+            self._live = []
+        return n.value
+
+    def stats(self):
+        st = SwgsServeStats()
+        st.struct_size = ctypes.sizeof(SwgsServeStats)
+        self.ctx.check(swgs_server_stats(self.h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in SwgsServeStats._fields_ if k != "struct_size"}
+
+    def close(self):
+        if self.h:
+            swgs_server_destroy(self.h)
+            self.h = None
+            self._live = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -49,6 +49,34 @@ def test_struct_sizes_match_the_header():
     assert ctypes.sizeof(swgs.SwgsPlanOpts) == 8 + 16 + 8
 
 
+def test_struct_layouts_match_a_c_compiler(tmp_path):
+    """sizeof / offsetof of every ABI struct as gcc sees the header equal the
+    ctypes mirrors the binding uses."""
+    import shutil
+    import subprocess
+    if not shutil.which("gcc"):
+        pytest.skip("gcc not available")
+    structs = {"swgs_pool": swgs.SwgsPool, "swgs_view": swgs.SwgsView, "swgs_plan_opts": swgs.SwgsPlanOpts,
+               "swgs_step_cfg": swgs.SwgsStepCfg, "swgs_server_opts": swgs.SwgsServerOpts,
+               "swgs_request": swgs.SwgsRequest, "swgs_serve_stats": swgs.SwgsServeStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "swgs.h"', "int main(void) {"]
+    for cname, ct in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in ct._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {" ".join(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, ct in structs.items():
+        assert got[f"{cname} size"] == ctypes.sizeof(ct), cname
+        for fname, _ in ct._fields_:
+            assert got[f"{cname} {fname}"] == getattr(ct, fname).offset, (cname, fname)
+
+
 def test_buffer_enum_matches_the_header():
     txt = open(os.path.join(ROOT, "include", "swgs.h")).read()
     block = txt[txt.index("SWGS_BUF_ACTIVE_LIST = 0"):txt.index("SWGS_BUF_COUNT_")]
