@@ -128,7 +128,7 @@ struct swgs_server {
     Budget budget;
     std::vector<std::unique_ptr<Lane>> lanes;
     std::deque<swgs_request *> queue;
-    double ratio = 4.0;                      // pairs-per-record estimate
+    double ratio = 4.0;                      // pairs-per-record estimate (largest seen x 1.15)
     Clock::time_point origin;
     int64_t next_batch = 0, pending = 0, batched_reqs = 0;
     swgs_serve_stats st{};
@@ -314,7 +314,7 @@ swgs_status retire_lane(swgs_server *s, Lane &L) {
         if (R > 0) s->ratio = std::max(s->ratio, 1.15 * (double)K / R);
         return redo_lane(s, L);
     }
-    if (R > 0) s->ratio = std::max(1.15 * (double)K / R, 0.98 * s->ratio);
+    if (R > 0) s->ratio = std::max(s->ratio, 1.15 * (double)K / R);
     const double t = s->now();
     for (auto *r : L.reqs) {
         r->batch = (int32_t)L.batch;

@@ -1,0 +1,266 @@
+"""Full-size parity of the window step the benchmark times.
+
+Workload: 200k optimisable + 200k frozen Gaussians, SH degree 3, frames
+10..19 x 4 cameras at 1352x1014, every frame with 200k live slots; one
+window step in the benchmark's launch configuration (captured hipGraph,
+16x16 tiles, 128 Gaussians per LDS batch, relocation every step).  Targets
+are seeded uniform images, an input independent of both sides.
+
+The oracle cannot render 40 megapixel views, so it computes sampled outputs
+one by one:
+ - per-frame live lists and, for all 40 views, every record's culling, tile
+   range, tile count and FP32 depth key (bit-exact; records within 1e-12 of
+   a decision threshold are reported and excluded), and the pair total;
+ - the depth-ordered list of sampled tiles (bit-exact) and their pixels
+   (1e-5): a pixel is rendered from the Gaussians whose tile range contains
+   its tile, which is exact because the support box bounds every pixel
+   where a Gaussian passes the 1/255 test;
+ - the gradient of sampled Gaussians summed over all views (1e-3
+   relative): the oracle renders every pixel of the Gaussian's tiles in each
+   view, takes its own L1 upstream gradient sign(C - target) / (3 P V),
+   runs its adjoint and chain rule and adds the regulariser gradient;
+   samples touching a pixel within 1e-5 of a sign change or of a blend
+   decision are excluded and counted;
+ - the Adam + SGLD update of those Gaussians.
+Properties checked at full size: the fused loss equals mean |C - target|
+plus the oracle's regulariser; frozen slots are untouched; no dead slot
+remains after relocation."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2409_07759_amd import synth as S
+from scenes import IMG_TOL, MARGIN_INT, MARGIN_PIX, grad_close
+
+pytestmark = pytest.mark.gpu
+
+NUM_GS, SWIN, DEG, ST0, CAMS, W, H = 200_000, 10, 3, 10, 4, 1352, 1014
+TILE, LDS = (16, 16), 128
+SEED_STEP = 2
+N_SAMPLE = 12
+# A gradient sample sums ~1e6 blend decisions; the FP32 kernel's alpha and
+# transmittance carry ~1e-6 relative error, so a decision can only differ
+# from the FP64 oracle's within a margin well below 1e-5 of its threshold.
+MARGIN_DECISION = 1e-5
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def run():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_07759_amd import swgs as sw
+    pool = S.steady_window_pool(NUM_GS, SWIN, DEG, ST0, seed=0)
+    views = S.ring_views(list(range(ST0, ST0 + SWIN)), CAMS, W, H, phase_deg=10.0)
+    tgt = S.random_images(views, 7)
+    say("full-size window step", len(views), "views")
+    ctx = sw.Context(0)
+    dp = sw.Pool.from_synth(pool)
+    plan = sw.Plan(ctx, dp, views, tile=TILE, lds_batch=LDS, headroom=1.5)
+    cfg = sw.step_cfg(mode=sw.SWGS_MODE_GRAPH, window_start=ST0, relocate_period=1)
+    img = plan.image_buffer()
+    stats = torch.zeros(8, dtype=torch.float64, device="cuda")
+    plan.window_step(cfg, torch.as_tensor(tgt, device="cuda"), 1, 0, SEED_STEP, images=img, stats=stats)
+    out = dict(sw=sw, pool=pool, views=views, tgt=tgt, cfg=cfg, img=host(img), stats=host(stats),
+               grads=host(dp.grads), params=host(dp.params),
+               lists=host(plan.buffer(sw.SWGS_BUF_ACTIVE_LIST)), counts=host(plan.buffer(sw.SWGS_BUF_ACTIVE_COUNT)),
+               rvb=host(plan.buffer(sw.SWGS_BUF_RECORD_VIEW_BASE)), tc=host(plan.buffer(sw.SWGS_BUF_TILE_COUNT)),
+               rect=host(plan.buffer(sw.SWGS_BUF_RECT)).reshape(-1, 2),
+               splat=host(plan.buffer(sw.SWGS_BUF_SPLAT, torch.float32)).reshape(-1, 12),
+               ranges=host(plan.buffer(sw.SWGS_BUF_TILE_RANGE)).reshape(-1, 2),
+               pair_val=host(plan.buffer(sw.SWGS_BUF_PAIR_VAL)))
+    say("step done; stats", out["stats"])
+    plan.close()
+    del dp
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def view_slots(r, vi):
+    """Slots of view vi's records, in record order (the frame's live list)."""
+    frames = []
+    for v in r["views"]:
+        if v.frame not in frames:
+            frames.append(v.frame)
+    base = np.concatenate([[0], np.cumsum(r["counts"][:len(frames)].astype(np.int64))])
+    g = frames.index(r["views"][vi].frame)
+    return r["lists"][base[g]:base[g + 1]]
+
+
+def test_fullsize_lists_records_and_pair_total(run):
+    r = run
+    pool, views = r["pool"], r["views"]
+    P0 = pool.params.astype(np.float64)
+    K_ref = 0
+    flagged = 0
+    for vi, v in enumerate(views):
+        slots = view_slots(r, vi)
+        act = np.nonzero(O.active(pool.start, pool.expire, v.frame))[0]
+        assert np.array_equal(slots.astype(np.int64), act), vi
+        vis, rec, orect = O.preprocess(P0, DEG, pool.start, pool.expire, v, *TILE)
+        r0 = int(r["rvb"][vi])
+        tc = r["tc"][r0:r0 + len(slots)]
+        rect = r["rect"][r0:r0 + len(slots)]
+        splat = r["splat"][r0:r0 + len(slots)]
+        ok = rec[slots, O.R_MARGIN] >= MARGIN_INT
+        flagged += int((~ok).sum())
+        ovis = vis[slots] == 1
+        orc = orect[slots]
+        same = ovis == (tc > 0)
+        same &= ~ovis | (((rect[:, 0] & 0xFFFF) == orc[:, 0]) & ((rect[:, 0] >> 16) == orc[:, 1]) &
+                         ((rect[:, 1] & 0xFFFF) == orc[:, 2]) & ((rect[:, 1] >> 16) == orc[:, 3]))
+        same &= ~ovis | (tc == (orc[:, 2] - orc[:, 0]) * (orc[:, 3] - orc[:, 1]))
+        same &= ~ovis | (splat[:, 11].view(np.uint32) == rec[slots, O.R_DEPTH].astype(np.float32).view(np.uint32))
+        assert np.all(same | ~ok), (vi, np.nonzero(~same & ok)[0][:5])
+        K_ref += int(((orc[:, 2] - orc[:, 0]) * (orc[:, 3] - orc[:, 1]))[ovis].sum())
+    say("records flagged", flagged, "pairs", int(r["stats"][4]), "oracle", K_ref)
+    assert flagged <= 1e-3 * len(views) * 2 * NUM_GS
+    if flagged == 0:
+        assert int(r["stats"][4]) == K_ref
+    else:
+        assert abs(int(r["stats"][4]) - K_ref) <= 64 * flagged
+
+
+def test_fullsize_tile_lists_and_pixels(run):
+    r = run
+    pool, views = r["pool"], r["views"]
+    P0 = pool.params.astype(np.float64)
+    rng = np.random.default_rng(11)
+    tx, ty = (W + TILE[0] - 1) // TILE[0], (H + TILE[1] - 1) // TILE[1]
+    excl = tot = 0
+    worst = 0.0
+    for vi in (0, 13, 26, 39):
+        v = views[vi]
+        slots = view_slots(r, vi)
+        r0 = int(r["rvb"][vi])
+        vis, rec, orect = O.preprocess(P0, DEG, pool.start, pool.expire, v, *TILE)
+        tiles = [(int(rng.integers(0, tx)), int(rng.integers(0, ty))) for _ in range(6)]
+        tiles += [(tx // 2, ty // 2), (tx - 1, ty - 1)]          # centre and the ragged corner
+        for (x, y) in tiles:
+            cover = (vis == 1) & (orect[:, 0] <= x) & (x < orect[:, 2]) & (orect[:, 1] <= y) & (y < orect[:, 3])
+            # bit-exact depth-ordered list of the tile
+            cs = np.nonzero(cover)[0]
+            ref = cs[np.lexsort((cs, rec[cs, O.R_DEPTH].astype(np.float32)))]
+            t = vi * tx * ty + y * tx + x
+            lo, hi = r["ranges"][t]
+            got = slots[r["pair_val"][lo:hi] - r0]
+            if (rec[cs, O.R_MARGIN] >= MARGIN_INT).all():
+                assert np.array_equal(got.astype(np.int64), ref), (vi, x, y)
+            # pixels of the tile from the Gaussians covering it
+            xs = np.arange(x * TILE[0], min(W, (x + 1) * TILE[0]))
+            ys = np.arange(y * TILE[1], min(H, (y + 1) * TILE[1]))
+            pix = (ys[:, None] * W + xs[None, :]).reshape(-1)
+            rgb, To, cnt, dm, cm = O.render_records(cover.astype(np.int32), rec, v, pix)
+            o = 3 * vi * W * H
+            g = np.stack([r["img"][o + c * W * H + pix] for c in range(3)])
+            keep = dm >= MARGIN_PIX
+            excl += int((~keep).sum())
+            tot += len(pix)
+            d = np.abs(g - rgb)[:, keep]
+            worst = max(worst, float(d.max(initial=0)))
+            assert d.max(initial=0) <= IMG_TOL, (vi, x, y, float(d.max()))
+    say("pixels", tot, "excluded", excl, "worst", worst)
+    assert excl <= 0.01 * tot
+
+
+def test_fullsize_loss_frozen_and_relocation_properties(run):
+    r = run
+    pool, views = r["pool"], r["views"]
+    V = len(views)
+    n = 3 * W * H
+    d = np.abs(r["img"].astype(np.float64) - r["tgt"].astype(np.float64))
+    l1 = sum(d[i * n:(i + 1) * n].mean() for i in range(V)) / V
+    A = O.window_set(pool.start, pool.expire, NUM_GS, [v.frame for v in views])
+    L, l1_o, _, _ = O.loss_and_grad(np.zeros(0), np.zeros(0), [], pool.params, A)
+    say("loss", r["stats"][3], "=", l1, "+", L)
+    assert abs(r["stats"][3] - (l1 + L)) <= 1e-6 * abs(l1 + L)
+    # frozen slots untouched, no dead optimisable slot left
+    assert np.array_equal(r["params"][:, NUM_GS:], pool.params[:, NUM_GS:])
+    dead = r["params"][10, :NUM_GS][A] < np.float32(np.log(0.005 / 0.995))
+    assert int(dead.sum()) == 0
+
+
+def test_fullsize_gradients_and_step_of_sampled_gaussians(run):
+    r = run
+    sw, pool, views, cfg = r["sw"], r["pool"], r["views"], r["cfg"]
+    V = len(views)
+    P0 = pool.params.astype(np.float64)
+    F = P0.shape[0]
+    rng = np.random.default_rng(12)
+    sample = np.sort(rng.choice(NUM_GS, size=N_SAMPLE, replace=False))
+    g_orc = np.zeros((F, N_SAMPLE))
+    bad = np.zeros(N_SAMPLE, bool)
+    norm = 1.0 / (V * 3.0 * W * H)
+    for vi, v in enumerate(views):
+        vis, rec, orect = O.preprocess(P0, DEG, pool.start, pool.expire, v, *TILE)
+        drec = np.zeros((P0.shape[1], 9))
+        here = []
+        for j, i in enumerate(sample):
+            if vis[i] != 1:
+                continue
+            x0, y0, x1, y1 = orect[i]
+            cover = (vis == 1) & (orect[:, 0] < x1) & (orect[:, 2] > x0) & (orect[:, 1] < y1) & (orect[:, 3] > y0)
+            if (rec[cover, O.R_MARGIN] < MARGIN_INT).any():
+                bad[j] = True
+            xs = np.arange(x0 * TILE[0], min(W, x1 * TILE[0]))
+            ys = np.arange(y0 * TILE[1], min(H, y1 * TILE[1]))
+            pix = (ys[:, None] * W + xs[None, :]).reshape(-1)
+            rgb, To, cnt, dm, cm = O.render_records(cover.astype(np.int32), rec, v, pix)
+            o = 3 * vi * W * H
+            t = np.stack([r["tgt"][o + c * W * H + pix] for c in range(3)]).astype(np.float64)
+            diff = rgb - t
+            if (np.abs(diff) < 1e-5).any() or (dm < MARGIN_DECISION).any() or (cm < MARGIN_DECISION).any():
+                bad[j] = True
+            dl = np.sign(diff) * norm
+            dr = O.blend_backward_pixels(cover.astype(np.int32), rec, v, pix, dl)
+            drec[i] = dr[i]
+            here.append(i)
+        if here:
+            gp = O.preprocess_backward(P0, DEG, v, drec, here)
+            for i in here:
+                g_orc[:, np.searchsorted(sample, i)] += gp[:, i]
+    A = O.window_set(pool.start, pool.expire, NUM_GS, [v.frame for v in views])
+    _, _, _, dreg = O.loss_and_grad(np.zeros(0), np.zeros(0), [], pool.params, A)
+    g_orc += dreg[:, sample]
+    keep = ~bad
+    say("sampled", N_SAMPLE, "excluded", int(bad.sum()))
+    assert keep.sum() >= N_SAMPLE // 2
+    G = r["grads"][:, sample].astype(np.float64)
+    for row in range(F):
+        ok = grad_close(G[row, keep], g_orc[row, keep])
+        assert ok.all(), (row, G[row, keep][~ok][:4], g_orc[row, keep][~ok][:4])
+    assert r["stats"][5] == 0          # nothing relocated: the step's outputs are Adam + SGLD only
+    # Adam + SGLD of the sampled Gaussians from the oracle's own gradients;
+    # coordinates whose gradient is below the relative-tolerance floor may
+    # differ in sign, so there only the step bound |dp| <= lr is checked
+    f32 = lambda x: float(np.float32(x))
+    lr = {k: f32(v_) for k, v_ in O.DEFAULT_LR.items()}
+    ks = sample[keep]
+    Gfull = np.zeros((F, NUM_GS))
+    Gfull[:, ks] = g_orc[:, keep]
+    inA = np.zeros(NUM_GS, bool)
+    inA[ks] = True
+    Z = np.zeros((F, NUM_GS))
+    Pr, _, _ = O.adam_sgld_step(P0[:, :NUM_GS], Gfull, Z, Z, inA, 1, DEG, seed=SEED_STEP, step=0, lr=lr,
+                                betas=(f32(cfg.beta1), f32(cfg.beta2)), eps=f32(cfg.eps),
+                                noise_lr=f32(cfg.noise_lr), k=f32(cfg.noise_k), t0=f32(cfg.noise_t0))
+    Pg = r["params"][:, ks].astype(np.float64)
+    ref = Pr[:, ks]
+    strong = np.abs(g_orc[:, keep]) >= 1e-2 * np.abs(g_orc[:, keep]).max(axis=1, keepdims=True)
+    assert np.allclose(Pg[strong], ref[strong], rtol=2e-6, atol=2e-7)
+    lrr = O.lr_rows(DEG, lr)[:, None] * np.ones((1, len(ks)))
+    step = np.abs(Pg - P0[:, ks])
+    assert np.all(step[3:] <= lrr[3:] * (1 + 1e-5) + 1e-7)
