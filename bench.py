@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--serve-lanes", type=int, default=3)
     ap.add_argument("--serve-max-batch", type=int, default=16)
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run 3 device-to-device copies of this many MiB (HBM counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -80,6 +82,16 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.calibrate_copy_mib:
+        n = args.calibrate_copy_mib << 18
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": 3}), flush=True)
+        return
 
     from paper_2409_07759_amd import swgs
     from paper_2409_07759_amd import synth as S
@@ -204,7 +216,8 @@ def main():
         if dom in ("blend_fwd", "blend_bwd"):
             ach = blend_work[dom] / avg_s / 1e12
             out["roofline"] = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": PEAK_FP32_NONPACKED,
-                               "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_NONPACKED, 4), "traffic": None,
+                               "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_NONPACKED, 4),
+                               "traffic": measured_traffic(dom, tw, th, args.lds_batch),
                                "flops_per_launch": int(blend_work[dom]), "avg_launch_ms": round(avg_s * 1e3, 4)}
         else:
             out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -219,6 +232,26 @@ def main():
         out["cpu_baseline"] = cpu_baseline(S.steady_window_pool(args.num_gs, args.swin, args.sh_degree, st0, seed=0),
                                            views, args)
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic(kernel, tw, th, lds):
+    """HBM bytes per launch of `kernel` measured by rocprofv3 counters
+    (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size), as
+    recorded in profiles/hbm_traffic.json for this workload -- or None when
+    the kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        src = os.path.join(ROOT, "paper_2409_07759_amd", "csrc", "kernels_blend.hip")
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        e = rec["kernels"][kernel]
+        if rec["source_sha256"] != digest or e["config"] != f"{tw}x{th}/lds{lds}":
+            return None
+        return e["bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 RESOLUTIONS = [(640, 480), (1280, 720), (1920, 1080)]
@@ -311,6 +344,18 @@ def run_serving(args, ctx, tile, lds):
         if row["served"]["p99_ms"] and row["plain"]["p99_ms"]:
             row["p99_speedup_vs_plain"] = round(row["plain"]["p99_ms"] / row["served"]["p99_ms"], 3)
         res["rates"][str(int(rate))] = row
+    # saturation: every request queued at once (capacity of each form)
+    _, views = serving_trace(2000.0, 0.5, args.serve_frames, seed=7)
+    sat = {}
+    for k, srv in servers.items():
+        (a, ready, status, batch), st = srv.run(views)
+        ok = int((status == 0).sum())
+        sat[k] = dict(requests=len(views), completed=ok, frames_per_s=round(ok / st["wall_s"], 2),
+                      mean_batch=round(st["mean_batch"], 2), redone=st["redone"])
+        log(f"serve saturation {k}: {sat[k]['frames_per_s']} frames/s over {len(views)} requests, "
+            f"mean batch {sat[k]['mean_batch']}")
+    sat["speedup_vs_plain"] = round(sat["served"]["frames_per_s"] / sat["plain"]["frames_per_s"], 3)
+    res["saturation"] = sat
     for srv in servers.values():
         srv.close()
     return res

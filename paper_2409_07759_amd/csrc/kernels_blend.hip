@@ -258,10 +258,33 @@ __device__ __forceinline__ float row_sum16(float x) {
     return x;
 }
 
+// One exchange step of a transposed reduction: lanes whose `bit` is clear
+// keep the partial sum of a, the others that of c, each adding the partner
+// lane's copy (the partner, selected by CTRL, has the opposite bit).
+template <int CTRL>
+__device__ __forceinline__ float xstep(float a, float c, bool bit) {
+    const float keep = bit ? c : a, send = bit ? a : c;
+    return keep + dpp_f<CTRL, 0xf>(send);
+}
+
+// Row sums of eight values at once: after the xor-1, xor-2 and rotate-4
+// exchanges and a rotate-8 add, lane l of every 16-lane row holds the row
+// sum of v[l & 7] (22 VALU operations instead of 32 for eight separate
+// row sums).
+__device__ __forceinline__ float row_sum16_x8(float v0, float v1, float v2, float v3, float v4, float v5,
+                                              float v6, float v7, int lane) {
+    const bool b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1;
+    const float w0 = xstep<0xB1>(v0, v1, b0), w1 = xstep<0xB1>(v2, v3, b0);
+    const float w2 = xstep<0xB1>(v4, v5, b0), w3 = xstep<0xB1>(v6, v7, b0);
+    const float x0 = xstep<0x4E>(w0, w1, b1), x1 = xstep<0x4E>(w2, w3, b1);
+    const float y = xstep<0x124>(x0, x1, b2);
+    return y + dpp_f<0x128, 0xf>(y);
+}
+
 // Backward batches are BB splats; per splat each wave reduces its 9
-// gradient terms to one value per 16-lane row (4 DPP adds each) and the four
-// row leaders store them to LDS, so a splat costs 36 DPP adds and 3 LDS
-// stores per wave instead of a full 64-lane reduction per term.
+// gradient terms to one value per 16-lane row (a transposed reduction for
+// eight of them, a plain row sum for the ninth) and lanes 0-8 of each row
+// store the nine sums to LDS.
 constexpr int kTerm = 12;                 // 9 terms padded to 3 x float4
 
 template <int TW, int TH, int BATCH>
@@ -316,7 +339,7 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     const float bg0 = V.bg[0], bg1 = V.bg[1], bg2 = V.bg[2];
     float U0 = 0.0f, U1 = 0.0f, U2 = 0.0f, Rr = 1.0f;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const bool row_leader = (lane & 15) == 15;
+    const int r16 = lane & 15;
     const int prow = wave * 4 + (lane >> 4);
 
     for (uint32_t b_end = nmax; b_end > 0;) {
@@ -357,19 +380,14 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             U1 = contrib ? fmaf(c.y, alpha, om * U1) : U1;
             U2 = contrib ? fmaf(c.z, alpha, om * U2) : U2;
             Rr = contrib ? Rr * om : Rr;
+            float *pk = reinterpret_cast<float *>(&part[k][prow][0]);
             if (__ballot(contrib) != 0) {
-                v0 = row_sum16(v0); v1 = row_sum16(v1); v2 = row_sum16(v2);
-                v3 = row_sum16(v3); v4 = row_sum16(v4); v5 = row_sum16(v5);
-                v6 = row_sum16(v6); v7 = row_sum16(v7); v8 = row_sum16(v8);
-                if (row_leader) {
-                    part[k][prow][0] = make_float4(v0, v1, v2, v3);
-                    part[k][prow][1] = make_float4(v4, v5, v6, v7);
-                    part[k][prow][2] = make_float4(v8, 0.0f, 0.0f, 0.0f);
-                }
-            } else if (row_leader) {
-                part[k][prow][0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                part[k][prow][1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                part[k][prow][2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                const float y = row_sum16_x8(v0, v1, v2, v3, v4, v5, v6, v7, lane);
+                const float s8 = row_sum16(v8);
+                if (r16 < 8) pk[r16] = y;
+                else if (r16 == 8) pk[8] = s8;
+            } else if (r16 < 9) {
+                pk[r16] = 0.0f;
             }
         }
         __syncthreads();
@@ -416,14 +434,13 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     }
 }
 
-__global__ void __launch_bounds__(256)
-k_loss_reduce(const double *__restrict__ part, int nparts, double inv_3p, double *__restrict__ stats) {
+// Window L1 sum: per-tile partials (written by the forward epilogue) are
+// reduced in two fixed-order levels, kLossBlocks contiguous chunks and then
+// their kLossBlocks sums, so the result does not depend on scheduling.
+constexpr int kLossBlocks = 256;
+
+__device__ __forceinline__ void block_sum2(double &a, double &b) {
     __shared__ double sa[256], sb[256];
-    double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += 256) {
-        a += part[2 * (size_t)i];
-        b += part[2 * (size_t)i + 1];
-    }
     sa[threadIdx.x] = a;
     sb[threadIdx.x] = b;
     __syncthreads();
@@ -434,9 +451,33 @@ k_loss_reduce(const double *__restrict__ part, int nparts, double inv_3p, double
         }
         __syncthreads();
     }
+    a = sa[0];
+    b = sb[0];
+}
+
+__global__ void __launch_bounds__(256)
+k_loss_partial(const double *__restrict__ part, int nparts, double *__restrict__ sums) {
+    const int chunk = (nparts + kLossBlocks - 1) / kLossBlocks;
+    const int lo = blockIdx.x * chunk, hi = min(nparts, lo + chunk);
+    double a = 0.0, b = 0.0;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += 256) {
+        a += part[2 * (size_t)i];
+        b += part[2 * (size_t)i + 1];
+    }
+    block_sum2(a, b);
     if (threadIdx.x == 0) {
-        stats[0] = sa[0];
-        stats[1] = sb[0] * inv_3p;
+        sums[2 * blockIdx.x] = a;
+        sums[2 * blockIdx.x + 1] = b;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_loss_final(const double *__restrict__ sums, double inv_3p, double *__restrict__ stats) {
+    double a = sums[2 * threadIdx.x], b = sums[2 * threadIdx.x + 1];
+    block_sum2(a, b);
+    if (threadIdx.x == 0) {
+        stats[0] = a;
+        stats[1] = b * inv_3p;
     }
 }
 
@@ -493,8 +534,11 @@ void launch_loss_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, const sw
                         bool with_reg) {
     (void)cfg;
     (void)with_reg;
-    hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, s, wsp<double>(ws, p, WB_LOSS_PART), (int)p.T,
-                       1.0 / (3.0 * (double)p.P), wsp<double>(ws, p, WB_STATS));
+    double *part = wsp<double>(ws, p, WB_LOSS_PART);
+    double *sums = part + 2 * (size_t)p.T;
+    hipLaunchKernelGGL(k_loss_partial, dim3(kLossBlocks), dim3(256), 0, s, part, (int)p.T, sums);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, sums, 1.0 / (3.0 * (double)p.P),
+                       wsp<double>(ws, p, WB_STATS));
 }
 
 }  // namespace swgs

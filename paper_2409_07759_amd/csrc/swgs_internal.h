@@ -17,9 +17,6 @@ namespace swgs {
 constexpr int kMaxShDegree = 3;
 constexpr int kMaxRows = 11 + 3 * 16;      // F at SH degree 3
 constexpr int kGateChunk = 2048;           // slots per gating block
-constexpr int kSortBlocks = 1024;          // fixed grid of the radix-sort passes
-constexpr int kRadixBits = 8;
-constexpr int kRadix = 1 << kRadixBits;
 constexpr int kSplatFloats = 12;           // floats per splat record
 
 inline int rows_for(int sh_degree) { return 11 + 3 * (sh_degree + 1) * (sh_degree + 1); }
@@ -72,8 +69,8 @@ enum WsBuf {
     WB_RECT, WB_SPLAT, WB_PAIR_KEY, WB_PAIR_VAL, WB_PAIR_COUNT, WB_TILE_RANGE, WB_T_FINAL,
     WB_DLDC, WB_REC_GRAD,
     // internal
-    WB_GATE_BLK, WB_POS_OF, WB_REC_IDX, WB_KEY_ALT, WB_IDX_ALT, WB_PAIR_KEY_ALT, WB_PAIR_VAL_ALT,
-    WB_PAIR_OFFSET, WB_SORT_HIST, WB_SORT_TOTAL, WB_LAST, WB_LOSS_PART, WB_STATS, WB_STEP,
+    WB_GATE_BLK, WB_POS_OF, WB_PAIR_KEY_ALT, WB_PAIR_VAL_ALT, WB_TILE_HIST, WB_BIG_TILES,
+    WB_PAIR_OFFSET, WB_SORT_TOTAL, WB_LAST, WB_LOSS_PART, WB_STATS, WB_STEP,
     WB_VIEWS, WB_GROUPS, WB_GROUP_VIEWS,
     WB_RELOC_W, WB_RELOC_FLAG, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_CNT, WB_RELOC_SCAN, WB_REG_PART, WB_COUNTERS, WB_CFLAGS,
     WB_COUNT
@@ -101,7 +98,6 @@ struct swgs_plan {
     uint32_t n_A = 0;                             // |A|
     uint32_t list_A_base = 0;
     int64_t R = 0, P = 0, T = 0;
-    int depth_key_bits = 32, tile_key_bits = 1;
     int loss_blocks = 0;
     swgs::Layout lay;
     // graph mode
@@ -135,16 +131,17 @@ void launch_count_live(hipStream_t s, const int32_t *start, const int32_t *expir
 
 // Preprocess and binning (kernels_preprocess.hip)
 void launch_preprocess(hipStream_t s, const swgs_plan &p, uint8_t *ws, int view_lo, int view_hi);
-void launch_pair_offsets(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi);
-void launch_emit_pairs(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi);
-void launch_tile_ranges(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t tile_lo, uint32_t tile_hi);
+// pairs per tile of records [rec_lo, rec_hi) over tiles [tile_lo, tile_hi):
+// counts, exclusive scan (pair total -> pair_count[0], overflow -> [1]),
+// tile ranges clamped to the capacity and write cursors
+void launch_bin_count(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi,
+                      uint32_t tile_lo, uint32_t tile_hi);
+// (depth key, record) of every pair written at its tile's cursor
+void launch_bin_emit(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi);
 
-// Radix sort (kernels_sort.hip): stable LSD sort of (key, val) uint32 pairs,
-// n given on the device (*d_n, clamped to cap) over bits [0, bits).
-// On return the sorted data is in (keys, vals); alt buffers are scratch.
-void radix_sort_pairs(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
-                      uint32_t *vals_alt, const uint32_t *d_n, uint32_t n_fixed, uint32_t cap,
-                      int bits, uint32_t *hist, uint32_t *totals);
+// Per-tile sort and scans (kernels_sort.hip): pairs of tiles
+// [tile_lo, tile_hi) ordered by (depth key, record) inside each tile.
+void launch_tile_sort(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t tile_lo, uint32_t tile_hi);
 void exclusive_scan_u32(hipStream_t s, const uint32_t *in, uint32_t *out, uint32_t n,
                         uint32_t *total_out, uint32_t *scratch);
 // same over in[idx[i]]

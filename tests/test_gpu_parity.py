@@ -181,20 +181,58 @@ def test_sorted_pairs_and_ranges_bit_exact(sw, ctx, tile):
     ref_tiles = np.concatenate(ref_tiles)
     ref_slots = np.concatenate(ref_slots)
     say("pairs", K, "flagged", flagged)
+    # tiles own contiguous, consecutive ranges; the tile of each pair follows
+    assert ranges[0, 0] == 0 and np.array_equal(ranges[1:, 0], ranges[:-1, 1]) and ranges[-1, 1] == K
+    tile_of = np.repeat(np.arange(len(ranges)), ranges[:, 1] - ranges[:, 0])
     if flagged == 0:
         assert K == len(ref_tiles)
-        assert np.array_equal(keys.astype(np.int64), ref_tiles)
+        assert np.array_equal(tile_of, ref_tiles)
         assert np.array_equal(rec_slot[vals], ref_slots)
     else:
         # flagged records may legitimately differ; everything else must not
         assert abs(K - len(ref_tiles)) <= 8 * flagged
-    # depth order: records by (FP32 depth, record)
-    order = host(pl.buffer(sw.SWGS_BUF_DEPTH_ORDER))[:pl.n_records]
+    # pair keys are the records' FP32 depth bits, ascending inside each tile
+    # with ties by record
     splat = host(pl.buffer(sw.SWGS_BUF_SPLAT, torch.float32)).reshape(-1, 12)
-    tc = host(pl.buffer(sw.SWGS_BUF_TILE_COUNT))
-    dk = np.where(tc > 0, splat[:, 11].view(np.uint32), np.uint32(0xFFFFFFFF)).astype(np.uint64)
-    ref = np.lexsort((np.arange(pl.n_records), dk))
-    assert np.array_equal(order, ref)
+    assert np.array_equal(keys, splat[vals, 11].view(np.uint32))
+    order = np.lexsort((vals, keys, tile_of))
+    assert np.array_equal(order, np.arange(K))
+
+
+def test_dense_tiles_take_the_merge_path(sw, ctx):
+    """Tiles holding more pairs than one LDS sort run (4096) are sorted as
+    runs plus merge passes; their lists and pixels still match the oracle."""
+    say("dense tiles")
+    pool, views = tiny(n=60000, width=40, height=24, frames=(0,), cams=2)
+    dp, pl = plan_for(sw, ctx, pool, views, tile=(16, 16))
+    img = host(pl.forward())
+    K = int(host(pl.buffer(sw.SWGS_BUF_PAIR_COUNT))[0])
+    vals = host(pl.buffer(sw.SWGS_BUF_PAIR_VAL))[:K]
+    ranges = host(pl.buffer(sw.SWGS_BUF_TILE_RANGE)).reshape(-1, 2)
+    rvb = host(pl.buffer(sw.SWGS_BUF_RECORD_VIEW_BASE))
+    recs = records_of(sw, pl, pool, views)
+    counts = ranges[:, 1] - ranges[:, 0]
+    say("largest tile", int(counts.max()))
+    assert counts.max() > 3 * 4096
+    rec_slot = np.zeros(pl.n_records, np.int64)
+    for vi, (slots, *_r) in enumerate(recs):
+        rec_slot[rvb[vi]:rvb[vi] + len(slots)] = slots
+    tbase, o = 0, 0
+    for v in views:
+        vis, rec, rect = O.preprocess(pool.params, 0, pool.start, pool.expire, v, 16, 16)
+        t, s_, rg = O.tile_pairs(vis, rec, rect, v, 16, 16)
+        act = O.active(pool.start, pool.expire, v.frame)
+        nt = len(rg)
+        if not ((rec[:, O.R_MARGIN] < MARGIN_INT) & act).any():
+            for k in range(nt):
+                lo, hi = ranges[tbase + k]
+                assert np.array_equal(rec_slot[vals[lo:hi]], s_[rg[k, 0]:rg[k, 1]]), k
+        n = v.width * v.height
+        rgb, To, cnt, dm, cm = O.render_view(pool.params, 0, pool.start, pool.expire, v)
+        keep = dm >= MARGIN_PIX
+        assert np.abs(img[o:o + 3 * n].reshape(3, n) - rgb)[:, keep].max(initial=0) <= IMG_TOL
+        tbase += nt
+        o += 3 * n
 
 
 # ----------------------------------------------------------- a5 forward blend

@@ -1,0 +1,215 @@
+"""Uneven window in one captured graph, against the oracle.
+
+Workload: a 500k-slot pool over a 30-frame window: 40k Gaussians live in
+every frame, 460k start at U{0..29} and live U{1..27} frames, so the live
+sets grow from ~55k to ~255k per frame; SH degree 3; 6 cameras per frame,
+cameras 0/2/4 at 960x720 and 1/3/5 at 1352x1014: 180 views rendered,
+differentiated and stepped as one hipGraph window step, with the tile shape
+and LDS batch picked by the autotuner among {8x8, 16x16, 32x8} x {128, 256}.
+
+Checked against the FP64 oracle:
+ - per-frame live counts and lists (bit-exact; the counts are printed);
+ - pixels of sampled tiles of both resolutions (1e-5);
+ - the gradient of 64 parameters (16 random Gaussians x 4 random parameter
+   rows) against a central finite difference of the oracle's window loss,
+   eps = 1e-4 in FP64.  Only the pixels a perturbed Gaussian can reach (its
+   tiles at theta and theta +- eps) are re-rendered, from the Gaussians whose
+   tiles overlap them; a stencil is rejected when any such pixel changes its
+   contributor count, comes near the 0.99 clamp or changes the sign of its
+   L1 residual between theta + eps and theta - eps."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2409_07759_amd import synth as S
+from scenes import IMG_TOL, MARGIN_PIX
+
+pytestmark = pytest.mark.gpu
+
+N_TOTAL, N_BASE, W_FRAMES, DEG = 500_000, 40_000, 30, 3
+SIZES = [(960, 720), (1352, 1014)] * 3
+EPS = 1e-4
+CANDIDATES = [((8, 8), 128), ((8, 8), 256), ((16, 16), 128), ((16, 16), 256), ((32, 8), 128), ((32, 8), 256)]
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def run():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_07759_amd import autotune
+    from paper_2409_07759_amd import swgs as sw
+    pool = S.uneven_window_pool(N_TOTAL, N_BASE, W_FRAMES, DEG, 5)
+    views = S.ring_views(list(range(W_FRAMES)), 6, 0, 0, sizes=SIZES)
+    tgt = S.random_images(views, 9)
+    say("uneven window:", len(views), "views")
+    ctx = sw.Context(0)
+    dp = sw.Pool.from_synth(pool)
+    (tw, th), lds, table = autotune.tune(ctx, dp, views, reps=1, use_cache=False, candidates=CANDIDATES, log=say)
+    say("autotuned", tw, th, lds, table)
+    plan = sw.Plan(ctx, dp, views, tile=(tw, th), lds_batch=lds, headroom=1.5)
+    cfg = sw.step_cfg(mode=sw.SWGS_MODE_GRAPH, window_start=0, relocate_period=1)
+    img = plan.image_buffer()
+    stats = torch.zeros(8, dtype=torch.float64, device="cuda")
+    plan.window_step(cfg, torch.as_tensor(tgt, device="cuda"), 1, 0, 3, images=img, stats=stats)
+    out = dict(pool=pool, views=views, tgt=tgt, tile=(tw, th), table=table, img=host(img), stats=host(stats),
+               grads=host(dp.grads), counts=host(plan.buffer(sw.SWGS_BUF_ACTIVE_COUNT)),
+               lists=host(plan.buffer(sw.SWGS_BUF_ACTIVE_LIST)), n_groups=plan.n_groups)
+    say("step done; stats", out["stats"])
+    plan.close()
+    del dp
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def test_uneven_counts_lists_and_autotune(run):
+    pool = run["pool"]
+    counts = run["counts"][:run["n_groups"]]
+    say("live per frame", counts.tolist())
+    assert run["n_groups"] == W_FRAMES and len(run["table"]) == len(CANDIDATES)
+    assert 40_000 <= counts.min() and counts.max() <= 260_000 and counts.max() > 4 * counts.min()
+    base = 0
+    for f in range(W_FRAMES):
+        ref = np.nonzero(O.active(pool.start, pool.expire, f))[0]
+        assert counts[f] == len(ref)
+        assert np.array_equal(run["lists"][base:base + counts[f]].astype(np.int64), ref), f
+        base += int(counts[f])
+
+
+def view_offsets(views):
+    off, o = [], 0
+    for v in views:
+        off.append(o)
+        o += 3 * v.width * v.height
+    return off
+
+
+def test_uneven_sampled_tiles_match_oracle(run):
+    pool, views, (tw, th) = run["pool"], run["views"], run["tile"]
+    P0 = pool.params.astype(np.float64)
+    off = view_offsets(views)
+    rng = np.random.default_rng(13)
+    excl = tot = 0
+    for vi in (0, 1, 89, 94, 178, 179):
+        v = views[vi]
+        vis, rec, rect = O.preprocess(P0, DEG, pool.start, pool.expire, v, tw, th)
+        ntx, nty = (v.width + tw - 1) // tw, (v.height + th - 1) // th
+        for _ in range(4):
+            x, y = int(rng.integers(ntx // 4, 3 * ntx // 4)), int(rng.integers(nty // 4, 3 * nty // 4))
+            cover = (vis == 1) & (rect[:, 0] <= x) & (x < rect[:, 2]) & (rect[:, 1] <= y) & (y < rect[:, 3])
+            xs = np.arange(x * tw, min(v.width, (x + 1) * tw))
+            ys = np.arange(y * th, min(v.height, (y + 1) * th))
+            pix = (ys[:, None] * v.width + xs[None, :]).reshape(-1)
+            rgb, To, cnt, dm, cm = O.render_records(cover.astype(np.int32), rec, v, pix)
+            g = np.stack([run["img"][off[vi] + c * v.width * v.height + pix] for c in range(3)])
+            keep = dm >= MARGIN_PIX
+            excl += int((~keep).sum())
+            tot += len(pix)
+            assert np.abs(g - rgb)[:, keep].max(initial=0) <= IMG_TOL, (vi, x, y)
+    say("pixels", tot, "excluded", excl)
+    assert excl <= 0.01 * tot
+
+
+def test_uneven_gradient_matches_central_fd(run):
+    pool, views, tgt, (tw, th) = run["pool"], run["views"], run["tgt"], run["tile"]
+    P0 = pool.params.astype(np.float64)
+    F = P0.shape[0]
+    V = len(views)
+    off = view_offsets(views)
+    A = O.window_set(pool.start, pool.expire, N_TOTAL, list(range(W_FRAMES)))
+    nA = int(A.sum())
+    rng = np.random.default_rng(14)
+    slots = np.sort(rng.choice(np.nonzero(A)[0], size=16, replace=False))
+    rows = [np.sort(rng.choice(F, size=4, replace=False)) for _ in slots]
+    fd = np.zeros((16, 4))
+    bad = np.zeros((16, 4), bool)
+    # regulariser part: separable, so the oracle's regulariser on the one slot, over |A|
+    for a, i in enumerate(slots):
+        for b, r in enumerate(rows[a]):
+            vals = []
+            for sgn in (1.0, -1.0):
+                p1 = P0[:, [i]].copy()
+                p1[r, 0] += sgn * EPS
+                L1, _, _, _ = O.loss_and_grad(np.zeros(0), np.zeros(0), [], p1, np.ones(1, bool))
+                vals.append(L1)
+            fd[a, b] += (vals[0] - vals[1]) / (2 * EPS) / nA
+    for vi, v in enumerate(views):
+        live = O.active(pool.start[slots], pool.expire[slots], v.frame)
+        if not live.any():
+            continue
+        vis, rec, rect = O.preprocess(P0, DEG, pool.start, pool.expire, v, tw, th)
+        norm = 1.0 / (V * 3.0 * v.width * v.height)
+        HW = v.width * v.height
+        for a in np.nonzero(live)[0]:
+            i = slots[a]
+            for b, r in enumerate(rows[a]):
+                recs, rects, viss = [], [], []
+                for sgn in (1.0, -1.0):
+                    p1 = P0[:, [i]].copy()
+                    p1[r, 0] += sgn * EPS
+                    vs1, rc1, rt1 = O.preprocess(p1, DEG, pool.start[[i]], pool.expire[[i]], v, tw, th)
+                    viss.append(vs1[0])
+                    recs.append(rc1[0])
+                    rects.append(rt1[0])
+                boxes = [rect[i]] + [rects[k] for k in range(2) if viss[k] == 1]
+                if vis[i] != 1:
+                    boxes = boxes[1:]
+                if not boxes:
+                    continue
+                x0 = min(bx[0] for bx in boxes)
+                y0 = min(bx[1] for bx in boxes)
+                x1 = max(bx[2] for bx in boxes)
+                y1 = max(bx[3] for bx in boxes)
+                if x1 <= x0 or y1 <= y0:
+                    continue
+                others = (vis == 1) & (rect[:, 0] < x1) & (rect[:, 2] > x0) & (rect[:, 1] < y1) & (rect[:, 3] > y0)
+                others[i] = False
+                idx = np.sort(np.concatenate([np.nonzero(others)[0], [i]]))
+                j = int(np.searchsorted(idx, i))
+                xs = np.arange(x0 * tw, min(v.width, x1 * tw))
+                ys = np.arange(y0 * th, min(v.height, y1 * th))
+                pix = (ys[:, None] * v.width + xs[None, :]).reshape(-1)
+                t = np.stack([tgt[off[vi] + c * HW + pix] for c in range(3)]).astype(np.float64)
+                res = []
+                for k in range(2):
+                    sub = rec[idx].copy()
+                    sv = np.ones(len(idx), np.int32)
+                    sub[j] = recs[k]
+                    sv[j] = viss[k]
+                    rgb, To, cnt, dm, cm = O.render_records(sv, sub, v, pix)
+                    res.append((rgb - t, cnt, cm))
+                (d_p, c_p, cm_p), (d_m, c_m, cm_m) = res
+                if (np.any(c_p != c_m) or np.any(np.sign(d_p) != np.sign(d_m)) or
+                        min(cm_p.min(initial=np.inf), cm_m.min(initial=np.inf)) < 1e-4):
+                    bad[a, b] = True
+                fd[a, b] += (np.abs(d_p).sum() - np.abs(d_m).sum()) * norm / (2 * EPS)
+    G = run["grads"]
+    got = np.array([[G[r, i] for r in rows[a]] for a, i in enumerate(slots)], np.float64)
+    keep = ~bad
+    say("FD samples", keep.sum(), "of 64 kept")
+    assert keep.sum() >= 32
+    # per-sample relative tolerance with a floor at 1e-2 of the largest FD
+    # magnitude among parameters of the same kind
+    kind = np.array([[0 if r < 3 else 1 if r < 6 else 2 if r < 10 else 3 if r == 10 else 4 for r in rr]
+                     for rr in rows])
+    for k in range(5):
+        m = keep & (kind == k)
+        if not m.any():
+            continue
+        floor = 1e-2 * np.abs(fd[m]).max()
+        err = np.abs(got[m] - fd[m])
+        tol = 1e-3 * np.maximum(np.abs(fd[m]), floor) + 1e-12
+        assert np.all(err <= tol), (k, got[m][err > tol][:4], fd[m][err > tol][:4])
