@@ -183,14 +183,16 @@ swgs_status swgs_render_backward(swgs_context *ctx, swgs_plan *plan, void *works
                                  int32_t add_regulariser, const swgs_step_cfg *cfg);
 
 /* ------------------------------------------------------------- step
- * Optimiser hyper-parameters (Sec. 8.1 gives lambda_o, lambda_s, noise_lr;
- * the rest are readings of the 3DGS / 3DGS-MCMC defaults). */
+ * Optimiser and loss hyper-parameters (Sec. 8.1 gives lambda_o, lambda_s,
+ * noise_lr; the loss follows 3DGS-MCMC's practice, Sec. 4.4; the rest are
+ * readings of the 3DGS / 3DGS-MCMC defaults). */
 struct swgs_step_cfg {
     size_t struct_size;        /* sizeof(swgs_step_cfg) */
     float lr_mean, lr_scale, lr_quat, lr_logit, lr_sh_dc, lr_sh_rest;
     float beta1, beta2, eps;
     float noise_lr, noise_k, noise_t0;     /* SGLD: noise_lr lr_mean sigmoid(-k (o - t0)) Sigma eta */
     float lambda_opacity, lambda_scale;    /* regulariser weights */
+    float lambda_dssim;                    /* image term (1 - l) L1 + l (1 - SSIM), in [0, 1] (default 0.2) */
     float grad_scale_base;                 /* adaptive mean-gradient scaling base (0 = off) */
     int32_t window_start;                  /* st of the window [st, st + swin) */
     int32_t relocate_period;               /* relocate when step % period == 0 (0 = never) */
@@ -220,13 +222,18 @@ swgs_status swgs_relocate(swgs_context *ctx, swgs_plan *plan, void *workspace, s
 
 /* One window step (Algorithm 1's inner iteration over all views of the
  * window at once): forward with the fused L1 gradient against `targets`,
- * backward with the regulariser, Adam + scaling + SGLD, and relocation when
+ * the D-SSIM term and its gradient when cfg->lambda_dssim > 0 (SSIM of Wang
+ * et al. 2004: 11x11 Gaussian window, sigma 1.5, zero padding,
+ * C1 = 0.01^2, C2 = 0.03^2, averaged over pixels and channels), backward
+ * with the regulariser, Adam + scaling + SGLD, and relocation when
  * step % relocate_period == 0.  cfg->mode selects the launch structure:
  * PLAIN = one launch sequence per view (the per-frame baseline), BATCHED =
  * one launch per kernel over all views, GRAPH = the batched sequence
  * captured once into a hipGraph and replayed (step numbers advance on the
- * device; the first call with a plan captures).  `images` may be NULL.
- * stats (device double[8]): [0] L1 term, [1] MSE, [2] regulariser,
+ * device; the first call with a plan captures).  `images` may be NULL (the
+ * renders then stay in the workspace).
+ * stats (device double[8]): [0] image term
+ * (1/V) sum_v [(1 - l) mean|C - GT| + l (1 - SSIM_v)], [1] MSE, [2] regulariser,
  * [3] total loss, [4] pairs, [5] dead slots relocated, [6] overflow flag,
  * [7] |A|. */
 swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *plan, void *workspace, size_t ws_bytes,
@@ -240,14 +247,14 @@ swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *plan, void *workspace
  * (pixel, list entry) pairs they evaluate.  swgs_plan_set_timing
  * synchronises, resets the records and switches timing on (on != 0) or off.
  * swgs_plan_timing synchronises, returns per class the summed kernel time
- * (ms[8], host) and the number of bracketed launches (launches[8], host),
+ * (ms[9], host) and the number of bracketed launches (launches[9], host),
  * and, if evals (host uint64[3]) is not NULL, the (pixel, list entry) pairs
  * evaluated by the forward [0] and the backward [1] blend and the pairs the
  * forward blended [2] (the backward differentiates exactly those); then
  * resets.  Classes: 0 gating,
- * 1 preprocess, 2 depth sort + pair emission + tile sort + ranges,
+ * 1 preprocess, 2 binning + per-tile depth sort,
  * 3 forward blend, 4 backward blend, 5 backward preprocess, 6 Adam + SGLD,
- * 7 relocation. */
+ * 7 relocation, 8 D-SSIM (forward and gradient). */
 swgs_status swgs_plan_set_timing(swgs_context *ctx, swgs_plan *plan, void *workspace, size_t ws_bytes,
                                  int32_t on);
 swgs_status swgs_plan_timing(swgs_context *ctx, swgs_plan *plan, void *workspace, size_t ws_bytes,

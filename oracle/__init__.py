@@ -238,19 +238,25 @@ def window_set(start, expire, num_gs, frames):
     return m
 
 
-def loss_and_grad(images, targets, views, params, in_A, lam_o=2e-2, lam_s=1e-2):
-    """Window loss (Algorithm 1; regulariser weights from Sec. 8.1):
-    L = (1/V) sum_v mean|C - GT| + lam_o mean_A sigmoid(logit)
-        + lam_s mean_A sum_j exp(s_j).
-    Returns (L, l1 part, dL/dimages, dL/dparams of the regulariser)."""
+def loss_and_grad(images, targets, views, params, in_A, lam_o=2e-2, lam_s=1e-2, lam_dssim=0.0):
+    """Window loss (Algorithm 1; image term after 3DGS-MCMC, Sec. 4.4;
+    regulariser weights from Sec. 8.1):
+    L = (1/V) sum_v [(1 - lam_dssim) mean|C - GT| + lam_dssim (1 - SSIM(C, GT))]
+        + lam_o mean_A sigmoid(logit) + lam_s mean_A sum_j exp(s_j).
+    Returns (L, image part, dL/dimages, dL/dparams of the regulariser)."""
     V = len(views)
     g = np.zeros(images.shape[0])
     l1, o = 0.0, 0
     for v in views:
         n = 3 * v.width * v.height
         d = images[o:o + n].astype(np.float64) - targets[o:o + n].astype(np.float64)
-        l1 += np.abs(d).mean() / V
-        g[o:o + n] = np.sign(d) / (V * n)
+        l1 += (1.0 - lam_dssim) * np.abs(d).mean() / V
+        g[o:o + n] = (1.0 - lam_dssim) * np.sign(d) / (V * n)
+        if lam_dssim != 0.0:
+            shape = (3, v.height, v.width)
+            sv, gs = ssim(images[o:o + n].reshape(shape), targets[o:o + n].reshape(shape))
+            l1 += lam_dssim * (1.0 - sv) / V
+            g[o:o + n] -= lam_dssim * gs.reshape(-1) / V
         o += n
     P = _f64(params)
     dreg = np.zeros_like(P)
@@ -264,6 +270,87 @@ def loss_and_grad(images, targets, views, params, in_A, lam_o=2e-2, lam_s=1e-2):
         dreg[10, idx] = lam_o * sig * (1.0 - sig) / nA
         dreg[3:6, idx] = lam_s * es / nA
     return l1 + reg, l1, g, dreg
+
+
+# ------------------------------------------------------------ D-SSIM
+# The loss follows 3DGS-MCMC's practice (Sec. 4.4): an image term
+# (1 - lam) L1 + lam (1 - SSIM) with lam = 0.2.  SSIM is the structural
+# similarity index of Wang, Bovik, Sheikh and Simoncelli (2004) with their
+# constants C1 = (0.01 L)^2, C2 = (0.03 L)^2, L = 1, an 11x11 Gaussian window
+# of standard deviation 1.5 normalised to sum 1, zero padding outside the
+# image, averaged over pixels and colour channels.
+SSIM_C1 = 0.01 ** 2
+SSIM_C2 = 0.03 ** 2
+
+
+def ssim_window(size: int = 11, sigma: float = 1.5):
+    """w[i, j] = g[i] g[j], g[k] proportional to exp(-(k - size//2)^2 / (2 sigma^2)), sum 1."""
+    k = np.arange(size, dtype=np.float64) - size // 2
+    g = np.exp(-k * k / (2.0 * sigma * sigma))
+    g /= g.sum()
+    return np.outer(g, g)
+
+
+def window_sum(img, w):
+    """out(p) = sum_o w(o) img(p + o - r), r = size // 2, zero outside the image."""
+    img = _f64(img)
+    H, W = img.shape
+    r = w.shape[0] // 2
+    pad = np.zeros((H + 2 * r, W + 2 * r))
+    pad[r:r + H, r:r + W] = img
+    out = np.zeros((H, W))
+    for dy in range(w.shape[0]):
+        for dx in range(w.shape[1]):
+            out += w[dy, dx] * pad[dy:dy + H, dx:dx + W]
+    return out
+
+
+def window_sum_adjoint(g, w):
+    """Adjoint of window_sum: in(q) = sum_p w(q - p + r) g(p) over pixels p of the image."""
+    g = _f64(g)
+    H, W = g.shape
+    r = w.shape[0] // 2
+    pad = np.zeros((H + 2 * r, W + 2 * r))
+    pad[r:r + H, r:r + W] = g
+    out = np.zeros((H, W))
+    for dy in range(w.shape[0]):
+        for dx in range(w.shape[1]):
+            out += w[dy, dx] * pad[2 * r - dy:2 * r - dy + H, 2 * r - dx:2 * r - dx + W]
+    return out
+
+
+def ssim_map(x, y, w=None):
+    """Per-pixel SSIM of two single-channel images [H, W] and the partial
+    derivatives of the map with respect to the window mean of x, the window
+    mean of x^2 and the window mean of x y."""
+    w = ssim_window() if w is None else w
+    x, y = _f64(x), _f64(y)
+    mx, my = window_sum(x, w), window_sum(y, w)
+    exx, eyy, exy = window_sum(x * x, w), window_sum(y * y, w), window_sum(x * y, w)
+    A = 2.0 * mx * my + SSIM_C1
+    B = 2.0 * (exy - mx * my) + SSIM_C2
+    C = mx * mx + my * my + SSIM_C1
+    D = (exx - mx * mx) + (eyy - my * my) + SSIM_C2
+    S = A * B / (C * D)
+    dS_dmx = 2.0 * my * (B - A) / (C * D) - 2.0 * mx * S / C + 2.0 * mx * S / D
+    dS_dexx = -S / D
+    dS_dexy = 2.0 * A / (C * D)
+    return S, dS_dmx, dS_dexx, dS_dexy
+
+
+def ssim(x, y):
+    """Mean SSIM of two planar images [3, H, W] over pixels and channels, and
+    its gradient with respect to x (chain rule through the window sums)."""
+    w = ssim_window()
+    x, y = _f64(x), _f64(y)
+    n = x.size
+    total, grad = 0.0, np.zeros_like(x)
+    for c in range(x.shape[0]):
+        S, a, b, e = ssim_map(x[c], y[c], w)
+        total += S.sum()
+        grad[c] = (window_sum_adjoint(a, w) + 2.0 * x[c] * window_sum_adjoint(b, w)
+                   + y[c] * window_sum_adjoint(e, w))
+    return total / n, grad / n
 
 
 def psnr(images, targets):

@@ -128,11 +128,15 @@ void swgs::compute_layout(const LayoutDims &d, Layout &lay, size_t &consts_bytes
     sz[WB_REG_PART] = 2 * ((nA + 255) / 256 + 1) * 8;
     sz[WB_COUNTERS] = 256 * 4 * 8;   // 256 slots x {fwd evals, bwd evals, blended, pad}
     sz[WB_CFLAGS] = R + 16;
+    sz[WB_SSIM_PART] = 9 * P * 4;                     // dS/d(mu_x, E[x^2], E[xy]) per pixel and channel
+    sz[WB_SSIM_SUM] = (3 * d.T16 + 256) * 8;          // per (SSIM tile, channel), then 256 chunk sums
+    sz[WB_IMAGE] = 3 * P * 4;                         // renders when the caller passes no image buffer
     if (d.forward_only) {
         // serving: no gating (the live lists are resident), no gradients,
         // no loss, no step; pair buffers may live outside (ext)
         for (int b : {WB_ACTIVE_LIST, WB_GATE_BLK, WB_POS_OF, WB_DLDC, WB_REC_GRAD, WB_LOSS_PART, WB_RELOC_W,
-                      WB_RELOC_FLAG, WB_RELOC_CNT, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_SCAN, WB_REG_PART})
+                      WB_RELOC_FLAG, WB_RELOC_CNT, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_SCAN, WB_REG_PART,
+                      WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE})
             sz[b] = 0;
     }
     // order: constant block, then the rest
@@ -169,13 +173,14 @@ void build_layout(swgs_plan &p) {
     d.nA = p.n_A;
     d.n_list = p.n_A;
     for (auto &g : p.groups) d.n_list += g.n_live;
+    d.T16 = (size_t)p.T16;
     d.forward_only = p.forward_only;
     compute_layout(d, p.lay, p.consts_bytes);
 }
 
 
 // kernel classes timed with events when a plan's timing is on
-enum { TK_GATE = 0, TK_PREPROCESS, TK_SORT, TK_FWD, TK_BWD, TK_PREBWD, TK_ADAM, TK_RELOC, TK_N };
+enum { TK_GATE = 0, TK_PREPROCESS, TK_SORT, TK_FWD, TK_BWD, TK_PREBWD, TK_ADAM, TK_RELOC, TK_SSIM, TK_N };
 
 struct TimeScope {
     swgs_plan &p;
@@ -211,7 +216,8 @@ void seq_gate(hipStream_t s, swgs_plan &p, uint8_t *ws) {
 
 // forward of records [rec_lo, rec_hi) and tiles [tile_lo, tile_hi): one
 // view (plain) or all views (batched)
-void seq_forward(hipStream_t s, swgs_plan &p, uint8_t *ws, int view, float *images, const float *targets) {
+void seq_forward(hipStream_t s, swgs_plan &p, uint8_t *ws, int view, float *images, const float *targets,
+                 float l1_weight = 1.0f) {
     uint32_t rec_lo = 0, rec_hi = (uint32_t)p.R, tile_lo = 0, tile_hi = (uint32_t)p.T;
     if (view >= 0) {
         rec_lo = p.vdev[view].rec_base;
@@ -231,7 +237,7 @@ void seq_forward(hipStream_t s, swgs_plan &p, uint8_t *ws, int view, float *imag
     }
     {
         TimeScope t(p, s, TK_FWD);
-        launch_blend_forward(s, p, ws, images, targets, tile_lo, tile_hi, counters_of(p, ws));
+        launch_blend_forward(s, p, ws, images, targets, tile_lo, tile_hi, counters_of(p, ws), l1_weight);
     }
 }
 
@@ -275,7 +281,7 @@ std::string swgs::plan_geometry(swgs_plan &p, const swgs_view *views, int n_view
     }
     // per-view geometry in caller order
     p.vdev.resize(n_views);
-    uint64_t rec = 0, tiles = 0;
+    uint64_t rec = 0, tiles = 0, t16 = 0;
     int64_t pix = 0;
     for (int v = 0; v < n_views; ++v) {
         const swgs_view &w = views[v];
@@ -298,6 +304,8 @@ std::string swgs::plan_geometry(swgs_plan &p, const swgs_view *views, int n_view
         d.tile_base = (uint32_t)tiles;
         d.pix_base = pix;
         d.inv_norm = (float)(1.0 / ((double)n_views * 3.0 * (double)w.width * (double)w.height));
+        d.ssim_tile_base = (uint32_t)t16;
+        t16 += ssim_tiles(w.width, w.height);
         rec += live[vgroup[v]];
         tiles += (uint64_t)d.tiles_x * d.tiles_y;
         pix += (int64_t)w.width * w.height;
@@ -305,6 +313,7 @@ std::string swgs::plan_geometry(swgs_plan &p, const swgs_view *views, int n_view
     if (rec >= 0xFFFFFFF0ull || tiles >= 0xFFFFFFF0ull) return "more than 2^32 records or tiles in one plan";
     p.R = (int64_t)rec;
     p.T = (int64_t)tiles;
+    p.T16 = (int64_t)t16;
     p.P = pix;
     build_layout(p);
     return std::string();
@@ -363,6 +372,7 @@ void swgs_step_cfg_default(swgs_step_cfg *c) {
     c->noise_t0 = 0.005f;
     c->lambda_opacity = 2e-2f;
     c->lambda_scale = 1e-2f;
+    c->lambda_dssim = 0.2f;
     c->grad_scale_base = 0.0f;
     c->window_start = 0;
     c->relocate_period = 1;
@@ -573,6 +583,8 @@ static swgs_status check_cfg(swgs_context *ctx, const swgs_step_cfg *cfg) {
     if (cfg->relocate_period < 0) return fail(ctx, SWGS_ERR_INVALID_ARG, "relocate_period must be >= 0");
     if (!(cfg->beta1 >= 0 && cfg->beta1 < 1 && cfg->beta2 >= 0 && cfg->beta2 < 1))
         return fail(ctx, SWGS_ERR_INVALID_ARG, "betas must be in [0, 1)");
+    if (!(cfg->lambda_dssim >= 0 && cfg->lambda_dssim <= 1))
+        return fail(ctx, SWGS_ERR_INVALID_ARG, "lambda_dssim must be in [0, 1]");
     return SWGS_OK;
 }
 
@@ -631,11 +643,21 @@ static void seq_step_tail(hipStream_t s, swgs_plan &p, uint8_t *ws, const swgs_s
     }
 }
 
+static void seq_ssim(hipStream_t s, swgs_plan &p, uint8_t *ws, int v_lo, int v_hi, const float *images,
+                     const float *targets, float lambda) {
+    TimeScope t(p, s, TK_SSIM);
+    launch_ssim(s, p, ws, v_lo, v_hi, images, targets, lambda);
+}
+
 static void seq_window_batched(hipStream_t s, swgs_plan &p, uint8_t *ws, const swgs_step_cfg &cfg,
                                const float *targets, float *images) {
     seq_gate(s, p, ws);
-    seq_forward(s, p, ws, -1, images, targets);
+    seq_forward(s, p, ws, -1, images, targets, 1.0f - cfg.lambda_dssim);
     launch_loss_reduce(s, p, ws, &cfg, true);
+    if (cfg.lambda_dssim > 0.0f) {
+        seq_ssim(s, p, ws, 0, (int)p.views.size(), images, targets, cfg.lambda_dssim);
+        launch_ssim_reduce(s, p, ws, cfg.lambda_dssim);
+    }
     launch_fill_f32(s, wsp<float>(ws, p, WB_REC_GRAD), 0.0f, 9 * (size_t)p.R);
     seq_backward_blend(s, p, ws, -1, wsp<float>(ws, p, WB_DLDC));
     seq_step_tail(s, p, ws, cfg);
@@ -655,6 +677,9 @@ swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *p, void *workspace, s
     uint8_t *ws = static_cast<uint8_t *>(workspace);
     hipStream_t s = ctx->stream;
     double *sdev = wsp<double>(ws, *p, WB_STATS);
+    // the D-SSIM term needs the rendered images: without a caller buffer
+    // they go to the workspace
+    if (!images && cfg->lambda_dssim > 0.0f) images = wsp<float>(ws, *p, WB_IMAGE);
     upload_consts(s, *p, ws);
 
     if (cfg->mode == SWGS_MODE_GRAPH) {
@@ -698,7 +723,8 @@ swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *p, void *workspace, s
         launch_fill_f32(s, wsp<float>(ws, *p, WB_REC_GRAD), 0.0f, 9 * (size_t)p->R);
         uint32_t *pc = wsp<uint32_t>(ws, *p, WB_PAIR_COUNT);
         for (int v = 0; v < (int)p->views.size(); ++v) {
-            seq_forward(s, *p, ws, v, images, targets);
+            seq_forward(s, *p, ws, v, images, targets, 1.0f - cfg->lambda_dssim);
+            if (cfg->lambda_dssim > 0.0f) seq_ssim(s, *p, ws, v, v + 1, images, targets, cfg->lambda_dssim);
             uint32_t k = 0;
             HIP_TRY(ctx, hipMemcpyAsync(&k, pc, 4, hipMemcpyDeviceToHost, s));
             HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -706,6 +732,7 @@ swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *p, void *workspace, s
             seq_backward_blend(s, *p, ws, v, wsp<float>(ws, *p, WB_DLDC));
         }
         launch_loss_reduce(s, *p, ws, cfg, true);
+        if (cfg->lambda_dssim > 0.0f) launch_ssim_reduce(s, *p, ws, cfg->lambda_dssim);
         seq_step_tail(s, *p, ws, *cfg);
     }
     if (stats)

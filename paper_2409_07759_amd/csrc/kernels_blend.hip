@@ -11,12 +11,13 @@
 //
 // The backward walks the same list back to front from each pixel's last
 // contributor, recovering the transmittance in front of each splat by
-// T <- T / (1 - alpha) (nothing per pair is stored), and keeping the colour
-// behind the splat U and the product of (1 - alpha) behind it, so that
-//     dC/dalpha_k = T_k (c_k - U_k - prod_k bg).
-// Per-splat gradient terms are summed over each 16-lane row with DPP adds,
-// the row sums of all waves are combined per batch through LDS, and flushed
-// with one global float atomic per term per (tile, splat).
+// T <- T / (1 - alpha) (nothing per pair is stored), and keeping W, the
+// colour behind the splat including the background seen through it
+// (W <- c alpha + (1 - alpha) W from W = bg), so that
+//     dC/dalpha_k = T_k (c_k - W_k).
+// Per-splat gradient terms are summed over each 16-lane row with DPP
+// exchanges, the row sums of all waves are combined per batch through LDS,
+// and flushed with one global float atomic per term per (tile, splat).
 #include "swgs_internal.h"
 
 namespace swgs {
@@ -129,7 +130,7 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             int n_views, uint32_t tile_lo, float *__restrict__ images,
             float *__restrict__ T_final, uint32_t *__restrict__ last_out,
             const float *__restrict__ targets, float *__restrict__ dLdC, double *__restrict__ loss_part,
-            unsigned long long *__restrict__ counters) {
+            unsigned long long *__restrict__ counters, float l1_weight) {
     constexpr int NT = TW * TH;
     constexpr bool CULL = NT > 64;        // per-wave support-box lists
     constexpr int NW = NT / 64;
@@ -209,7 +210,7 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         last_out[pix] = last;
         if (targets) {
             const float d0 = o0 - targets[o3], d1 = o1 - targets[o3 + HW], d2 = o2 - targets[o3 + 2 * HW];
-            const float s = V.inv_norm;
+            const float s = V.inv_norm * l1_weight;
             dLdC[o3] = d0 > 0.0f ? s : (d0 < 0.0f ? -s : 0.0f);
             dLdC[o3 + HW] = d1 > 0.0f ? s : (d1 < 0.0f ? -s : 0.0f);
             dLdC[o3 + 2 * HW] = d2 > 0.0f ? s : (d2 < 0.0f ? -s : 0.0f);
@@ -305,6 +306,7 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     __shared__ uint32_t srec[BB];
     __shared__ float4 part[BB][NP][kTerm / 4];
     __shared__ uint32_t smax;
+    __shared__ uint32_t swlast[NW];
     __shared__ unsigned long long cnt_evals;
     const uint32_t tile = tile_lo + blockIdx.x;
     const ViewDev &V = views[view_of_tile(views, n_views, tile)];
@@ -329,15 +331,22 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         g1 = dLdC[o3 + HW];
         g2 = dLdC[o3 + 2 * HW];
     }
+    // a wave never needs splats at or beyond its pixels' largest `last`
+    uint32_t wlast = lst;
+    for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
     if (threadIdx.x == 0) { smax = 0; cnt_evals = 0; }
+    if ((threadIdx.x & 63) == 0) swlast[threadIdx.x >> 6] = wlast;
     __syncthreads();
     atomicMax(&smax, lst);
     if (counters) atomicAdd(&cnt_evals, (unsigned long long)lst);
     __syncthreads();
     const uint32_t nmax = smax;
     if (counters && threadIdx.x == 0) atomicAdd(counters + 4 * (blockIdx.x % kCounterSlots) + 1, cnt_evals);
-    const float bg0 = V.bg[0], bg1 = V.bg[1], bg2 = V.bg[2];
-    float U0 = 0.0f, U1 = 0.0f, U2 = 0.0f, Rr = 1.0f;
+    // W = what lies behind the current splat as seen through it: the colour
+    // of the splats already walked (back to front) plus the background
+    // through their transmittance.  It follows the blend recurrence
+    // W <- c a + (1 - a) W from W = bg, and dC/da_k = T_k (c_k - W).
+    float W0 = V.bg[0], W1 = V.bg[1], W2 = V.bg[2];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r16 = lane & 15;
     const int prow = wave * 4 + (lane >> 4);
@@ -355,7 +364,8 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             smask[k] = CULL ? box_wave_mask<TW, TH>(cull_box(a, b), tx * TW, ty * TH) : 1u;
         }
         __syncthreads();
-        const int cnt = CULL ? wave_list<BB>(smask, m, wave, lane, slist[CULL ? wave : 0]) : m;
+        const int wm = (int)min((uint32_t)m, wlast > b_start ? wlast - b_start : 0u);
+        const int cnt = CULL ? wave_list<BB>(smask, wm, wave, lane, slist[CULL ? wave : 0]) : wm;
         for (int i = cnt - 1; i >= 0; --i) {
             const int k = CULL ? (int)slist[CULL ? wave : 0][i] : i;
             const uint32_t idx = b_start + (uint32_t)k;
@@ -366,8 +376,7 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             const float om = 1.0f - alpha;
             const float Tk = T * __builtin_amdgcn_rcpf(om);     // transmittance in front of k
             const float4 c = sc[k];
-            const float da = Tk * (g0 * (c.x - U0 - Rr * bg0) + g1 * (c.y - U1 - Rr * bg1) +
-                                   g2 * (c.z - U2 - Rr * bg2));
+            const float da = Tk * (g0 * (c.x - W0) + g1 * (c.y - W1) + g2 * (c.z - W2));
             const float w = contrib ? alpha * Tk : 0.0f;
             float v0 = g0 * w, v1 = g1 * w, v2 = g2 * w;
             // alpha = o g, g = exp(-Q/2): dQ = -alpha/2 dalpha (zero when clamped)
@@ -376,10 +385,9 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             float v7 = dQ * e.dx, v8 = dQ * e.dy;
             float v4 = v7 * e.dx, v5 = v7 * e.dy, v6 = v8 * e.dy;
             T = contrib ? Tk : T;
-            U0 = contrib ? fmaf(c.x, alpha, om * U0) : U0;
-            U1 = contrib ? fmaf(c.y, alpha, om * U1) : U1;
-            U2 = contrib ? fmaf(c.z, alpha, om * U2) : U2;
-            Rr = contrib ? Rr * om : Rr;
+            W0 = contrib ? fmaf(c.x, alpha, om * W0) : W0;
+            W1 = contrib ? fmaf(c.y, alpha, om * W1) : W1;
+            W2 = contrib ? fmaf(c.z, alpha, om * W2) : W2;
             float *pk = reinterpret_cast<float *>(&part[k][prow][0]);
             if (__ballot(contrib) != 0) {
                 const float y = row_sum16_x8(v0, v1, v2, v3, v4, v5, v6, v7, lane);
@@ -398,10 +406,12 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         // unscaled (A = -2 A' ln2, B = -B' ln2, C = -2 C' ln2)
         for (int t = threadIdx.x; t < 3 * m; t += NT) {
             const int k = t % m, j = t / m;
-            const uint32_t wm = smask[k];
+            const uint32_t hit = smask[k];
             float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             for (int q = 0; q < NP; ++q) {
-                if (!((wm >> (q >> 2)) & 1u)) continue;
+                // wave q/4 wrote this partial only if the splat reaches its
+                // block and lies before its pixels' largest `last`
+                if (!((hit >> (q >> 2)) & 1u) || b_start + (uint32_t)k >= swlast[q >> 2]) continue;
                 const float4 a = part[k][q][j];
                 acc.x += a.x; acc.y += a.y; acc.z += a.z; acc.w += a.w;
             }
@@ -483,13 +493,13 @@ k_loss_final(const double *__restrict__ sums, double inv_3p, double *__restrict_
 
 template <int TW, int TH, int BATCH>
 void fwd_launch(hipStream_t s, const swgs_plan &p, uint8_t *ws, float *images, const float *targets,
-                uint32_t tile_lo, uint32_t tile_hi, unsigned long long *counters) {
+                uint32_t tile_lo, uint32_t tile_hi, unsigned long long *counters, float l1_weight) {
     hipLaunchKernelGGL((k_blend_fwd<TW, TH, BATCH>), dim3(tile_hi - tile_lo), dim3(TW * TH), 0, s,
                        wsp<uint2>(ws, p, WB_TILE_RANGE), wsp<uint32_t>(ws, p, WB_PAIR_VAL),
                        wsp<float4>(ws, p, WB_SPLAT), wsp<ViewDev>(ws, p, WB_VIEWS),
                        (int)p.views.size(), tile_lo, images, wsp<float>(ws, p, WB_T_FINAL),
                        wsp<uint32_t>(ws, p, WB_LAST), targets, wsp<float>(ws, p, WB_DLDC),
-                       wsp<double>(ws, p, WB_LOSS_PART) + 2 * (size_t)tile_lo, counters);
+                       wsp<double>(ws, p, WB_LOSS_PART) + 2 * (size_t)tile_lo, counters, l1_weight);
 }
 
 template <int TW, int TH, int BATCH>
@@ -519,9 +529,9 @@ void bwd_launch(hipStream_t s, const swgs_plan &p, uint8_t *ws, const float *dLd
 
 void launch_blend_forward(hipStream_t s, const swgs_plan &p, uint8_t *ws, float *images,
                           const float *targets, uint32_t tile_lo, uint32_t tile_hi,
-                          unsigned long long *counters) {
+                          unsigned long long *counters, float l1_weight) {
     if (tile_hi <= tile_lo) return;
-    SWGS_DISPATCH_TILE(fwd_launch, s, p, ws, images, targets, tile_lo, tile_hi, counters);
+    SWGS_DISPATCH_TILE(fwd_launch, s, p, ws, images, targets, tile_lo, tile_hi, counters, l1_weight);
 }
 
 void launch_blend_backward(hipStream_t s, const swgs_plan &p, uint8_t *ws, const float *dLdC,

@@ -37,7 +37,7 @@ struct ViewDev {
     uint32_t tile_base;        // first global tile id of this view
     int64_t pix_base;          // first pixel of this view in the image buffers
     float inv_norm;            // 1 / (V * 3 * H * W): L1 gradient scale
-    int32_t pad;
+    uint32_t ssim_tile_base;   // first 16x16 SSIM tile of this view
 };
 
 struct GroupDev {
@@ -60,7 +60,7 @@ struct Layout {
 // tiles, pixels, pair capacity, pool slots, optimisable slots, window set,
 // live-list entries.
 struct LayoutDims {
-    size_t V = 0, G = 0, R = 0, T = 0, P = 0, cap = 0, S = 0, NG = 0, nA = 0, n_list = 0;
+    size_t V = 0, G = 0, R = 0, T = 0, P = 0, cap = 0, S = 0, NG = 0, nA = 0, n_list = 0, T16 = 0;
     bool forward_only = false;
 };
 
@@ -73,6 +73,7 @@ enum WsBuf {
     WB_PAIR_OFFSET, WB_SORT_TOTAL, WB_LAST, WB_LOSS_PART, WB_STATS, WB_STEP,
     WB_VIEWS, WB_GROUPS, WB_GROUP_VIEWS,
     WB_RELOC_W, WB_RELOC_FLAG, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_CNT, WB_RELOC_SCAN, WB_REG_PART, WB_COUNTERS, WB_CFLAGS,
+    WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE,
     WB_COUNT
 };
 
@@ -97,7 +98,7 @@ struct swgs_plan {
     std::vector<int32_t> group_views;             // view indices ordered by group
     uint32_t n_A = 0;                             // |A|
     uint32_t list_A_base = 0;
-    int64_t R = 0, P = 0, T = 0;
+    int64_t R = 0, P = 0, T = 0, T16 = 0;     // records, pixels, tiles, 16x16 SSIM tiles
     int loss_blocks = 0;
     swgs::Layout lay;
     // graph mode
@@ -117,8 +118,8 @@ struct swgs_plan {
     uint8_t *ext[swgs::WB_COUNT] = {};
     // event timing of kernel classes (off unless enabled; never inside a graph)
     bool timing = false;
-    std::vector<hipEvent_t> ev[8];
-    size_t ev_used[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    std::vector<hipEvent_t> ev[9];
+    size_t ev_used[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace swgs {
@@ -151,13 +152,21 @@ void exclusive_scan_gather_u32(hipStream_t s, const uint32_t *in, const uint32_t
 // Blend (kernels_blend.hip)
 // counters (nullable): [0] pixel x list entries evaluated by the forward,
 // [1] by the backward
+// l1_weight scales the fused L1 term and its gradient (1 - lambda_dssim)
 void launch_blend_forward(hipStream_t s, const swgs_plan &p, uint8_t *ws, float *images,
                           const float *targets, uint32_t tile_lo, uint32_t tile_hi,
-                          unsigned long long *counters);
+                          unsigned long long *counters, float l1_weight);
 void launch_blend_backward(hipStream_t s, const swgs_plan &p, uint8_t *ws, const float *dLdC,
                            uint32_t tile_lo, uint32_t tile_hi, unsigned long long *counters);
 void launch_loss_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, const swgs_step_cfg *cfg,
                         bool with_reg);
+
+// D-SSIM term (kernels_ssim.hip): SSIM of views [view_lo, view_hi) with its
+// gradient added into dL/dC, then the weighted SSIM sums added to stats[0]
+size_t ssim_tiles(int width, int height);
+void launch_ssim(hipStream_t s, const swgs_plan &p, uint8_t *ws, int view_lo, int view_hi, const float *images,
+                 const float *targets, float lambda);
+void launch_ssim_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, float lambda);
 
 // Backward preprocess, step, relocation, mature (kernels_step.hip)
 void launch_preprocess_backward(hipStream_t s, const swgs_plan &p, uint8_t *ws, int add_reg,

@@ -53,7 +53,7 @@ class SwgsPlanOpts(ctypes.Structure):
 class SwgsStepCfg(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_size_t)] + [(n, ctypes.c_float) for n in (
         "lr_mean", "lr_scale", "lr_quat", "lr_logit", "lr_sh_dc", "lr_sh_rest", "beta1", "beta2", "eps",
-        "noise_lr", "noise_k", "noise_t0", "lambda_opacity", "lambda_scale", "grad_scale_base")] + [
+        "noise_lr", "noise_k", "noise_t0", "lambda_opacity", "lambda_scale", "lambda_dssim", "grad_scale_base")] + [
         (n, ctypes.c_int32) for n in ("window_start", "relocate_period", "reloc_n_max", "mode", "reserved")]
 
 
@@ -105,7 +105,8 @@ _sigs = {
     "swgs_server_run": ([P, P, I32, I32, P], ctypes.c_int),
     "swgs_server_stats": ([P, P], ctypes.c_int),
 }
-TIMING_CLASSES = ("gate", "preprocess", "sort", "blend_fwd", "blend_bwd", "preprocess_bwd", "adam_sgld", "relocate")
+TIMING_CLASSES = ("gate", "preprocess", "sort", "blend_fwd", "blend_bwd", "preprocess_bwd", "adam_sgld", "relocate",
+                  "dssim")
 for _n, (_a, _r) in _sigs.items():
     _f = getattr(_lib, _n)
     _f.argtypes = _a
@@ -318,8 +319,8 @@ class Plan:
 
     def timing(self):
         """{class: (total ms, launches)} and (fwd evaluated, bwd evaluated, blended) pairs since the last reset."""
-        ms = (ctypes.c_double * 8)()
-        n = (ctypes.c_int64 * 8)()
+        ms = (ctypes.c_double * len(TIMING_CLASSES))()
+        n = (ctypes.c_int64 * len(TIMING_CLASSES))()
         ev = (ctypes.c_uint64 * 3)()
         with self.ctx:
             self.ctx.check(swgs_plan_timing(self.ctx.h, self.h, ptr(self.ws), self.ws_bytes, ms, n, ev))

@@ -549,10 +549,44 @@ def test_window_step_end_to_end_loss_matches_oracle(sw, ctx):
     st = host(stats)
     ref_img, _ = O.window_render(pool.params, 0, pool.start, pool.expire, views)
     A = O.window_set(pool.start, pool.expire, pool.num_gs, [0, 1, 2])
-    L, l1, _, _ = O.loss_and_grad(ref_img, tgt_h, views, pool.params, A)
+    L, l1, _, _ = O.loss_and_grad(ref_img, tgt_h, views, pool.params, A, lam_dssim=float(np.float32(cfg.lambda_dssim)))
+    assert cfg.lambda_dssim == pytest.approx(0.2)
     assert st[0] == pytest.approx(l1, rel=1e-5)
     assert st[3] == pytest.approx(L, rel=1e-5)
     assert st[7] == A.sum()
+
+
+@pytest.mark.parametrize("mode", ["batched", "plain", "graph"])
+def test_dssim_term_and_image_gradient_match_oracle(sw, ctx, mode):
+    """The D-SSIM image term (lambda 0.2) and the full dL/dC it leaves for the
+    backward, on views of mixed and ragged sizes (down to smaller than the
+    11x11 window), in every launch structure."""
+    say("dssim", mode)
+    pool, _ = tiny(n=900)
+    views = S.ring_views([0, 1], 2, 0, 0, sizes=[(64, 48), (37, 23)]) + S.ring_views([2], 1, 7, 5)
+    tgt_h = S.random_images(views, 12)
+    dp, pl = plan_for(sw, ctx, pool, views)
+    m = {"batched": sw.SWGS_MODE_BATCHED, "plain": sw.SWGS_MODE_PLAIN, "graph": sw.SWGS_MODE_GRAPH}[mode]
+    cfg = sw.step_cfg(mode=m, relocate_period=0)
+    stats = torch.zeros(8, dtype=torch.float64, device="cuda")
+    img = pl.image_buffer()
+    pl.window_step(cfg, torch.as_tensor(tgt_h, device="cuda"), 1, 0, 3, images=img, stats=stats)
+    st = host(stats)
+    dldc = host(pl.buffer(sw.SWGS_BUF_DLDC, torch.float32)).astype(np.float64)
+    ref_img, _ = O.window_render(pool.params, 0, pool.start, pool.expire, views)
+    lam = float(np.float32(cfg.lambda_dssim))
+    A = O.window_set(pool.start, pool.expire, pool.num_gs, [0, 1, 2])
+    L, part, g, _ = O.loss_and_grad(ref_img, tgt_h, views, pool.params, A, lam_dssim=lam)
+    assert st[0] == pytest.approx(part, rel=1e-5)
+    assert st[3] == pytest.approx(L, rel=1e-5)
+    # the L1 sign is only defined away from zero residuals
+    clear = np.abs(ref_img - tgt_h) > 1e-4
+    _, _, g1, _ = O.loss_and_grad(ref_img, tgt_h, views, pool.params, A)
+    g_ssim = g - (1.0 - lam) * g1
+    scale = np.abs(g_ssim).max()
+    err = np.abs(dldc - g)[clear]
+    assert err.max() <= 1e-3 * scale, (err.max(), scale)
+    assert np.abs(g_ssim).max() > 0
 
 
 def test_pair_capacity_overflow_is_reported(sw, ctx):
