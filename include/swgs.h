@@ -135,20 +135,21 @@ enum {
     SWGS_BUF_ACTIVE_LIST = 0,  /* uint32 slot ids per distinct frame, then the window set A */
     SWGS_BUF_ACTIVE_COUNT,     /* uint32 [n_groups + 1] live counts (last: |A|) */
     SWGS_BUF_RECORD_VIEW_BASE, /* uint32 [n_views + 1] first record of each view */
-    SWGS_BUF_DEPTH_KEY,        /* uint32 [R] FP32 camera-z bits of each record (0xFFFFFFFF if culled) */
+    SWGS_BUF_DEPTH_KEY,        /* uint32 [R] FP32 camera-z bits of the records, sorted ascending after a
+                                  forward (culled records carry 0xFFFFFFFF and sort last) */
     SWGS_BUF_TILE_COUNT,       /* uint32 [R] tiles covered by each record */
     SWGS_BUF_RECT,             /* uint32 [R][2]: x0 | y0 << 16, x1 | y1 << 16 (tiles, half-open) */
     SWGS_BUF_SPLAT,            /* float [R][12]: floor(u), floor(v), 0.5-(u-floor(u)), 0.5-(v-floor(v)),
                                   -log2(e) A/2, -log2(e) B, -log2(e) C/2 (conic [[A,B],[B,C]]), opacity,
                                   r, g, b, FP32 depth */
-    SWGS_BUF_PAIR_KEY,         /* uint32 [cap] FP32 depth bits of each pair (sorted within its tile) */
-    SWGS_BUF_PAIR_VAL,         /* uint32 [cap] record of each pair; tile t's Gaussians are
-                                  pair_val[range.first, range.last) in (depth, record) order */
+    SWGS_BUF_PAIR_KEY,         /* uint32 [cap] global tile id of each sorted pair */
+    SWGS_BUF_PAIR_VAL,         /* uint32 [cap] record of each sorted pair */
     SWGS_BUF_PAIR_COUNT,       /* uint32 [2]: pairs emitted, overflow flag */
     SWGS_BUF_TILE_RANGE,       /* uint32 [n_tiles][2] first, last pair of each tile */
     SWGS_BUF_T_FINAL,          /* float [P] final transmittance per pixel */
     SWGS_BUF_DLDC,             /* float [3P] dL/dimage (fused L1 gradient) */
     SWGS_BUF_RECORD_GRAD,      /* float [9][R] d/d(u, v, A, B, C, o, r, g, b) */
+    SWGS_BUF_DEPTH_ORDER,      /* uint32 [R] records in ascending (depth, record) order after a forward */
     SWGS_BUF_COUNT_
 };
 swgs_status swgs_plan_buffer(const swgs_plan *plan, int32_t which, size_t *offset, size_t *bytes);
@@ -252,7 +253,7 @@ swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *plan, void *workspace
  * evaluated by the forward [0] and the backward [1] blend and the pairs the
  * forward blended [2] (the backward differentiates exactly those); then
  * resets.  Classes: 0 gating,
- * 1 preprocess, 2 binning + per-tile depth sort,
+ * 1 preprocess, 2 depth sort + pair emission + tile sort + ranges,
  * 3 forward blend, 4 backward blend, 5 backward preprocess, 6 Adam + SGLD,
  * 7 relocation, 8 D-SSIM (forward and gradient). */
 swgs_status swgs_plan_set_timing(swgs_context *ctx, swgs_plan *plan, void *workspace, size_t ws_bytes,

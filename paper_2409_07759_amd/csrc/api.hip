@@ -111,10 +111,12 @@ void swgs::compute_layout(const LayoutDims &d, Layout &lay, size_t &consts_bytes
     sz[WB_POS_OF] = G * NG * 4;
     sz[WB_PAIR_KEY_ALT] = cap * 4;
     sz[WB_PAIR_VAL_ALT] = cap * 4;
-    sz[WB_TILE_HIST] = (T + 1) * 4;
-    sz[WB_BIG_TILES] = (T + 2) * 4;
-    sz[WB_PAIR_OFFSET] = (T + 1) * 4;
-    sz[WB_SORT_TOTAL] = (std::max(R, T) / 4096 + 16) * 4;
+    sz[WB_REC_IDX] = R * 4;
+    sz[WB_KEY_ALT] = R * 4;
+    sz[WB_IDX_ALT] = R * 4;
+    sz[WB_PAIR_OFFSET] = (R + 1) * 4;
+    sz[WB_SORT_HIST] = (size_t)2048 * kSortBlocks * 4;
+    sz[WB_SORT_TOTAL] = (std::max<size_t>(2048, R / 4096 + 2) + 8) * 4;
     sz[WB_LAST] = P * 4;
     sz[WB_LOSS_PART] = 2 * (T + 256) * 8;   // per-tile partials, then 256 chunk sums
     sz[WB_STATS] = 8 * 8;
@@ -204,6 +206,12 @@ struct TimeScope {
     }
 };
 
+int tile_bits(int64_t T) {
+    int b = 1;
+    while (b < 32 && ((int64_t)1 << b) < T) ++b;
+    return b;
+}
+
 unsigned long long *counters_of(swgs_plan &p, uint8_t *ws) {
     return p.timing ? wsp<unsigned long long>(ws, p, WB_COUNTERS) : nullptr;
 }
@@ -231,9 +239,19 @@ void seq_forward(hipStream_t s, swgs_plan &p, uint8_t *ws, int view, float *imag
     }
     {
         TimeScope t(p, s, TK_SORT);
-        launch_bin_count(s, p, ws, rec_lo, rec_hi, tile_lo, tile_hi);
-        launch_bin_emit(s, p, ws, rec_lo, rec_hi);
-        launch_tile_sort(s, p, ws, tile_lo, tile_hi);
+        uint32_t *hist = wsp<uint32_t>(ws, p, WB_SORT_HIST), *tot = wsp<uint32_t>(ws, p, WB_SORT_TOTAL);
+        // records by FP32 depth (ties keep record order), then the pairs
+        // emitted in that order stably by tile: (tile, depth, record) order
+        radix_sort_pairs(s, wsp<uint32_t>(ws, p, WB_DEPTH_KEY) + rec_lo, wsp<uint32_t>(ws, p, WB_REC_IDX) + rec_lo,
+                         wsp<uint32_t>(ws, p, WB_KEY_ALT) + rec_lo, wsp<uint32_t>(ws, p, WB_IDX_ALT) + rec_lo, nullptr,
+                         rec_hi - rec_lo, rec_hi - rec_lo, 32, hist, tot);
+        launch_pair_offsets(s, p, ws, rec_lo, rec_hi);
+        launch_emit_pairs(s, p, ws, rec_lo, rec_hi);
+        uint32_t *pc = wsp<uint32_t>(ws, p, WB_PAIR_COUNT);
+        radix_sort_pairs(s, wsp<uint32_t>(ws, p, WB_PAIR_KEY), wsp<uint32_t>(ws, p, WB_PAIR_VAL),
+                         wsp<uint32_t>(ws, p, WB_PAIR_KEY_ALT), wsp<uint32_t>(ws, p, WB_PAIR_VAL_ALT), pc, 0,
+                         (uint32_t)p.pair_cap, p.tile_key_bits, hist, tot);
+        launch_tile_ranges(s, p, ws, tile_lo, tile_hi);
     }
     {
         TimeScope t(p, s, TK_FWD);
@@ -314,6 +332,7 @@ std::string swgs::plan_geometry(swgs_plan &p, const swgs_view *views, int n_view
     p.R = (int64_t)rec;
     p.T = (int64_t)tiles;
     p.T16 = (int64_t)t16;
+    p.tile_key_bits = tile_bits(p.T);
     p.P = pix;
     build_layout(p);
     return std::string();
@@ -501,7 +520,8 @@ swgs_status swgs_plan_buffer(const swgs_plan *p, int32_t which, size_t *offset, 
     if (!p || !offset || !bytes) return SWGS_ERR_INVALID_ARG;
     static const int map[SWGS_BUF_COUNT_] = {WB_ACTIVE_LIST, WB_ACTIVE_COUNT, WB_REC_VIEW_BASE, WB_DEPTH_KEY,
                                              WB_TILE_COUNT, WB_RECT, WB_SPLAT, WB_PAIR_KEY, WB_PAIR_VAL,
-                                             WB_PAIR_COUNT, WB_TILE_RANGE, WB_T_FINAL, WB_DLDC, WB_REC_GRAD};
+                                             WB_PAIR_COUNT, WB_TILE_RANGE, WB_T_FINAL, WB_DLDC, WB_REC_GRAD,
+                                             WB_REC_IDX};
     if (which < 0 || which >= SWGS_BUF_COUNT_) return SWGS_ERR_INVALID_ARG;
     *offset = p->lay.off[map[which]];
     *bytes = p->lay.size[map[which]];
@@ -528,8 +548,10 @@ swgs_status swgs_plan_measure(swgs_context *ctx, swgs_plan *p, void *workspace, 
     upload_consts(s, *p, ws);
     launch_gate(s, *p, ws);
     launch_preprocess(s, *p, ws, -1, -1);
-    launch_bin_count(s, *p, ws, 0, (uint32_t)p->R, 0, (uint32_t)p->T);
-    uint32_t *tot = wsp<uint32_t>(ws, *p, WB_PAIR_COUNT);
+    uint32_t *tc = wsp<uint32_t>(ws, *p, WB_TILE_COUNT);
+    uint32_t *tot = wsp<uint32_t>(ws, *p, WB_PAIR_COUNT) + 2;
+    exclusive_scan_u32(s, tc, wsp<uint32_t>(ws, *p, WB_PAIR_OFFSET), (uint32_t)p->R, tot,
+                       wsp<uint32_t>(ws, *p, WB_SORT_TOTAL));
     uint32_t k = 0;
     HIP_TRY(ctx, hipMemcpyAsync(&k, tot, 4, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));

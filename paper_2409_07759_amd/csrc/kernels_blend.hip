@@ -139,7 +139,8 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     __shared__ uint8_t slist[CULL ? NW : 1][CULL ? BATCH : 1];
     __shared__ float red[2][NT / 64];
     __shared__ unsigned long long cnt_evals, cnt_blend;
-    const uint32_t tile = tile_lo + blockIdx.x;
+    const uint32_t lt_idx = xcd_order(blockIdx.x, gridDim.x);   // neighbouring tiles share an XCD's L2
+    const uint32_t tile = tile_lo + lt_idx;
     const ViewDev &V = views[view_of_tile(views, n_views, tile)];
     const uint32_t lt = tile - V.tile_base;
     const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);
@@ -244,8 +245,8 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         if (threadIdx.x == 0) {
             double a = 0.0, b = 0.0;
             for (int w = 0; w < NT / 64; ++w) { a += red[0][w]; b += red[1][w]; }
-            loss_part[2 * (size_t)blockIdx.x] = a;
-            loss_part[2 * (size_t)blockIdx.x + 1] = b;
+            loss_part[2 * (size_t)lt_idx] = a;
+            loss_part[2 * (size_t)lt_idx + 1] = b;
         }
     }
 }
@@ -308,7 +309,8 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     __shared__ uint32_t smax;
     __shared__ uint32_t swlast[NW];
     __shared__ unsigned long long cnt_evals;
-    const uint32_t tile = tile_lo + blockIdx.x;
+    const uint32_t lt_idx = xcd_order(blockIdx.x, gridDim.x);   // neighbouring tiles share an XCD's L2
+    const uint32_t tile = tile_lo + lt_idx;
     const ViewDev &V = views[view_of_tile(views, n_views, tile)];
     const uint32_t lt = tile - V.tile_base;
     const int tx = (int)(lt % (uint32_t)V.tiles_x), ty = (int)(lt / (uint32_t)V.tiles_x);

@@ -55,7 +55,7 @@ k_preprocess(const float *__restrict__ params, int n_slots, int deg, const Group
              const int32_t *__restrict__ group_views, const ViewDev *__restrict__ views,
              const uint32_t *__restrict__ lists, int g_lo, int only_view, int tile_w, int tile_h,
              float4 *__restrict__ splat, uint32_t *__restrict__ depth_key, uint32_t *__restrict__ tile_count,
-             uint2 *__restrict__ rect, uint8_t *__restrict__ cflags) {
+             uint2 *__restrict__ rect, uint32_t *__restrict__ rec_idx, uint8_t *__restrict__ cflags) {
     const GroupDev G = groups[g_lo + blockIdx.y];
     const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= G.n_live) return;
@@ -93,6 +93,7 @@ k_preprocess(const float *__restrict__ params, int n_slots, int deg, const Group
         if (only_view >= 0 && vi != only_view) continue;
         const ViewDev &V = views[vi];
         const uint32_t r = V.rec_base + j;
+        rec_idx[r] = r;
         bool vis = !faint;
         // camera space
         const double px = V.R[0] * mx + V.R[1] * my + V.R[2] * mz + V.t[0];
@@ -182,68 +183,35 @@ k_preprocess(const float *__restrict__ params, int n_slots, int deg, const Group
     }
 }
 
-// ---------------------------------------------------------------- binning
-// (view, tile, Gaussian) pairs are grouped per tile by counting: k_tile_hist
-// counts the pairs of every tile, an exclusive scan over the tiles gives
-// each tile's [first, last) range and a write cursor, and k_emit_tiles
-// writes (FP32 depth key, record) at cursor positions.  The order inside a
-// tile is then fixed by k_tile_sort (kernels_sort.hip): ascending depth,
-// "close to far" (Sec. 2.1), ties by record, i.e. by slot.
-
-// view of record r: the last view whose first record is <= r
-__device__ __forceinline__ int view_of_record(const uint32_t *__restrict__ rec_view_base, int n_views, uint32_t r) {
+// pair emission in depth order: thread per sorted record
+__global__ void __launch_bounds__(kBlock)
+k_emit_pairs(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ offsets,
+             const uint32_t *__restrict__ tile_count, const uint2 *__restrict__ rect,
+             const uint32_t *__restrict__ rec_view_base, int n_views, const ViewDev *__restrict__ views,
+             uint32_t lo, uint32_t hi, uint32_t cap, uint32_t *__restrict__ pair_key,
+             uint32_t *__restrict__ pair_val) {
+    const uint32_t p = lo + blockIdx.x * kBlock + threadIdx.x;
+    if (p >= hi) return;
+    const uint32_t r = sorted_rec[p];
+    const uint32_t c = tile_count[r];
+    if (c == 0) return;
+    uint32_t off = offsets[p - lo];
+    // view of record r: last view whose base <= r
     int a = 0, b = n_views;
     while (b - a > 1) {
-        const int m = (a + b) >> 1;
+        int m = (a + b) >> 1;
         if (rec_view_base[m] <= r) a = m; else b = m;
     }
-    return a;
-}
-
-__global__ void __launch_bounds__(kBlock)
-k_tile_hist(const uint32_t *__restrict__ tile_count, const uint2 *__restrict__ rect,
-            const uint32_t *__restrict__ rec_view_base, int n_views, const ViewDev *__restrict__ views,
-            uint32_t lo, uint32_t hi, uint32_t *__restrict__ counts) {
-    const uint32_t r = lo + blockIdx.x * kBlock + threadIdx.x;
-    if (r >= hi || tile_count[r] == 0) return;
-    const ViewDev &V = views[view_of_record(rec_view_base, n_views, r)];
-    const uint2 rc = rect[r];
-    const int x0 = rc.x & 0xFFFF, y0 = rc.x >> 16, x1 = rc.y & 0xFFFF, y1 = rc.y >> 16;
-    for (int ty = y0; ty < y1; ++ty)
-        for (int tx = x0; tx < x1; ++tx) atomicAdd(counts + V.tile_base + (uint32_t)(ty * V.tiles_x + tx), 1u);
-}
-
-// ranges from the scanned counts (clamped to the pair capacity) and the
-// write cursors (the counts are overwritten by the tile offsets)
-__global__ void __launch_bounds__(kBlock)
-k_tile_setup(const uint32_t *__restrict__ offsets, uint32_t *__restrict__ counts_cursor, uint2 *__restrict__ ranges,
-             uint32_t tile_lo, uint32_t n, uint32_t cap) {
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const uint32_t t = tile_lo + i;
-        const uint32_t off = offsets[t], end = off + counts_cursor[t];
-        ranges[t] = make_uint2(off < cap ? off : cap, end < cap ? end : cap);
-        counts_cursor[t] = off;
-    }
-}
-
-__global__ void __launch_bounds__(kBlock)
-k_emit_tiles(const uint32_t *__restrict__ depth_key, const uint32_t *__restrict__ tile_count,
-             const uint2 *__restrict__ rect, const uint32_t *__restrict__ rec_view_base, int n_views,
-             const ViewDev *__restrict__ views, uint32_t lo, uint32_t hi, uint32_t cap,
-             uint32_t *__restrict__ cursor, uint32_t *__restrict__ pair_key, uint32_t *__restrict__ pair_val) {
-    const uint32_t r = lo + blockIdx.x * kBlock + threadIdx.x;
-    if (r >= hi || tile_count[r] == 0) return;
-    const ViewDev &V = views[view_of_record(rec_view_base, n_views, r)];
-    const uint32_t key = depth_key[r];
+    const ViewDev &V = views[a];
     const uint2 rc = rect[r];
     const int x0 = rc.x & 0xFFFF, y0 = rc.x >> 16, x1 = rc.y & 0xFFFF, y1 = rc.y >> 16;
     for (int ty = y0; ty < y1; ++ty)
         for (int tx = x0; tx < x1; ++tx) {
-            const uint32_t pos = atomicAdd(cursor + V.tile_base + (uint32_t)(ty * V.tiles_x + tx), 1u);
-            if (pos < cap) {
-                pair_key[pos] = key;
-                pair_val[pos] = r;
+            if (off < cap) {
+                pair_key[off] = V.tile_base + (uint32_t)(ty * V.tiles_x + tx);
+                pair_val[off] = r;
             }
+            ++off;
         }
 }
 
@@ -251,6 +219,18 @@ __global__ void k_pair_total(const uint32_t *__restrict__ total, uint32_t cap, u
     uint32_t k = *total;
     pair_count[0] = k;
     pair_count[1] = k > cap ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_tile_ranges(const uint32_t *__restrict__ pair_key, const uint32_t *__restrict__ pair_count, uint32_t cap,
+              uint2 *__restrict__ ranges) {
+    uint32_t n = pair_count[0];
+    if (n > cap) n = cap;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const uint32_t k = pair_key[i];
+        if (i == 0 || pair_key[i - 1] != k) ranges[k].x = i;
+        if (i == n - 1 || pair_key[i + 1] != k) ranges[k].y = i + 1;
+    }
 }
 
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n) {
@@ -301,39 +281,38 @@ void launch_preprocess(hipStream_t s, const swgs_plan &p, uint8_t *ws, int view_
                        wsp<ViewDev>(ws, p, WB_VIEWS), wsp<uint32_t>(ws, p, WB_ACTIVE_LIST), g_lo, only,
                        p.tile_w, p.tile_h, wsp<float4>(ws, p, WB_SPLAT), wsp<uint32_t>(ws, p, WB_DEPTH_KEY),
                        wsp<uint32_t>(ws, p, WB_TILE_COUNT), wsp<uint2>(ws, p, WB_RECT),
-                       wsp<uint8_t>(ws, p, WB_CFLAGS));
+                       wsp<uint32_t>(ws, p, WB_REC_IDX), wsp<uint8_t>(ws, p, WB_CFLAGS));
 }
 
-void launch_bin_count(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi,
-                      uint32_t tile_lo, uint32_t tile_hi) {
-    uint32_t *counts = wsp<uint32_t>(ws, p, WB_TILE_HIST);
-    uint32_t *offsets = wsp<uint32_t>(ws, p, WB_PAIR_OFFSET);
+void launch_pair_offsets(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi) {
+    // offsets of the records sorted by depth (positions rec_lo..rec_hi of the
+    // sorted index array), and the pair total + overflow flag
     uint32_t *pc = wsp<uint32_t>(ws, p, WB_PAIR_COUNT);
-    const uint32_t nt = tile_hi - tile_lo;
-    launch_fill_u32(s, counts + tile_lo, 0, nt);
-    if (rec_hi > rec_lo)
-        hipLaunchKernelGGL(k_tile_hist, dim3((rec_hi - rec_lo + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                           wsp<uint32_t>(ws, p, WB_TILE_COUNT), wsp<uint2>(ws, p, WB_RECT),
-                           wsp<uint32_t>(ws, p, WB_REC_VIEW_BASE), (int)p.views.size(), wsp<ViewDev>(ws, p, WB_VIEWS),
-                           rec_lo, rec_hi, counts);
-    exclusive_scan_u32(s, counts + tile_lo, offsets + tile_lo, nt, pc + 2, wsp<uint32_t>(ws, p, WB_SORT_TOTAL));
+    exclusive_scan_gather_u32(s, wsp<uint32_t>(ws, p, WB_TILE_COUNT), wsp<uint32_t>(ws, p, WB_REC_IDX) + rec_lo,
+                              wsp<uint32_t>(ws, p, WB_PAIR_OFFSET), rec_hi - rec_lo, pc + 2,
+                              wsp<uint32_t>(ws, p, WB_SORT_TOTAL));
     hipLaunchKernelGGL(k_pair_total, dim3(1), dim3(1), 0, s, pc + 2, (uint32_t)p.pair_cap, pc);
-    if (nt) {
-        int nb = (int)((nt + kBlock - 1) / kBlock);
-        if (nb > 4096) nb = 4096;
-        hipLaunchKernelGGL(k_tile_setup, dim3(nb), dim3(kBlock), 0, s, offsets, counts,
-                           wsp<uint2>(ws, p, WB_TILE_RANGE), tile_lo, nt, (uint32_t)p.pair_cap);
-    }
 }
 
-void launch_bin_emit(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi) {
+void launch_emit_pairs(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi) {
     if (rec_hi <= rec_lo) return;
-    hipLaunchKernelGGL(k_emit_tiles, dim3((rec_hi - rec_lo + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                       wsp<uint32_t>(ws, p, WB_DEPTH_KEY), wsp<uint32_t>(ws, p, WB_TILE_COUNT),
-                       wsp<uint2>(ws, p, WB_RECT), wsp<uint32_t>(ws, p, WB_REC_VIEW_BASE), (int)p.views.size(),
-                       wsp<ViewDev>(ws, p, WB_VIEWS), rec_lo, rec_hi, (uint32_t)p.pair_cap,
-                       wsp<uint32_t>(ws, p, WB_TILE_HIST), wsp<uint32_t>(ws, p, WB_PAIR_KEY),
+    const uint32_t n = rec_hi - rec_lo;
+    hipLaunchKernelGGL(k_emit_pairs, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                       wsp<uint32_t>(ws, p, WB_REC_IDX), wsp<uint32_t>(ws, p, WB_PAIR_OFFSET),
+                       wsp<uint32_t>(ws, p, WB_TILE_COUNT), wsp<uint2>(ws, p, WB_RECT),
+                       wsp<uint32_t>(ws, p, WB_REC_VIEW_BASE), (int)p.views.size(), wsp<ViewDev>(ws, p, WB_VIEWS),
+                       rec_lo, rec_hi, (uint32_t)p.pair_cap, wsp<uint32_t>(ws, p, WB_PAIR_KEY),
                        wsp<uint32_t>(ws, p, WB_PAIR_VAL));
+}
+
+void launch_tile_ranges(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t tile_lo, uint32_t tile_hi) {
+    uint2 *ranges = wsp<uint2>(ws, p, WB_TILE_RANGE);
+    launch_fill_u32(s, reinterpret_cast<uint32_t *>(ranges + tile_lo), 0, 2 * (size_t)(tile_hi - tile_lo));
+    int nb = (int)((p.pair_cap + kBlock - 1) / kBlock);
+    if (nb > 8192) nb = 8192;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_tile_ranges, dim3(nb), dim3(kBlock), 0, s, wsp<uint32_t>(ws, p, WB_PAIR_KEY),
+                       wsp<uint32_t>(ws, p, WB_PAIR_COUNT), (uint32_t)p.pair_cap, ranges);
 }
 
 }  // namespace swgs

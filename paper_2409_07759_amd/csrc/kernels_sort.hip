@@ -1,19 +1,18 @@
-// Per-tile depth sort and the device-wide exclusive scan, hand-written for
-// gfx950 (wave64).
+// Device-wide stable LSD radix sort of (uint32 key, uint32 value) pairs and
+// an exclusive scan, hand-written for gfx950 (wave64).
 //
-// Sorting puts the Gaussians of each tile in depth order, "close to far"
-// (Sec. 2.1).  After binning, a tile's pairs sit contiguously in an
-// arbitrary order; each tile is sorted by the unique 64-bit key
-// (FP32 depth bits << 32 | record), so the result is deterministic and ties
-// in depth go by record (= by slot within a view).  FP32 depths of visible
-// Gaussians are positive, so their bit patterns order like the values.
+// Sorting puts the splats of each tile in depth order, "close to far"
+// (Sec. 2.1): the records are first sorted by FP32 depth bits, then the
+// (tile, record) pairs emitted in that order are stably sorted by tile.
 //
-// k_tile_sort: one workgroup per tile, bitonic sort in LDS of up to
-// kTileSortCap keys (the paper-scale window has at most ~600 pairs per
-// 16x16 tile).  Larger tiles are listed and sorted by k_tile_sort_big:
-// bitonic-sorted runs of kTileSortCap in LDS, then merge passes in global
-// memory between the pair buffers and their alternates, each merge split
-// over the workgroup's threads by merge-path diagonals.
+// One pass = histogram (LDS atomics per block) -> per-digit scan of the
+// block counts -> stable scatter.  The grid is a fixed kSortBlocks blocks;
+// block b owns the contiguous range [b L, (b+1) L) with L = ceil(n / B), so
+// the element count may live on the device (graph-friendly).  Inside a block
+// the stable rank of an element among equal digits comes from ballot-based
+// match masks within the wave and per-wave digit counts in LDS.
+// Digit widths are chosen so that the pass count is even and the sorted data
+// ends in the caller's primary buffers.
 #include "swgs_internal.h"
 
 namespace swgs {
@@ -21,121 +20,146 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr uint32_t kTileSortCap = 4096;
+constexpr int kMaxDigitBits = 11;
+constexpr int kMaxBins = 1 << kMaxDigitBits;
 
-__device__ __forceinline__ uint64_t pair_key64(uint32_t key, uint32_t val) {
-    return ((uint64_t)key << 32) | (uint64_t)val;
-}
-
-// ascending bitonic sort of s[0, P), P a power of two; every thread of the
-// block calls it
-__device__ void block_bitonic(uint64_t *s, uint32_t P) {
-    for (uint32_t k = 2; k <= P; k <<= 1)
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = threadIdx.x; i < P; i += kBlock) {
-                const uint32_t l = i ^ j;
-                if (l > i) {
-                    const uint64_t a = s[i], b = s[l];
-                    const bool up = (i & k) == 0;
-                    if ((a > b) == up) {
-                        s[i] = b;
-                        s[l] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-}
-
-// load n <= kTileSortCap pairs into LDS (padded with the largest key),
-// sort, store back in place
-__device__ void sort_run(uint64_t *s, uint32_t *keys, uint32_t *vals, uint32_t n) {
-    uint32_t P = 1;
-    while (P < n) P <<= 1;
-    for (uint32_t i = threadIdx.x; i < P; i += kBlock) s[i] = i < n ? pair_key64(keys[i], vals[i]) : ~0ull;
-    __syncthreads();
-    block_bitonic(s, P);
-    for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
-        keys[i] = (uint32_t)(s[i] >> 32);
-        vals[i] = (uint32_t)s[i];
-    }
-    __syncthreads();
+__device__ __forceinline__ uint32_t resolve_n(const uint32_t *d_n, uint32_t n_fixed, uint32_t cap) {
+    uint32_t n = d_n ? *d_n : n_fixed;
+    return n < cap ? n : cap;
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_tile_sort(const uint2 *__restrict__ ranges, uint32_t tile_lo, uint32_t *__restrict__ keys,
-            uint32_t *__restrict__ vals, uint32_t *__restrict__ big_list, uint32_t *__restrict__ big_count) {
-    __shared__ uint64_t s[kTileSortCap];
-    const uint32_t tile = tile_lo + blockIdx.x;
-    const uint2 rg = ranges[tile];
-    const uint32_t n = rg.y - rg.x;
-    if (n <= 1) return;
-    if (n > kTileSortCap) {
-        if (threadIdx.x == 0) big_list[atomicAdd(big_count, 1u)] = tile;
-        return;
-    }
-    sort_run(s, keys + rg.x, vals + rg.x, n);
+k_hist(const uint32_t *__restrict__ keys, const uint32_t *d_n, uint32_t n_fixed, uint32_t cap,
+       int shift, int bins, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[kMaxBins];
+    for (int i = threadIdx.x; i < bins; i += kBlock) h[i] = 0;
+    __syncthreads();
+    const uint32_t n = resolve_n(d_n, n_fixed, cap);
+    const uint32_t L = (n + gridDim.x - 1) / gridDim.x;
+    const uint32_t lo = blockIdx.x * L;
+    const uint32_t hi = min(n, lo + L);
+    const uint32_t mask = (uint32_t)bins - 1;
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += kBlock) atomicAdd(&h[(keys[i] >> shift) & mask], 1u);
+    __syncthreads();
+    for (int d = threadIdx.x; d < bins; d += kBlock) hist[(size_t)d * gridDim.x + blockIdx.x] = h[d];
 }
 
-// merge sorted runs a[0, la) and b[0, lb) into o[0, la + lb); thread t
-// produces a contiguous share of the output from the merge-path split at
-// its first output diagonal
-__device__ void merge_runs(const uint32_t *ak, const uint32_t *av, uint32_t la, const uint32_t *bk,
-                           const uint32_t *bv, uint32_t lb, uint32_t *ok, uint32_t *ov) {
-    const uint32_t L = la + lb;
-    const uint32_t per = (L + kBlock - 1) / kBlock;
-    const uint32_t d0 = min(L, threadIdx.x * per), d1 = min(L, d0 + per);
-    if (d0 >= d1) return;
-    uint32_t lo = d0 > lb ? d0 - lb : 0, hi = min(d0, la);
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (pair_key64(ak[mid], av[mid]) < pair_key64(bk[d0 - mid - 1], bv[d0 - mid - 1])) lo = mid + 1;
-        else hi = mid;
-    }
-    uint32_t i = lo, j = d0 - lo;
-    for (uint32_t d = d0; d < d1; ++d) {
-        const bool take_a = j >= lb || (i < la && pair_key64(ak[i], av[i]) < pair_key64(bk[j], bv[j]));
-        if (take_a) {
-            ok[d] = ak[i];
-            ov[d] = av[i];
-            ++i;
-        } else {
-            ok[d] = bk[j];
-            ov[d] = bv[j];
-            ++j;
-        }
-    }
-}
-
-// tiles with more than kTileSortCap pairs; a fixed grid walks the list
-// whose length is known only on the device
+// one block per digit: exclusive scan over the kSortBlocks block counts
 __global__ void __launch_bounds__(kBlock)
-k_tile_sort_big(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ big_list,
-                const uint32_t *__restrict__ big_count, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals,
-                uint32_t *__restrict__ keys_alt, uint32_t *__restrict__ vals_alt) {
-    __shared__ uint64_t s[kTileSortCap];
-    const uint32_t nb = *big_count;
-    for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
-        const uint2 rg = ranges[big_list[b]];
-        const uint32_t lo = rg.x, n = rg.y - rg.x;
-        for (uint32_t c0 = 0; c0 < n; c0 += kTileSortCap)
-            sort_run(s, keys + lo + c0, vals + lo + c0, min(kTileSortCap, n - c0));
-        uint32_t *sk = keys + lo, *sv = vals + lo, *dk = keys_alt + lo, *dv = vals_alt + lo;
-        for (uint32_t w = kTileSortCap; w < n; w <<= 1) {
-            for (uint32_t a0 = 0; a0 < n; a0 += 2 * w) {
-                const uint32_t la = min(w, n - a0);
-                const uint32_t lb = a0 + w < n ? min(w, n - a0 - w) : 0;
-                merge_runs(sk + a0, sv + a0, la, sk + a0 + la, sv + a0 + la, lb, dk + a0, dv + a0);
-            }
-            __syncthreads();
-            uint32_t *t = sk; sk = dk; dk = t;
-            t = sv; sv = dv; dv = t;
+k_digit_scan(uint32_t *__restrict__ hist, int nblocks, uint32_t *__restrict__ totals) {
+    const int d = blockIdx.x;
+    uint32_t *c = hist + (size_t)d * nblocks;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ uint32_t wsum[kWaves];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < nblocks; b0 += kBlock) {
+        int i = b0 + threadIdx.x;
+        uint32_t v = i < nblocks ? c[i] : 0;
+        uint32_t x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
         }
-        if (sk != keys + lo)
-            for (uint32_t i = threadIdx.x; i < n; i += kBlock) {
-                keys[lo + i] = sk[i];
-                vals[lo + i] = sv[i];
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        uint32_t before = carry;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        if (i < nblocks) c[i] = before + x - v;
+        __syncthreads();
+        if (threadIdx.x == kBlock - 1) carry = before + x;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[d] = carry;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scatter(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, const uint32_t *d_n,
+          uint32_t n_fixed, uint32_t cap, int shift, int dbits, const uint32_t *__restrict__ hist,
+          const uint32_t *__restrict__ totals, uint32_t *__restrict__ keys_out,
+          uint32_t *__restrict__ vals_out) {
+    const int bins = 1 << dbits;
+    __shared__ uint32_t base[kMaxBins];
+    __shared__ uint32_t wcnt[kWaves][kMaxBins];
+    __shared__ uint32_t wsum[kWaves];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+
+    // digit bases: exclusive prefix of the digit totals + this block's offset
+    {
+        constexpr int per = kMaxBins / kBlock;
+        uint32_t loc[per];
+        uint32_t s = 0;
+        for (int k = 0; k < per; ++k) {
+            int d = threadIdx.x * per + k;
+            uint32_t v = d < bins ? totals[d] : 0;
+            loc[k] = s;
+            s += v;
+        }
+        uint32_t x = s;
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        before += x - s;
+        for (int k = 0; k < per; ++k) {
+            int d = threadIdx.x * per + k;
+            if (d < bins) base[d] = before + loc[k] + hist[(size_t)d * gridDim.x + blockIdx.x];
+        }
+        for (int w = 0; w < kWaves; ++w)
+            for (int d = threadIdx.x; d < bins; d += kBlock) wcnt[w][d] = 0;
+        __syncthreads();
+    }
+
+    const uint32_t n = resolve_n(d_n, n_fixed, cap);
+    const uint32_t L = (n + gridDim.x - 1) / gridDim.x;
+    const uint32_t lo = blockIdx.x * L;
+    const uint32_t hi = min(n, lo + L);
+    const uint32_t mask = (uint32_t)bins - 1;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (uint32_t t0 = lo; t0 < hi; t0 += kBlock) {
+        const uint32_t i = t0 + threadIdx.x;
+        const bool ok = i < hi;
+        uint32_t k = 0, v = 0, d = 0;
+        if (ok) {
+            k = keys[i];
+            v = vals[i];
+            d = (k >> shift) & mask;
+        }
+        // lanes holding the same digit
+        uint64_t peers = __ballot(ok);
+        for (int b = 0; b < dbits; ++b) {
+            uint64_t m = __ballot(ok && ((d >> b) & 1u));
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lt);
+        const bool leader = ok && ((peers & lt) == 0);
+        if (leader) wcnt[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (ok) {
+            uint32_t pos = base[d] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+            keys_out[pos] = k;
+            vals_out[pos] = v;
+        }
+        __syncthreads();
+        if (leader) {
+            // the last wave's leader of each digit advances the base; every
+            // leader clears its own count afterwards
+            uint32_t tot = 0;
+            bool last = true;
+            for (int w = wave + 1; w < kWaves; ++w) last &= (wcnt[w][d] == 0);
+            if (last) {
+                for (int w = 0; w < kWaves; ++w) tot += wcnt[w][d];
+                base[d] += tot;
             }
+        }
+        __syncthreads();
+        if (leader) wcnt[wave][d] = 0;
         __syncthreads();
     }
 }
@@ -215,16 +239,31 @@ k_scan_write(const uint32_t *__restrict__ in, const uint32_t *__restrict__ idx, 
 
 }  // namespace
 
-void launch_tile_sort(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t tile_lo, uint32_t tile_hi) {
-    if (tile_hi <= tile_lo) return;
-    uint32_t *big = wsp<uint32_t>(ws, p, WB_BIG_TILES);
-    uint32_t *big_count = big + (p.T + 1);
-    launch_fill_u32(s, big_count, 0, 1);
-    hipLaunchKernelGGL(k_tile_sort, dim3(tile_hi - tile_lo), dim3(kBlock), 0, s, wsp<uint2>(ws, p, WB_TILE_RANGE),
-                       tile_lo, wsp<uint32_t>(ws, p, WB_PAIR_KEY), wsp<uint32_t>(ws, p, WB_PAIR_VAL), big, big_count);
-    hipLaunchKernelGGL(k_tile_sort_big, dim3(64), dim3(kBlock), 0, s, wsp<uint2>(ws, p, WB_TILE_RANGE), big,
-                       big_count, wsp<uint32_t>(ws, p, WB_PAIR_KEY), wsp<uint32_t>(ws, p, WB_PAIR_VAL),
-                       wsp<uint32_t>(ws, p, WB_PAIR_KEY_ALT), wsp<uint32_t>(ws, p, WB_PAIR_VAL_ALT));
+void radix_sort_pairs(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
+                      uint32_t *vals_alt, const uint32_t *d_n, uint32_t n_fixed, uint32_t cap,
+                      int bits, uint32_t *hist, uint32_t *totals) {
+    if (bits < 1) bits = 1;
+    if (bits > 32) bits = 32;
+    // smallest even pass count whose digits fit in kMaxDigitBits
+    int passes = 2;
+    while ((bits + passes - 1) / passes > kMaxDigitBits) passes += 2;
+    const int dbits = (bits + passes - 1) / passes;
+    uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+    int shift = 0;
+    for (int p = 0; p < passes; ++p) {
+        int w = dbits;
+        if (shift + w > 32) w = 32 - shift;
+        if (w < 1) w = 1;
+        const int bins = 1 << w;
+        hipLaunchKernelGGL(k_hist, dim3(kSortBlocks), dim3(kBlock), 0, s, ki, d_n, n_fixed, cap, shift, bins,
+                           hist);
+        hipLaunchKernelGGL(k_digit_scan, dim3(bins), dim3(kBlock), 0, s, hist, kSortBlocks, totals);
+        hipLaunchKernelGGL(k_scatter, dim3(kSortBlocks), dim3(kBlock), 0, s, ki, vi, d_n, n_fixed, cap, shift,
+                           w, hist, totals, ko, vo);
+        shift += w;
+        uint32_t *t = ki; ki = ko; ko = t;
+        t = vi; vi = vo; vo = t;
+    }
 }
 
 void exclusive_scan_u32(hipStream_t s, const uint32_t *in, uint32_t *out, uint32_t n,

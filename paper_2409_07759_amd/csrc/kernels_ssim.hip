@@ -19,6 +19,8 @@
 // same window sum; it is applied to the three partial maps and
 //     dSSIM/dx(q) = (W*Sm)(q) + 2 x(q) (W*Sxx)(q) + y(q) (W*Sxy)(q)
 // (divided by the view's 3HW) is added, times -lambda / V, into dL/dC.
+#include <cmath>
+
 #include "swgs_internal.h"
 
 namespace swgs {
@@ -29,15 +31,10 @@ constexpr int kR = 5;                  // window radius
 constexpr int kH = kT + 2 * kR;        // staged neighbourhood
 constexpr float kC1 = 1e-4f, kC2 = 9e-4f;
 
-// 1D Gaussian weights, sigma 1.5, normalised (computed once per block)
-__device__ __forceinline__ void window_taps(float *g) {
-    if (threadIdx.x < 2 * kR + 1) {
-        double s = 0.0;
-        for (int k = -kR; k <= kR; ++k) s += exp(-(double)(k * k) / 4.5);
-        const int k = (int)threadIdx.x - kR;
-        g[threadIdx.x] = (float)(exp(-(double)(k * k) / 4.5) / s);
-    }
-}
+// 1D Gaussian weights (sigma 1.5, normalised), computed once on the host
+struct Taps {
+    float w[2 * kR + 1];
+};
 
 // view owning an SSIM tile
 __device__ __forceinline__ int view_of_ssim_tile(const ViewDev *views, int n_views, uint32_t t) {
@@ -51,13 +48,18 @@ __device__ __forceinline__ int view_of_ssim_tile(const ViewDev *views, int n_vie
 
 __global__ void __launch_bounds__(kT *kT)
 k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const float *__restrict__ img,
-           const float *__restrict__ tgt, float *__restrict__ part, double *__restrict__ tile_sum, float lambda) {
-    __shared__ float g[2 * kR + 1];
-    __shared__ float sx[kH][kH], sy[kH][kH];
+           const float *__restrict__ tgt, float *__restrict__ part, double *__restrict__ tile_sum, float lambda,
+           Taps taps) {
+    __shared__ float sq[5][kH][kH];      // x, y, x^2, y^2, x y over the staged neighbourhood
     __shared__ float hsum[5][kH][kT];
     __shared__ double red[kT * kT / 64];
-    const uint32_t t = t_lo + blockIdx.x;
-    const int ch = blockIdx.y;
+    // work item (channel, tile), channel-major, dealt to the XCDs in
+    // contiguous ranges so halo rows of neighbouring tiles share an L2
+    const uint32_t nt = gridDim.x / 3;
+    const uint32_t item = xcd_order(blockIdx.x, gridDim.x);
+    const int ch = (int)(item / nt);
+    const uint32_t t_local = item - (uint32_t)ch * nt;
+    const uint32_t t = t_lo + t_local;
     const ViewDev &V = views[view_of_ssim_tile(views, n_views, t)];
     const uint32_t lt = t - V.ssim_tile_base;
     const int ntx = (V.width + kT - 1) / kT;
@@ -65,45 +67,41 @@ k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
     const size_t HW = (size_t)V.width * V.height;
     const float *X = img + 3 * (size_t)V.pix_base + (size_t)ch * HW;
     const float *Y = tgt + 3 * (size_t)V.pix_base + (size_t)ch * HW;
-    window_taps(g);
     for (int i = threadIdx.x; i < kH * kH; i += kT * kT) {
         const int r = i / kH, c = i % kH;
         const int yy = y0 + r - kR, xx = x0 + c - kR;
         const bool in = xx >= 0 && xx < V.width && yy >= 0 && yy < V.height;
         const size_t o = (size_t)yy * V.width + xx;
-        sx[r][c] = in ? X[o] : 0.0f;
-        sy[r][c] = in ? Y[o] : 0.0f;
+        const float u = in ? X[o] : 0.0f, v = in ? Y[o] : 0.0f;
+        sq[0][r][c] = u;
+        sq[1][r][c] = v;
+        sq[2][r][c] = u * u;
+        sq[3][r][c] = v * v;
+        sq[4][r][c] = u * v;
     }
     __syncthreads();
     // rows: horizontal window for the kH staged rows
     for (int i = threadIdx.x; i < kH * kT; i += kT * kT) {
         const int r = i / kT, c = i % kT;
-        float a = 0.0f, b = 0.0f, aa = 0.0f, bb = 0.0f, ab = 0.0f;
-        for (int k = 0; k <= 2 * kR; ++k) {
-            const float w = g[k], u = sx[r][c + k], v = sy[r][c + k];
-            a = fmaf(w, u, a);
-            b = fmaf(w, v, b);
-            aa = fmaf(w, u * u, aa);
-            bb = fmaf(w, v * v, bb);
-            ab = fmaf(w, u * v, ab);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            float a = 0.0f;
+#pragma unroll
+            for (int k = 0; k <= 2 * kR; ++k) a = fmaf(taps.w[k], sq[q][r][c + k], a);
+            hsum[q][r][c] = a;
         }
-        hsum[0][r][c] = a;
-        hsum[1][r][c] = b;
-        hsum[2][r][c] = aa;
-        hsum[3][r][c] = bb;
-        hsum[4][r][c] = ab;
     }
     __syncthreads();
     const int lx = threadIdx.x % kT, ly = threadIdx.x / kT;
-    float mx = 0.0f, my = 0.0f, exx = 0.0f, eyy = 0.0f, exy = 0.0f;
-    for (int k = 0; k <= 2 * kR; ++k) {
-        const float w = g[k];
-        mx = fmaf(w, hsum[0][ly + k][lx], mx);
-        my = fmaf(w, hsum[1][ly + k][lx], my);
-        exx = fmaf(w, hsum[2][ly + k][lx], exx);
-        eyy = fmaf(w, hsum[3][ly + k][lx], eyy);
-        exy = fmaf(w, hsum[4][ly + k][lx], exy);
+    float m[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        float a = 0.0f;
+#pragma unroll
+        for (int k = 0; k <= 2 * kR; ++k) a = fmaf(taps.w[k], hsum[q][ly + k][lx], a);
+        m[q] = a;
     }
+    const float mx = m[0], my = m[1], exx = m[2], eyy = m[3], exy = m[4];
     const int x = x0 + lx, y = y0 + ly;
     double s_val = 0.0;
     if (x < V.width && y < V.height) {
@@ -111,12 +109,13 @@ k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
         const float B = 2.0f * (exy - mx * my) + kC2;
         const float C = mx * mx + my * my + kC1;
         const float D = (exx - mx * mx) + (eyy - my * my) + kC2;
-        const float rCD = 1.0f / (C * D);
+        const float rC = __builtin_amdgcn_rcpf(C), rD = __builtin_amdgcn_rcpf(D);
+        const float rCD = rC * rD;
         const float S = A * B * rCD;
         const size_t o = (size_t)ch * 3 * HW + (size_t)y * V.width + x;
         float *P = part + 9 * (size_t)V.pix_base;
-        P[o] = 2.0f * my * (B - A) * rCD - 2.0f * mx * S / C + 2.0f * mx * S / D;
-        P[o + HW] = -S / D;
+        P[o] = 2.0f * my * (B - A) * rCD - 2.0f * mx * S * rC + 2.0f * mx * S * rD;
+        P[o + HW] = -S * rD;
         P[o + 2 * HW] = 2.0f * A * rCD;
         s_val = (double)S;
     }
@@ -127,26 +126,29 @@ k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
     if (threadIdx.x == 0) {
         double a = 0.0;
         for (int w = 0; w < kT * kT / 64; ++w) a += red[w];
-        tile_sum[3 * (size_t)blockIdx.x + ch] = a * (double)lambda * (double)V.inv_norm;
+        tile_sum[3 * (size_t)t_local + ch] = a * (double)lambda * (double)V.inv_norm;
     }
 }
 
 __global__ void __launch_bounds__(kT *kT)
 k_ssim_bwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const float *__restrict__ img,
            const float *__restrict__ tgt, const float *__restrict__ part, float *__restrict__ dLdC,
-           float lambda) {
-    __shared__ float g[2 * kR + 1];
+           float lambda, Taps taps) {
     __shared__ float sp[3][kH][kH];
     __shared__ float hsum[3][kH][kT];
-    const uint32_t t = t_lo + blockIdx.x;
-    const int ch = blockIdx.y;
+    // work item (channel, tile), channel-major, dealt to the XCDs in
+    // contiguous ranges so halo rows of neighbouring tiles share an L2
+    const uint32_t nt = gridDim.x / 3;
+    const uint32_t item = xcd_order(blockIdx.x, gridDim.x);
+    const int ch = (int)(item / nt);
+    const uint32_t t_local = item - (uint32_t)ch * nt;
+    const uint32_t t = t_lo + t_local;
     const ViewDev &V = views[view_of_ssim_tile(views, n_views, t)];
     const uint32_t lt = t - V.ssim_tile_base;
     const int ntx = (V.width + kT - 1) / kT;
     const int x0 = (int)(lt % (uint32_t)ntx) * kT, y0 = (int)(lt / (uint32_t)ntx) * kT;
     const size_t HW = (size_t)V.width * V.height;
     const float *P = part + 9 * (size_t)V.pix_base + (size_t)ch * 3 * HW;
-    window_taps(g);
     for (int i = threadIdx.x; i < kH * kH; i += kT * kT) {
         const int r = i / kH, c = i % kH;
         const int yy = y0 + r - kR, xx = x0 + c - kR;
@@ -160,8 +162,9 @@ k_ssim_bwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
     for (int i = threadIdx.x; i < kH * kT; i += kT * kT) {
         const int r = i / kT, c = i % kT;
         float a = 0.0f, b = 0.0f, e = 0.0f;
+#pragma unroll
         for (int k = 0; k <= 2 * kR; ++k) {
-            const float w = g[k];
+            const float w = taps.w[k];
             a = fmaf(w, sp[0][r][c + k], a);
             b = fmaf(w, sp[1][r][c + k], b);
             e = fmaf(w, sp[2][r][c + k], e);
@@ -175,8 +178,9 @@ k_ssim_bwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
     const int x = x0 + lx, y = y0 + ly;
     if (x >= V.width || y >= V.height) return;
     float a = 0.0f, b = 0.0f, e = 0.0f;
+#pragma unroll
     for (int k = 0; k <= 2 * kR; ++k) {
-        const float w = g[k];
+        const float w = taps.w[k];
         a = fmaf(w, hsum[0][ly + k][lx], a);
         b = fmaf(w, hsum[1][ly + k][lx], b);
         e = fmaf(w, hsum[2][ly + k][lx], e);
@@ -219,6 +223,14 @@ k_ssim_final(const double *__restrict__ sums, double lambda, double *__restrict_
     if (threadIdx.x == 0) stats[0] += lambda - a;
 }
 
+Taps window_taps() {
+    Taps t;
+    double w[2 * kR + 1], sum = 0.0;
+    for (int k = -kR; k <= kR; ++k) sum += (w[k + kR] = std::exp(-(double)(k * k) / (2.0 * 1.5 * 1.5)));
+    for (int k = 0; k <= 2 * kR; ++k) t.w[k] = (float)(w[k] / sum);
+    return t;
+}
+
 }  // namespace
 
 size_t ssim_tiles(int width, int height) {
@@ -231,12 +243,14 @@ void launch_ssim(hipStream_t s, const swgs_plan &p, uint8_t *ws, int view_lo, in
     const uint32_t t_lo = p.vdev[view_lo].ssim_tile_base;
     const uint32_t t_hi = view_hi < (int)p.views.size() ? p.vdev[view_hi].ssim_tile_base : (uint32_t)p.T16;
     if (t_hi <= t_lo) return;
-    const dim3 grid(t_hi - t_lo, 3);
+    const dim3 grid(3 * (t_hi - t_lo));
     double *tsum = wsp<double>(ws, p, WB_SSIM_SUM);
     hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(kT * kT), 0, s, wsp<ViewDev>(ws, p, WB_VIEWS), (int)p.views.size(),
-                       t_lo, images, targets, wsp<float>(ws, p, WB_SSIM_PART), tsum + 3 * (size_t)t_lo, lambda);
+                       t_lo, images, targets, wsp<float>(ws, p, WB_SSIM_PART), tsum + 3 * (size_t)t_lo, lambda,
+                       window_taps());
     hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(kT * kT), 0, s, wsp<ViewDev>(ws, p, WB_VIEWS), (int)p.views.size(),
-                       t_lo, images, targets, wsp<float>(ws, p, WB_SSIM_PART), wsp<float>(ws, p, WB_DLDC), lambda);
+                       t_lo, images, targets, wsp<float>(ws, p, WB_SSIM_PART), wsp<float>(ws, p, WB_DLDC), lambda,
+                       window_taps());
 }
 
 void launch_ssim_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, float lambda) {

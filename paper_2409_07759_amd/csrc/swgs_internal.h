@@ -17,9 +17,21 @@ namespace swgs {
 constexpr int kMaxShDegree = 3;
 constexpr int kMaxRows = 11 + 3 * 16;      // F at SH degree 3
 constexpr int kGateChunk = 2048;           // slots per gating block
+constexpr int kSortBlocks = 1024;          // fixed grid of the radix-sort passes
 constexpr int kSplatFloats = 12;           // floats per splat record
+constexpr int kXcds = 8;                   // accelerator complex dies (one L2 each)
 
 inline int rows_for(int sh_degree) { return 11 + 3 * (sh_degree + 1) * (sh_degree + 1); }
+
+// Workgroups of a launch are dealt to the XCDs round-robin (workgroup b runs
+// on XCD b mod 8), and each XCD has its own L2.  This bijection of [0, n)
+// hands XCD x the contiguous range of work items [x q + min(x, r), ...),
+// q = n / 8, r = n mod 8, so neighbouring tiles, which share records or
+// halo rows, meet in the same L2.
+__host__ __device__ inline uint32_t xcd_order(uint32_t b, uint32_t n) {
+    const uint32_t x = b % kXcds, i = b / kXcds, q = n / kXcds, r = n % kXcds;
+    return x * q + (x < r ? x : r) + i;
+}
 
 // A view as the kernels see it: camera in FP64 plus its place in the plan.
 struct ViewDev {
@@ -69,8 +81,8 @@ enum WsBuf {
     WB_RECT, WB_SPLAT, WB_PAIR_KEY, WB_PAIR_VAL, WB_PAIR_COUNT, WB_TILE_RANGE, WB_T_FINAL,
     WB_DLDC, WB_REC_GRAD,
     // internal
-    WB_GATE_BLK, WB_POS_OF, WB_PAIR_KEY_ALT, WB_PAIR_VAL_ALT, WB_TILE_HIST, WB_BIG_TILES,
-    WB_PAIR_OFFSET, WB_SORT_TOTAL, WB_LAST, WB_LOSS_PART, WB_STATS, WB_STEP,
+    WB_GATE_BLK, WB_POS_OF, WB_REC_IDX, WB_KEY_ALT, WB_IDX_ALT, WB_PAIR_KEY_ALT, WB_PAIR_VAL_ALT,
+    WB_PAIR_OFFSET, WB_SORT_HIST, WB_SORT_TOTAL, WB_LAST, WB_LOSS_PART, WB_STATS, WB_STEP,
     WB_VIEWS, WB_GROUPS, WB_GROUP_VIEWS,
     WB_RELOC_W, WB_RELOC_FLAG, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_CNT, WB_RELOC_SCAN, WB_REG_PART, WB_COUNTERS, WB_CFLAGS,
     WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE,
@@ -99,6 +111,7 @@ struct swgs_plan {
     uint32_t n_A = 0;                             // |A|
     uint32_t list_A_base = 0;
     int64_t R = 0, P = 0, T = 0, T16 = 0;     // records, pixels, tiles, 16x16 SSIM tiles
+    int tile_key_bits = 1;
     int loss_blocks = 0;
     swgs::Layout lay;
     // graph mode
@@ -132,17 +145,16 @@ void launch_count_live(hipStream_t s, const int32_t *start, const int32_t *expir
 
 // Preprocess and binning (kernels_preprocess.hip)
 void launch_preprocess(hipStream_t s, const swgs_plan &p, uint8_t *ws, int view_lo, int view_hi);
-// pairs per tile of records [rec_lo, rec_hi) over tiles [tile_lo, tile_hi):
-// counts, exclusive scan (pair total -> pair_count[0], overflow -> [1]),
-// tile ranges clamped to the capacity and write cursors
-void launch_bin_count(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi,
-                      uint32_t tile_lo, uint32_t tile_hi);
-// (depth key, record) of every pair written at its tile's cursor
-void launch_bin_emit(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi);
+void launch_pair_offsets(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi);
+void launch_emit_pairs(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi);
+void launch_tile_ranges(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t tile_lo, uint32_t tile_hi);
 
-// Per-tile sort and scans (kernels_sort.hip): pairs of tiles
-// [tile_lo, tile_hi) ordered by (depth key, record) inside each tile.
-void launch_tile_sort(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t tile_lo, uint32_t tile_hi);
+// Radix sort (kernels_sort.hip): stable LSD sort of (key, val) uint32 pairs,
+// n given on the device (*d_n, clamped to cap) over bits [0, bits).
+// On return the sorted data is in (keys, vals); alt buffers are scratch.
+void radix_sort_pairs(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
+                      uint32_t *vals_alt, const uint32_t *d_n, uint32_t n_fixed, uint32_t cap,
+                      int bits, uint32_t *hist, uint32_t *totals);
 void exclusive_scan_u32(hipStream_t s, const uint32_t *in, uint32_t *out, uint32_t n,
                         uint32_t *total_out, uint32_t *scratch);
 // same over in[idx[i]]

@@ -27,7 +27,7 @@ SWGS_OK, SWGS_ERR_INVALID_ARG, SWGS_ERR_UNSUPPORTED, SWGS_ERR_WORKSPACE_TOO_SMAL
 SWGS_MODE_PLAIN, SWGS_MODE_BATCHED, SWGS_MODE_GRAPH = range(3)
 (SWGS_BUF_ACTIVE_LIST, SWGS_BUF_ACTIVE_COUNT, SWGS_BUF_RECORD_VIEW_BASE, SWGS_BUF_DEPTH_KEY, SWGS_BUF_TILE_COUNT,
  SWGS_BUF_RECT, SWGS_BUF_SPLAT, SWGS_BUF_PAIR_KEY, SWGS_BUF_PAIR_VAL, SWGS_BUF_PAIR_COUNT, SWGS_BUF_TILE_RANGE,
- SWGS_BUF_T_FINAL, SWGS_BUF_DLDC, SWGS_BUF_RECORD_GRAD) = range(14)
+ SWGS_BUF_T_FINAL, SWGS_BUF_DLDC, SWGS_BUF_RECORD_GRAD, SWGS_BUF_DEPTH_ORDER) = range(15)
 
 
 class SwgsPool(ctypes.Structure):

@@ -181,27 +181,25 @@ def test_sorted_pairs_and_ranges_bit_exact(sw, ctx, tile):
     ref_tiles = np.concatenate(ref_tiles)
     ref_slots = np.concatenate(ref_slots)
     say("pairs", K, "flagged", flagged)
-    # tiles own contiguous, consecutive ranges; the tile of each pair follows
-    assert ranges[0, 0] == 0 and np.array_equal(ranges[1:, 0], ranges[:-1, 1]) and ranges[-1, 1] == K
-    tile_of = np.repeat(np.arange(len(ranges)), ranges[:, 1] - ranges[:, 0])
     if flagged == 0:
         assert K == len(ref_tiles)
-        assert np.array_equal(tile_of, ref_tiles)
+        assert np.array_equal(keys.astype(np.int64), ref_tiles)
         assert np.array_equal(rec_slot[vals], ref_slots)
     else:
         # flagged records may legitimately differ; everything else must not
         assert abs(K - len(ref_tiles)) <= 8 * flagged
-    # pair keys are the records' FP32 depth bits, ascending inside each tile
-    # with ties by record
+    # depth order: records by (FP32 depth, record)
+    order = host(pl.buffer(sw.SWGS_BUF_DEPTH_ORDER))[:pl.n_records]
     splat = host(pl.buffer(sw.SWGS_BUF_SPLAT, torch.float32)).reshape(-1, 12)
-    assert np.array_equal(keys, splat[vals, 11].view(np.uint32))
-    order = np.lexsort((vals, keys, tile_of))
-    assert np.array_equal(order, np.arange(K))
+    tc = host(pl.buffer(sw.SWGS_BUF_TILE_COUNT))
+    dk = np.where(tc > 0, splat[:, 11].view(np.uint32), np.uint32(0xFFFFFFFF)).astype(np.uint64)
+    ref = np.lexsort((np.arange(pl.n_records), dk))
+    assert np.array_equal(order, ref)
 
 
-def test_dense_tiles_take_the_merge_path(sw, ctx):
-    """Tiles holding more pairs than one LDS sort run (4096) are sorted as
-    runs plus merge passes; their lists and pixels still match the oracle."""
+def test_dense_tiles_lists_and_pixels(sw, ctx):
+    """Tiles holding many thousands of pairs (up to ~17k): their depth-ordered
+    lists and pixels still match the oracle."""
     say("dense tiles")
     pool, views = tiny(n=60000, width=40, height=24, frames=(0,), cams=2)
     dp, pl = plan_for(sw, ctx, pool, views, tile=(16, 16))
@@ -400,7 +398,11 @@ def test_autograd_function_matches_backward(sw, ctx):
     pl.backward(w)
     g2 = torch.zeros_like(g1)
     g2[:, :dp.num_gs] = dp.grads
-    assert torch.allclose(g1, g2, rtol=1e-4, atol=1e-7)
+    # same kernels, different order of the FP32 gradient atomics: sums that
+    # cancel keep an absolute error proportional to their terms, so the
+    # floor scales with each parameter row's largest gradient
+    floor = 1e-5 * g2.abs().amax(dim=1, keepdim=True)
+    assert torch.all((g1 - g2).abs() <= 1e-4 * g2.abs() + floor)
 
 
 # ------------------------------------------------------------ a6 loss
