@@ -46,12 +46,20 @@ __device__ __forceinline__ int view_of_ssim_tile(const ViewDev *views, int n_vie
     return a;
 }
 
+// Both kernels work in two separable passes over the staged neighbourhood,
+// two outputs per thread to cut LDS traffic: the row pass makes outputs
+// (r, c0), (r, c0 + 1) of every staged row from 12 staged columns; the
+// column pass makes outputs (r0, c), (r0 + 1, c) from 12 row sums.
+constexpr int kRowItems = kH * (kT / 2);   // row-pass work items (208)
+constexpr int kColItems = (kT / 2) * kT;   // column-pass work items (128)
+
 __global__ void __launch_bounds__(kT *kT)
 k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const float *__restrict__ img,
            const float *__restrict__ tgt, float *__restrict__ part, double *__restrict__ tile_sum, float lambda,
            Taps taps) {
-    __shared__ float sq[5][kH][kH];      // x, y, x^2, y^2, x y over the staged neighbourhood
-    __shared__ float hsum[5][kH][kT];
+    __shared__ __align__(16) float2 sxy[kH][kH];               // (x, y) over the staged neighbourhood
+    __shared__ __align__(16) float4 hq[kH][kT];                // row sums of x, y, x^2, y^2
+    __shared__ float hxy[kH][kT];                // row sums of x y
     __shared__ double red[kT * kT / 64];
     // work item (channel, tile), channel-major, dealt to the XCDs in
     // contiguous ranges so halo rows of neighbouring tiles share an L2
@@ -72,52 +80,73 @@ k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
         const int yy = y0 + r - kR, xx = x0 + c - kR;
         const bool in = xx >= 0 && xx < V.width && yy >= 0 && yy < V.height;
         const size_t o = (size_t)yy * V.width + xx;
-        const float u = in ? X[o] : 0.0f, v = in ? Y[o] : 0.0f;
-        sq[0][r][c] = u;
-        sq[1][r][c] = v;
-        sq[2][r][c] = u * u;
-        sq[3][r][c] = v * v;
-        sq[4][r][c] = u * v;
+        sxy[r][c] = make_float2(in ? X[o] : 0.0f, in ? Y[o] : 0.0f);
     }
     __syncthreads();
-    // rows: horizontal window for the kH staged rows
-    for (int i = threadIdx.x; i < kH * kT; i += kT * kT) {
-        const int r = i / kT, c = i % kT;
+    if (threadIdx.x < kRowItems) {
+        const int r = threadIdx.x / (kT / 2), c0 = 2 * (threadIdx.x % (kT / 2));
+        float u[2 * kR + 2], v[2 * kR + 2];
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            float a = 0.0f;
+        for (int k = 0; k < 2 * kR + 2; k += 2) {
+            const float4 e = *reinterpret_cast<const float4 *>(&sxy[r][c0 + k]);
+            u[k] = e.x; v[k] = e.y; u[k + 1] = e.z; v[k + 1] = e.w;
+        }
 #pragma unroll
-            for (int k = 0; k <= 2 * kR; ++k) a = fmaf(taps.w[k], sq[q][r][c + k], a);
-            hsum[q][r][c] = a;
+        for (int j = 0; j < 2; ++j) {
+            float a = 0.0f, b = 0.0f, aa = 0.0f, bb = 0.0f, ab = 0.0f;
+#pragma unroll
+            for (int k = 0; k <= 2 * kR; ++k) {
+                const float w = taps.w[k], uu = u[j + k], vv = v[j + k];
+                a = fmaf(w, uu, a);
+                b = fmaf(w, vv, b);
+                aa = fmaf(w * uu, uu, aa);
+                bb = fmaf(w * vv, vv, bb);
+                ab = fmaf(w * uu, vv, ab);
+            }
+            hq[r][c0 + j] = make_float4(a, b, aa, bb);
+            hxy[r][c0 + j] = ab;
         }
     }
     __syncthreads();
-    const int lx = threadIdx.x % kT, ly = threadIdx.x / kT;
-    float m[5];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        float a = 0.0f;
-#pragma unroll
-        for (int k = 0; k <= 2 * kR; ++k) a = fmaf(taps.w[k], hsum[q][ly + k][lx], a);
-        m[q] = a;
-    }
-    const float mx = m[0], my = m[1], exx = m[2], eyy = m[3], exy = m[4];
-    const int x = x0 + lx, y = y0 + ly;
     double s_val = 0.0;
-    if (x < V.width && y < V.height) {
-        const float A = 2.0f * mx * my + kC1;
-        const float B = 2.0f * (exy - mx * my) + kC2;
-        const float C = mx * mx + my * my + kC1;
-        const float D = (exx - mx * mx) + (eyy - my * my) + kC2;
-        const float rC = __builtin_amdgcn_rcpf(C), rD = __builtin_amdgcn_rcpf(D);
-        const float rCD = rC * rD;
-        const float S = A * B * rCD;
-        const size_t o = (size_t)ch * 3 * HW + (size_t)y * V.width + x;
-        float *P = part + 9 * (size_t)V.pix_base;
-        P[o] = 2.0f * my * (B - A) * rCD - 2.0f * mx * S * rC + 2.0f * mx * S * rD;
-        P[o + HW] = -S * rD;
-        P[o + 2 * HW] = 2.0f * A * rCD;
-        s_val = (double)S;
+    if (threadIdx.x < kColItems) {
+        const int c = threadIdx.x % kT, r0 = 2 * (threadIdx.x / kT);
+        float4 q[2 * kR + 2];
+        float e[2 * kR + 2];
+#pragma unroll
+        for (int k = 0; k < 2 * kR + 2; ++k) {
+            q[k] = hq[r0 + k][c];
+            e[k] = hxy[r0 + k][c];
+        }
+        float *P = part + 9 * (size_t)V.pix_base + (size_t)ch * 3 * HW;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            float mx = 0.0f, my = 0.0f, exx = 0.0f, eyy = 0.0f, exy = 0.0f;
+#pragma unroll
+            for (int k = 0; k <= 2 * kR; ++k) {
+                const float w = taps.w[k];
+                mx = fmaf(w, q[j + k].x, mx);
+                my = fmaf(w, q[j + k].y, my);
+                exx = fmaf(w, q[j + k].z, exx);
+                eyy = fmaf(w, q[j + k].w, eyy);
+                exy = fmaf(w, e[j + k], exy);
+            }
+            const int x = x0 + c, y = y0 + r0 + j;
+            if (x < V.width && y < V.height) {
+                const float A = 2.0f * mx * my + kC1;
+                const float B = 2.0f * (exy - mx * my) + kC2;
+                const float C = mx * mx + my * my + kC1;
+                const float D = (exx - mx * mx) + (eyy - my * my) + kC2;
+                const float rC = __builtin_amdgcn_rcpf(C), rD = __builtin_amdgcn_rcpf(D);
+                const float rCD = rC * rD;
+                const float S = A * B * rCD;
+                const size_t o = (size_t)y * V.width + x;
+                P[o] = 2.0f * my * (B - A) * rCD - 2.0f * mx * S * rC + 2.0f * mx * S * rD;
+                P[o + HW] = -S * rD;
+                P[o + 2 * HW] = 2.0f * A * rCD;
+                s_val += (double)S;
+            }
+        }
     }
     // tile sum of S, weighted lambda / (V 3 H W) = lambda * inv_norm
     for (int o = 32; o > 0; o >>= 1) s_val += __shfl_xor(s_val, o, 64);
@@ -134,15 +163,12 @@ __global__ void __launch_bounds__(kT *kT)
 k_ssim_bwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const float *__restrict__ img,
            const float *__restrict__ tgt, const float *__restrict__ part, float *__restrict__ dLdC,
            float lambda, Taps taps) {
-    __shared__ float sp[3][kH][kH];
-    __shared__ float hsum[3][kH][kT];
-    // work item (channel, tile), channel-major, dealt to the XCDs in
-    // contiguous ranges so halo rows of neighbouring tiles share an L2
+    __shared__ __align__(16) float4 sp[kH][kH];                // the three map derivatives (w unused)
+    __shared__ __align__(16) float4 hs[kH][kT];                // their row sums
     const uint32_t nt = gridDim.x / 3;
     const uint32_t item = xcd_order(blockIdx.x, gridDim.x);
     const int ch = (int)(item / nt);
-    const uint32_t t_local = item - (uint32_t)ch * nt;
-    const uint32_t t = t_lo + t_local;
+    const uint32_t t = t_lo + (item - (uint32_t)ch * nt);
     const ViewDev &V = views[view_of_ssim_tile(views, n_views, t)];
     const uint32_t lt = t - V.ssim_tile_base;
     const int ntx = (V.width + kT - 1) / kT;
@@ -154,42 +180,50 @@ k_ssim_bwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
         const int yy = y0 + r - kR, xx = x0 + c - kR;
         const bool in = xx >= 0 && xx < V.width && yy >= 0 && yy < V.height;
         const size_t o = (size_t)yy * V.width + xx;
-        sp[0][r][c] = in ? P[o] : 0.0f;
-        sp[1][r][c] = in ? P[o + HW] : 0.0f;
-        sp[2][r][c] = in ? P[o + 2 * HW] : 0.0f;
+        sp[r][c] = in ? make_float4(P[o], P[o + HW], P[o + 2 * HW], 0.0f) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < kH * kT; i += kT * kT) {
-        const int r = i / kT, c = i % kT;
-        float a = 0.0f, b = 0.0f, e = 0.0f;
+    if (threadIdx.x < kRowItems) {
+        const int r = threadIdx.x / (kT / 2), c0 = 2 * (threadIdx.x % (kT / 2));
+        float4 e[2 * kR + 2];
+#pragma unroll
+        for (int k = 0; k < 2 * kR + 2; ++k) e[k] = sp[r][c0 + k];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            float a = 0.0f, b = 0.0f, g = 0.0f;
+#pragma unroll
+            for (int k = 0; k <= 2 * kR; ++k) {
+                const float w = taps.w[k];
+                a = fmaf(w, e[j + k].x, a);
+                b = fmaf(w, e[j + k].y, b);
+                g = fmaf(w, e[j + k].z, g);
+            }
+            hs[r][c0 + j] = make_float4(a, b, g, 0.0f);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x >= kColItems) return;
+    const int c = threadIdx.x % kT, r0 = 2 * (threadIdx.x / kT);
+    float4 q[2 * kR + 2];
+#pragma unroll
+    for (int k = 0; k < 2 * kR + 2; ++k) q[k] = hs[r0 + k][c];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        float a = 0.0f, b = 0.0f, g = 0.0f;
 #pragma unroll
         for (int k = 0; k <= 2 * kR; ++k) {
             const float w = taps.w[k];
-            a = fmaf(w, sp[0][r][c + k], a);
-            b = fmaf(w, sp[1][r][c + k], b);
-            e = fmaf(w, sp[2][r][c + k], e);
+            a = fmaf(w, q[j + k].x, a);
+            b = fmaf(w, q[j + k].y, b);
+            g = fmaf(w, q[j + k].z, g);
         }
-        hsum[0][r][c] = a;
-        hsum[1][r][c] = b;
-        hsum[2][r][c] = e;
+        const int x = x0 + c, y = y0 + r0 + j;
+        if (x >= V.width || y >= V.height) continue;
+        const size_t o = 3 * (size_t)V.pix_base + (size_t)ch * HW + (size_t)y * V.width + x;
+        // d/dC of lambda (1 - SSIM_v) / V with SSIM_v = sum S / (3 H W):
+        // -lambda inv_norm (W*Sm + 2 x W*Sxx + y W*Sxy), inv_norm = 1 / (V 3 H W)
+        dLdC[o] -= lambda * V.inv_norm * (a + 2.0f * img[o] * b + tgt[o] * g);
     }
-    __syncthreads();
-    const int lx = threadIdx.x % kT, ly = threadIdx.x / kT;
-    const int x = x0 + lx, y = y0 + ly;
-    if (x >= V.width || y >= V.height) return;
-    float a = 0.0f, b = 0.0f, e = 0.0f;
-#pragma unroll
-    for (int k = 0; k <= 2 * kR; ++k) {
-        const float w = taps.w[k];
-        a = fmaf(w, hsum[0][ly + k][lx], a);
-        b = fmaf(w, hsum[1][ly + k][lx], b);
-        e = fmaf(w, hsum[2][ly + k][lx], e);
-    }
-    const size_t o = 3 * (size_t)V.pix_base + (size_t)ch * HW + (size_t)y * V.width + x;
-    const float xv = img[o], yv = tgt[o];
-    // d/dC of lambda (1 - SSIM_v) / V with SSIM_v = sum S / (3 H W):
-    // -lambda inv_norm (W*Sm + 2 x W*Sxx + y W*Sxy), inv_norm = 1 / (V 3 H W)
-    dLdC[o] -= lambda * V.inv_norm * (a + 2.0f * xv * b + yv * e);
 }
 
 // sum of the tile sums (fixed chunks, then one block): lambda * mean SSIM over views
