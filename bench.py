@@ -246,10 +246,10 @@ def measured_traffic(kernel, tw, th, lds):
             rec = json.load(f)
         src = os.path.join(ROOT, "paper_2409_07759_amd", "csrc", "kernels_blend.hip")
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        e = rec["kernels"][kernel]
-        if rec["source_sha256"] != digest or e["config"] != f"{tw}x{th}/lds{lds}":
+        e = rec["kernels"].get(f"{kernel}@{lds}")
+        if e is None or rec["source_sha256"] != digest or e["config"] != f"{tw}x{th}/lds{lds}":
             return None
-        return e["bytes_per_launch"]
+        return round(e["bytes_per_launch"])
     except (OSError, KeyError, ValueError):
         return None
 
