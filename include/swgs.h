@@ -148,7 +148,8 @@ enum {
     SWGS_BUF_TILE_RANGE,       /* uint32 [n_tiles][2] first, last pair of each tile */
     SWGS_BUF_T_FINAL,          /* float [P] final transmittance per pixel */
     SWGS_BUF_DLDC,             /* float [3P] dL/dimage (fused L1 gradient) */
-    SWGS_BUF_RECORD_GRAD,      /* float [9][R] d/d(u, v, A, B, C, o, r, g, b) */
+    SWGS_BUF_RECORD_GRAD,      /* float [R][9] d/d(u, v, A, B, C, o, r, g, b), each the sum of
+                                  the record's per-tile terms in tile row-major order */
     SWGS_BUF_DEPTH_ORDER,      /* uint32 [R] records in ascending (depth, record) order after a forward */
     SWGS_BUF_COUNT_
 };
@@ -254,7 +255,8 @@ swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *plan, void *workspace
  * forward blended [2] (the backward differentiates exactly those); then
  * resets.  Classes: 0 gating,
  * 1 preprocess, 2 depth sort + pair emission + tile sort + ranges,
- * 3 forward blend, 4 backward blend, 5 backward preprocess, 6 Adam + SGLD,
+ * 3 forward blend, 4 backward blend, 5 record-gradient reduce + backward
+ * preprocess, 6 Adam + SGLD,
  * 7 relocation, 8 D-SSIM (forward and gradient). */
 swgs_status swgs_plan_set_timing(swgs_context *ctx, swgs_plan *plan, void *workspace, size_t ws_bytes,
                                  int32_t on);

@@ -133,12 +133,15 @@ void swgs::compute_layout(const LayoutDims &d, Layout &lay, size_t &consts_bytes
     sz[WB_SSIM_PART] = 9 * P * 4;                     // dS/d(mu_x, E[x^2], E[xy]) per pixel and channel
     sz[WB_SSIM_SUM] = (3 * d.T16 + 256) * 8;          // per (SSIM tile, channel), then 256 chunk sums
     sz[WB_IMAGE] = 3 * P * 4;                         // renders when the caller passes no image buffer
+    sz[WB_PAIR_BASE] = R * 4;                         // first emission slot of each record
+    sz[WB_PAIR_GRAD] = cap * 9 * 4 + 16;              // 9 gradient terms per (tile, record) pair, emission
+                                                      // order (+16: the reduce reads whole 16-byte vectors)
     if (d.forward_only) {
         // serving: no gating (the live lists are resident), no gradients,
         // no loss, no step; pair buffers may live outside (ext)
         for (int b : {WB_ACTIVE_LIST, WB_GATE_BLK, WB_POS_OF, WB_DLDC, WB_REC_GRAD, WB_LOSS_PART, WB_RELOC_W,
                       WB_RELOC_FLAG, WB_RELOC_CNT, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_SCAN, WB_REG_PART,
-                      WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE})
+                      WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE, WB_PAIR_BASE, WB_PAIR_GRAD})
             sz[b] = 0;
     }
     // order: constant block, then the rest
@@ -259,14 +262,23 @@ void seq_forward(hipStream_t s, swgs_plan &p, uint8_t *ws, int view, float *imag
     }
 }
 
+// backward blend of one view (plain) or all views, then the record
+// gradients of the same records from their per-pair terms (a view's pair
+// slots are reused by the next view, so the reduce follows each backward)
 void seq_backward_blend(hipStream_t s, swgs_plan &p, uint8_t *ws, int view, const float *dLdC) {
-    uint32_t tile_lo = 0, tile_hi = (uint32_t)p.T;
+    uint32_t rec_lo = 0, rec_hi = (uint32_t)p.R, tile_lo = 0, tile_hi = (uint32_t)p.T;
     if (view >= 0) {
+        rec_lo = p.vdev[view].rec_base;
+        rec_hi = view + 1 < (int)p.views.size() ? p.vdev[view + 1].rec_base : (uint32_t)p.R;
         tile_lo = p.vdev[view].tile_base;
         tile_hi = view + 1 < (int)p.views.size() ? p.vdev[view + 1].tile_base : (uint32_t)p.T;
     }
-    TimeScope t(p, s, TK_BWD);
-    launch_blend_backward(s, p, ws, dLdC, tile_lo, tile_hi, counters_of(p, ws));
+    {
+        TimeScope t(p, s, TK_BWD);
+        launch_blend_backward(s, p, ws, dLdC, tile_lo, tile_hi, counters_of(p, ws));
+    }
+    TimeScope t(p, s, TK_PREBWD);
+    launch_pair_grad_reduce(s, p, ws, rec_lo, rec_hi);
 }
 
 }  // namespace
@@ -591,7 +603,6 @@ swgs_status swgs_render_backward(swgs_context *ctx, swgs_plan *p, void *workspac
     hipStream_t s = ctx->stream;
     upload_consts(s, *p, ws);
     const float *g = dL_dimages ? dL_dimages : wsp<float>(ws, *p, WB_DLDC);
-    launch_fill_f32(s, wsp<float>(ws, *p, WB_REC_GRAD), 0.0f, 9 * (size_t)p->R);
     seq_backward_blend(s, *p, ws, -1, g);
     launch_preprocess_backward(s, *p, ws, add_regulariser, cfg ? cfg->lambda_opacity : 0.f,
                                cfg ? cfg->lambda_scale : 0.f);
@@ -680,7 +691,6 @@ static void seq_window_batched(hipStream_t s, swgs_plan &p, uint8_t *ws, const s
         seq_ssim(s, p, ws, 0, (int)p.views.size(), images, targets, cfg.lambda_dssim);
         launch_ssim_reduce(s, p, ws, cfg.lambda_dssim);
     }
-    launch_fill_f32(s, wsp<float>(ws, p, WB_REC_GRAD), 0.0f, 9 * (size_t)p.R);
     seq_backward_blend(s, p, ws, -1, wsp<float>(ws, p, WB_DLDC));
     seq_step_tail(s, p, ws, cfg);
 }
@@ -742,7 +752,6 @@ swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *p, void *workspace, s
         launch_set_step(s, reinterpret_cast<uint8_t *>(wsp<StepDev>(ws, *p, WB_STEP)), adam_t, step, seed);
         launch_fill_f64(s, sdev, 0.0, 8);
         seq_gate(s, *p, ws);
-        launch_fill_f32(s, wsp<float>(ws, *p, WB_REC_GRAD), 0.0f, 9 * (size_t)p->R);
         uint32_t *pc = wsp<uint32_t>(ws, *p, WB_PAIR_COUNT);
         for (int v = 0; v < (int)p->views.size(); ++v) {
             seq_forward(s, *p, ws, v, images, targets, 1.0f - cfg->lambda_dssim);

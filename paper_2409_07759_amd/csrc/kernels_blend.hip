@@ -45,6 +45,17 @@ __device__ __forceinline__ Px eval_splat(float fx, float fy, const float4 a, con
 }
 #pragma clang fp contract(fast)
 
+// In-place updates of loop-carried registers: a <- a + b c and a <- a b.
+// The tied operand keeps the value in one register on both sides of the
+// backward's per-wave branch (the untied form made the register allocator
+// copy T and W back and forth every iteration).
+__device__ __forceinline__ void fmac_inplace(float &a, float b, float c) {
+    asm("v_fmac_f32 %0, %1, %2" : "+v"(a) : "v"(b), "v"(c));
+}
+__device__ __forceinline__ void mul_inplace(float &a, float b) {
+    asm("v_mul_f32 %0, %0, %1" : "+v"(a) : "v"(b));
+}
+
 // DPP move (row-level lane permutation), as float
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_f(float v) {
@@ -295,7 +306,8 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             const float4 *__restrict__ splat, const ViewDev *__restrict__ views,
             int n_views, uint32_t tile_lo, const float *__restrict__ T_final,
             const uint32_t *__restrict__ last_in, const float *__restrict__ dLdC,
-            float *__restrict__ rec_grad, size_t R, unsigned long long *__restrict__ counters) {
+            const uint2 *__restrict__ rect, const uint32_t *__restrict__ pair_base,
+            float *__restrict__ pair_grad, unsigned long long *__restrict__ counters) {
     constexpr int NT = TW * TH;
     constexpr int NW = NT / 64;           // waves
     constexpr int NP = 4 * NW;            // row partials per splat
@@ -304,7 +316,7 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     __shared__ float4 sa[BB], sb[BB], sc[BB];
     __shared__ uint32_t smask[BB];
     __shared__ uint8_t slist[CULL ? NW : 1][CULL ? BB : 1];
-    __shared__ uint32_t srec[BB];
+    __shared__ uint32_t sslot[BB];        // emission slot of each batch pair
     __shared__ float4 part[BB][NP][kTerm / 4];
     __shared__ uint32_t smax;
     __shared__ uint32_t swlast[NW];
@@ -344,6 +356,19 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     __syncthreads();
     const uint32_t nmax = smax;
     if (counters && threadIdx.x == 0) atomicAdd(counters + 4 * (blockIdx.x % kCounterSlots) + 1, cnt_evals);
+    // A pair's slot: the record's first emission slot plus this tile's
+    // row-major index inside the record's tile rect.
+    auto slot_of = [&](uint32_t r) {
+        const uint2 rc = rect[r];
+        const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu;
+        return pair_base[r] + ((uint32_t)ty - y0) * (x1 - x0) + ((uint32_t)tx - x0);
+    };
+    // pairs past every pixel's last contributor get zero terms
+    for (uint32_t q = nmax + threadIdx.x; q < rg.y - rg.x; q += NT) {
+        float *dst = pair_grad + 9 * (size_t)slot_of(pair_val[rg.x + q]);
+#pragma unroll
+        for (int t = 0; t < 9; ++t) dst[t] = 0.0f;
+    }
     // W = what lies behind the current splat as seen through it: the colour
     // of the splats already walked (back to front) plus the background
     // through their transmittance.  It follows the blend recurrence
@@ -358,7 +383,7 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         const int m = (int)(b_end - b_start);
         for (int k = threadIdx.x; k < m; k += NT) {
             const uint32_t r = pair_val[rg.x + b_start + k];
-            srec[k] = r;
+            sslot[k] = slot_of(r);
             const float4 a = splat[3 * (size_t)r], b = splat[3 * (size_t)r + 1];
             sa[k] = a;
             sb[k] = b;
@@ -371,41 +396,48 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         for (int i = cnt - 1; i >= 0; --i) {
             const int k = CULL ? (int)slist[CULL ? wave : 0][i] : i;
             const uint32_t idx = b_start + (uint32_t)k;
-            // branch-free per lane: contrib = the forward blended this splat here
+            // contrib = the forward blended this splat here
             const Px e = eval_splat(fx, fy, sa[k], sb[k]);
             const float alpha = fminf(0.99f, e.og);
             const bool contrib = idx < lst && alpha >= (1.0f / 255.0f);
-            const float om = 1.0f - alpha;
-            const float Tk = T * __builtin_amdgcn_rcpf(om);     // transmittance in front of k
-            const float4 c = sc[k];
-            const float da = Tk * (g0 * (c.x - W0) + g1 * (c.y - W1) + g2 * (c.z - W2));
-            const float w = contrib ? alpha * Tk : 0.0f;
-            float v0 = g0 * w, v1 = g1 * w, v2 = g2 * w;
-            // alpha = o g, g = exp(-Q/2): dQ = -alpha/2 dalpha (zero when clamped)
-            const float dQ = (contrib && e.og < 0.99f) ? -0.5f * e.og * da : 0.0f;
-            float v3 = (contrib && e.og < 0.99f) ? e.g * da : 0.0f;
-            float v7 = dQ * e.dx, v8 = dQ * e.dy;
-            float v4 = v7 * e.dx, v5 = v7 * e.dy, v6 = v8 * e.dy;
-            T = contrib ? Tk : T;
-            W0 = contrib ? fmaf(c.x, alpha, om * W0) : W0;
-            W1 = contrib ? fmaf(c.y, alpha, om * W1) : W1;
-            W2 = contrib ? fmaf(c.z, alpha, om * W2) : W2;
-            float *pk = reinterpret_cast<float *>(&part[k][prow][0]);
+            // T and W change only where the splat was blended: a wave with
+            // no such pixel skips the gradient (branch-free inside) and
+            // stores zero partials
+            float part_out = 0.0f;
             if (__ballot(contrib) != 0) {
+                const float ri = __builtin_amdgcn_rcpf(1.0f - alpha);
+                const float Tk = T * ri;                                     // transmittance in front of k
+                const float4 c = sc[k];
+                const float d0 = c.x - W0, d1 = c.y - W1, d2 = c.z - W2;
+                const float da = Tk * (g0 * d0 + g1 * d1 + g2 * d2);
+                const float ac = contrib ? alpha : 0.0f;
+                const float w = ac * Tk;
+                float v0 = g0 * w, v1 = g1 * w, v2 = g2 * w;
+                // alpha = o g, g = exp(-Q/2): dQ = -alpha/2 dalpha (zero when clamped)
+                const bool lin = contrib && e.og < 0.99f;
+                const float dQ = lin ? -0.5f * e.og * da : 0.0f;
+                float v3 = lin ? e.g * da : 0.0f;
+                float v7 = dQ * e.dx, v8 = dQ * e.dy;
+                float v4 = v7 * e.dx, v5 = v7 * e.dy, v6 = v8 * e.dy;
+                // T <- T / (1 - a) where blended (T x 1 elsewhere);
+                // W <- c a + (1 - a) W = W + a (c - W), a = 0 keeps W
+                mul_inplace(T, contrib ? ri : 1.0f);
+                fmac_inplace(W0, ac, d0);
+                fmac_inplace(W1, ac, d1);
+                fmac_inplace(W2, ac, d2);
                 const float y = row_sum16_x8(v0, v1, v2, v3, v4, v5, v6, v7, lane);
                 const float s8 = row_sum16(v8);
-                if (r16 < 8) pk[r16] = y;
-                else if (r16 == 8) pk[8] = s8;
-            } else if (r16 < 9) {
-                pk[r16] = 0.0f;
+                part_out = r16 < 8 ? y : s8;
             }
+            if (r16 < 9) reinterpret_cast<float *>(&part[k][prow][0])[r16] = part_out;
         }
         __syncthreads();
         // flush: the row partials of each splat (only from the waves whose
         // block it reaches) are summed per term group (3 float4 groups, one
-        // thread per (splat, group)), then one thread per splat issues the
-        // record gradients d/d(u, v, A, B, C, o, r, g, b) with the conic
-        // unscaled (A = -2 A' ln2, B = -B' ln2, C = -2 C' ln2)
+        // thread per (splat, group)), then nine neighbouring threads store
+        // the pair's terms d/d(u, v, A, B, C, o, r, g, b), conic unscaled
+        // (A = -2 A' ln2, B = -B' ln2, C = -2 C' ln2), as one 36-byte row at
+        // its emission slot: no atomics, and a fixed summation order
         for (int t = threadIdx.x; t < 3 * m; t += NT) {
             const int k = t % m, j = t / m;
             const uint32_t hit = smask[k];
@@ -420,26 +452,22 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             part[k][0][j] = acc;
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < m; k += NT) {
-            const float4 s0 = part[k][0][0], s1 = part[k][0][1];
-            const float s8 = part[k][0][2].x;
-            if (s0.x == 0.0f && s0.y == 0.0f && s0.z == 0.0f && s0.w == 0.0f && s1.x == 0.0f &&
-                s1.y == 0.0f && s1.z == 0.0f && s1.w == 0.0f && s8 == 0.0f)
-                continue;
-            const float4 b = sb[k];
-            const float A = -2.0f * kLn2 * b.x, B = -kLn2 * b.y, C = -2.0f * kLn2 * b.z;
-            const uint32_t r = srec[k];
-            const float s7 = s1.w;
-            // dQ/ddx = 2(A dx + B dy), ddx/du = -1
-            atomicAdd(rec_grad + 0 * R + r, -2.0f * (A * s7 + B * s8));
-            atomicAdd(rec_grad + 1 * R + r, -2.0f * (B * s7 + C * s8));
-            atomicAdd(rec_grad + 2 * R + r, s1.x);
-            atomicAdd(rec_grad + 3 * R + r, 2.0f * s1.y);
-            atomicAdd(rec_grad + 4 * R + r, s1.z);
-            atomicAdd(rec_grad + 5 * R + r, s0.w);
-            atomicAdd(rec_grad + 6 * R + r, s0.x);
-            atomicAdd(rec_grad + 7 * R + r, s0.y);
-            atomicAdd(rec_grad + 8 * R + r, s0.z);
+        for (int q = threadIdx.x; q < 9 * m; q += NT) {
+            const int k = q / 9, t = q - 9 * k;
+            // summed partials: 0-2 colour, 3 opacity, 4-6 conic terms,
+            // 7-8 offset terms
+            const float *pk = reinterpret_cast<const float *>(&part[k][0][0]);
+            float v;
+            if (t < 2) {
+                // dQ/ddx = 2(A dx + B dy), ddx/du = -1
+                const float4 b = sb[k];
+                const float A = -2.0f * kLn2 * b.x, B = -kLn2 * b.y, C = -2.0f * kLn2 * b.z;
+                v = t == 0 ? -2.0f * (A * pk[7] + B * pk[8]) : -2.0f * (B * pk[7] + C * pk[8]);
+            } else {
+                const int src = t < 5 ? t + 2 : (t == 5 ? 3 : t - 6);
+                v = (t == 3 ? 2.0f : 1.0f) * pk[src];
+            }
+            pair_grad[9 * (size_t)sslot[k] + t] = v;
         }
         __syncthreads();
         b_end = b_start;
@@ -493,6 +521,77 @@ k_loss_final(const double *__restrict__ sums, double inv_3p, double *__restrict_
     }
 }
 
+// Record gradients: each record's nine terms summed over its emission
+// slots in slot order (deterministic).  A block takes kReduceRecs records
+// in depth order, the order their slots were emitted in, so their terms
+// form one contiguous stretch: it is staged through LDS with 16-byte loads
+// (kReduceChunk pairs at a time, from the 16-byte boundary at or below its
+// start), then nine lanes per record (lane t summing term t) add their
+// record's rows, seven records per wave and round, and store each record's
+// sums as one 36-byte row.
+constexpr int kReduceRounds = 8;
+constexpr int kReduceRecs = 4 * 7 * kReduceRounds;   // 4 waves
+constexpr int kReduceChunk = 1024;                   // pairs per LDS stage
+constexpr int kReduceVec = (9 * kReduceChunk + 3) / 4 + 1;
+
+__global__ void __launch_bounds__(256)
+k_pair_grad_reduce(const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
+                   const uint32_t *__restrict__ pair_count, const float *__restrict__ pair_grad, uint32_t cap,
+                   uint32_t n, float *__restrict__ rec_grad) {
+    __shared__ float4 buf4[kReduceVec];
+    __shared__ uint32_t bound[kReduceRecs + 1];
+    const float *buf = reinterpret_cast<const float *>(buf4);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane / 9, t = lane - 9 * g;
+    const uint32_t j0 = blockIdx.x * kReduceRecs;
+    const uint32_t nb = min((uint32_t)kReduceRecs, n - j0);
+    const uint32_t total = pair_count[0];
+    // record boundaries; slots at or past the capacity were never emitted
+    for (uint32_t x = threadIdx.x; x <= nb; x += 256) bound[x] = min(j0 + x < n ? offsets[j0 + x] : total, cap);
+    uint32_t rec[kReduceRounds];
+#pragma unroll
+    for (int q = 0; q < kReduceRounds; ++q) {
+        const uint32_t jj = (uint32_t)(7 * (kReduceRounds * wave + q) + g);
+        rec[q] = (g < 7 && jj < nb) ? order[j0 + jj] : 0u;
+    }
+    __syncthreads();
+    const uint32_t lo = bound[0], hi = bound[nb];
+    float acc[kReduceRounds];
+#pragma unroll
+    for (int q = 0; q < kReduceRounds; ++q) acc[q] = 0.0f;
+    for (uint32_t base = lo; base < hi; base += kReduceChunk) {
+        const uint32_t cnt = min((uint32_t)kReduceChunk, hi - base);
+        const size_t f0 = 9 * (size_t)base, a0 = f0 & ~(size_t)3;
+        const uint32_t shift = (uint32_t)(f0 - a0);
+        const uint32_t n4 = (shift + 9 * cnt + 3) / 4;
+        const float4 *src = reinterpret_cast<const float4 *>(pair_grad + a0);
+        for (uint32_t x0 = threadIdx.x; x0 < n4; x0 += 8 * 256) {
+            float4 v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                v[k] = x0 + 256 * k < n4 ? src[x0 + 256 * k] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (x0 + 256 * k < n4) buf4[x0 + 256 * k] = v[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kReduceRounds; ++q) {
+            const uint32_t jj = (uint32_t)(7 * (kReduceRounds * wave + q) + g);
+            if (g < 7 && jj < nb) {
+                const uint32_t s0 = max(bound[jj], base), s1 = min(bound[jj + 1], base + cnt);
+                for (uint32_t i = s0; i < s1; ++i) acc[q] += buf[shift + 9 * (i - base) + t];
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < kReduceRounds; ++q) {
+        const uint32_t jj = (uint32_t)(7 * (kReduceRounds * wave + q) + g);
+        if (g < 7 && jj < nb) rec_grad[9 * (size_t)rec[q] + t] = acc[q];
+    }
+}
+
 template <int TW, int TH, int BATCH>
 void fwd_launch(hipStream_t s, const swgs_plan &p, uint8_t *ws, float *images, const float *targets,
                 uint32_t tile_lo, uint32_t tile_hi, unsigned long long *counters, float l1_weight) {
@@ -511,7 +610,8 @@ void bwd_launch(hipStream_t s, const swgs_plan &p, uint8_t *ws, const float *dLd
                        wsp<uint2>(ws, p, WB_TILE_RANGE), wsp<uint32_t>(ws, p, WB_PAIR_VAL),
                        wsp<float4>(ws, p, WB_SPLAT), wsp<ViewDev>(ws, p, WB_VIEWS),
                        (int)p.views.size(), tile_lo, wsp<float>(ws, p, WB_T_FINAL),
-                       wsp<uint32_t>(ws, p, WB_LAST), dLdC, wsp<float>(ws, p, WB_REC_GRAD), (size_t)p.R, counters);
+                       wsp<uint32_t>(ws, p, WB_LAST), dLdC, wsp<uint2>(ws, p, WB_RECT),
+                       wsp<uint32_t>(ws, p, WB_PAIR_BASE), wsp<float>(ws, p, WB_PAIR_GRAD), counters);
 }
 
 }  // namespace
@@ -551,6 +651,17 @@ void launch_loss_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, const sw
     hipLaunchKernelGGL(k_loss_partial, dim3(kLossBlocks), dim3(256), 0, s, part, (int)p.T, sums);
     hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, sums, 1.0 / (3.0 * (double)p.P),
                        wsp<double>(ws, p, WB_STATS));
+}
+
+void launch_pair_grad_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi) {
+    // depth-sorted positions [rec_lo, rec_hi), their emission offsets and
+    // the emitted total of the same range
+    if (rec_hi <= rec_lo) return;
+    const uint32_t n = rec_hi - rec_lo;
+    hipLaunchKernelGGL(k_pair_grad_reduce, dim3((n + kReduceRecs - 1) / kReduceRecs), dim3(256), 0, s,
+                       wsp<uint32_t>(ws, p, WB_REC_IDX) + rec_lo, wsp<uint32_t>(ws, p, WB_PAIR_OFFSET),
+                       wsp<uint32_t>(ws, p, WB_PAIR_COUNT), wsp<float>(ws, p, WB_PAIR_GRAD), (uint32_t)p.pair_cap, n,
+                       wsp<float>(ws, p, WB_REC_GRAD));
 }
 
 }  // namespace swgs

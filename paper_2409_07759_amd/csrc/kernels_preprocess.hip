@@ -189,13 +189,16 @@ k_emit_pairs(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict
              const uint32_t *__restrict__ tile_count, const uint2 *__restrict__ rect,
              const uint32_t *__restrict__ rec_view_base, int n_views, const ViewDev *__restrict__ views,
              uint32_t lo, uint32_t hi, uint32_t cap, uint32_t *__restrict__ pair_key,
-             uint32_t *__restrict__ pair_val) {
+             uint32_t *__restrict__ pair_val, uint32_t *__restrict__ pair_base) {
     const uint32_t p = lo + blockIdx.x * kBlock + threadIdx.x;
     if (p >= hi) return;
     const uint32_t r = sorted_rec[p];
     const uint32_t c = tile_count[r];
     if (c == 0) return;
     uint32_t off = offsets[p - lo];
+    // the record's pairs take slots off .. off + c - 1, its rect's tiles in
+    // row-major order (the backward finds a pair's slot from this base)
+    if (pair_base) pair_base[r] = off;
     // view of record r: last view whose base <= r
     int a = 0, b = n_views;
     while (b - a > 1) {
@@ -302,7 +305,8 @@ void launch_emit_pairs(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t 
                        wsp<uint32_t>(ws, p, WB_TILE_COUNT), wsp<uint2>(ws, p, WB_RECT),
                        wsp<uint32_t>(ws, p, WB_REC_VIEW_BASE), (int)p.views.size(), wsp<ViewDev>(ws, p, WB_VIEWS),
                        rec_lo, rec_hi, (uint32_t)p.pair_cap, wsp<uint32_t>(ws, p, WB_PAIR_KEY),
-                       wsp<uint32_t>(ws, p, WB_PAIR_VAL));
+                       wsp<uint32_t>(ws, p, WB_PAIR_VAL),
+                       p.forward_only ? nullptr : wsp<uint32_t>(ws, p, WB_PAIR_BASE));
 }
 
 void launch_tile_ranges(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t tile_lo, uint32_t tile_hi) {

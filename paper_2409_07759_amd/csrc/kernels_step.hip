@@ -102,7 +102,7 @@ k_prebwd_color(const float *__restrict__ params, int n_slots, int num_gs, const 
                uint32_t nA, const GroupDev *__restrict__ groups, int n_groups,
                const int32_t *__restrict__ group_views, const ViewDev *__restrict__ views,
                const int32_t *__restrict__ pos_of, const uint32_t *__restrict__ tile_count,
-               const uint8_t *__restrict__ cflags, const float *__restrict__ rec_grad, size_t R,
+               const uint8_t *__restrict__ cflags, const float *__restrict__ rec_grad,
                float *__restrict__ grads) {
     constexpr int nk = (DEG + 1) * (DEG + 1);
     const uint32_t a = blockIdx.x * kBlock + threadIdx.x;
@@ -124,9 +124,9 @@ k_prebwd_color(const float *__restrict__ params, int n_slots, int num_gs, const 
             if (tile_count[r] == 0) continue;                 // culled in this view
             const uint32_t fl = cflags[r];
             // rgb_c = max(0, sum_k Y_k f_kc + 1/2); clamped channels pass nothing
-            const float gc0 = (fl & 1u) ? 0.0f : rec_grad[6 * R + r];
-            const float gc1 = (fl & 2u) ? 0.0f : rec_grad[7 * R + r];
-            const float gc2 = (fl & 4u) ? 0.0f : rec_grad[8 * R + r];
+            const float gc0 = (fl & 1u) ? 0.0f : rec_grad[9 * (size_t)r + 6];
+            const float gc1 = (fl & 2u) ? 0.0f : rec_grad[9 * (size_t)r + 7];
+            const float gc2 = (fl & 4u) ? 0.0f : rec_grad[9 * (size_t)r + 8];
             const float dxv = mx - (float)V.campos[0], dyv = my - (float)V.campos[1], dzv = mz - (float)V.campos[2];
             const float il = rsqrtf(dxv * dxv + dyv * dyv + dzv * dzv);
             const float hx = dxv * il, hy = dyv * il, hz = dzv * il;
@@ -164,7 +164,7 @@ k_prebwd_geom(const float *__restrict__ params, int n_slots, int num_gs, const u
               uint32_t nA, const GroupDev *__restrict__ groups, int n_groups,
               const int32_t *__restrict__ group_views, const ViewDev *__restrict__ views,
               const int32_t *__restrict__ pos_of, const uint32_t *__restrict__ tile_count,
-              const uint8_t *__restrict__ cflags, const float *__restrict__ rec_grad, size_t R,
+              const uint8_t *__restrict__ cflags, const float *__restrict__ rec_grad,
               float *__restrict__ grads, int add_reg, double reg_o, double reg_s, double *__restrict__ reg_part) {
     const uint32_t a = blockIdx.x * kBlock + threadIdx.x;
     double rsig = 0.0, rscale = 0.0;
@@ -204,7 +204,7 @@ k_prebwd_geom(const float *__restrict__ params, int n_slots, int num_gs, const u
                 const uint32_t r = V.rec_base + (uint32_t)j;
                 if (tile_count[r] == 0) continue;                 // culled in this view
                 const uint32_t fl = cflags[r];
-                dlogit += (double)rec_grad[5 * R + r] * op * (1.0 - op);
+                dlogit += (double)rec_grad[9 * (size_t)r + 5] * op * (1.0 - op);
                 const double px = V.R[0] * mx + V.R[1] * my + V.R[2] * mz + V.t[0];
                 const double py = V.R[3] * mx + V.R[4] * my + V.R[5] * mz + V.t[1];
                 const double pz = V.R[6] * mx + V.R[7] * my + V.R[8] * mz + V.t[2];
@@ -231,7 +231,7 @@ k_prebwd_geom(const float *__restrict__ params, int n_slots, int num_gs, const u
                 const double det = ca * cc - cb * cb;
                 // conic (A, B, C) = (c, -b, a) / det
                 const double i2 = 1.0 / (det * det);
-                const double gA = rec_grad[2 * R + r], gB = rec_grad[3 * R + r], gC = rec_grad[4 * R + r];
+                const double gA = rec_grad[9 * (size_t)r + 2], gB = rec_grad[9 * (size_t)r + 3], gC = rec_grad[9 * (size_t)r + 4];
                 const double dca = (-cc * cc * gA + cb * cc * gB - cb * cb * gC) * i2;
                 const double dcb = (2.0 * cb * cc * gA - (ca * cc + cb * cb) * gB + 2.0 * ca * cb * gC) * i2;
                 const double dcc = (-cb * cb * gA + ca * cb * gB - ca * ca * gC) * i2;
@@ -258,7 +258,7 @@ k_prebwd_geom(const float *__restrict__ params, int n_slots, int num_gs, const u
                 if (!clx) { dpx += dtx * iz; dpz -= dtx * px * iz * iz; }
                 if (!cly) { dpy += dty * iz; dpz -= dty * py * iz * iz; }
                 // projected mean
-                const double gu = rec_grad[r], gv = rec_grad[R + r];
+                const double gu = rec_grad[9 * (size_t)r], gv = rec_grad[9 * (size_t)r + 1];
                 dpx += gu * V.fx * iz;
                 dpz -= gu * V.fx * px * iz * iz;
                 dpy += gv * V.fy * iz;
@@ -679,7 +679,7 @@ void launch_preprocess_backward(hipStream_t s, const swgs_plan &p, uint8_t *ws, 
         wsp<uint32_t>(ws, p, WB_ACTIVE_LIST) + p.list_A_base, nA, wsp<GroupDev>(ws, p, WB_GROUPS),        \
         (int)p.groups.size(), wsp<int32_t>(ws, p, WB_GROUP_VIEWS), wsp<ViewDev>(ws, p, WB_VIEWS),         \
         wsp<int32_t>(ws, p, WB_POS_OF), wsp<uint32_t>(ws, p, WB_TILE_COUNT), wsp<uint8_t>(ws, p, WB_CFLAGS), \
-        wsp<float>(ws, p, WB_REC_GRAD), (size_t)p.R, p.pool.grads
+        wsp<float>(ws, p, WB_REC_GRAD), p.pool.grads
     hipLaunchKernelGGL(k_prebwd_geom, SWGS_PREBWD_COMMON, add_reg, (double)lambda_o * inv, (double)lambda_s * inv,
                        wsp<double>(ws, p, WB_REG_PART));
     switch (p.sh_degree) {

@@ -85,7 +85,7 @@ enum WsBuf {
     WB_PAIR_OFFSET, WB_SORT_HIST, WB_SORT_TOTAL, WB_LAST, WB_LOSS_PART, WB_STATS, WB_STEP,
     WB_VIEWS, WB_GROUPS, WB_GROUP_VIEWS,
     WB_RELOC_W, WB_RELOC_FLAG, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_CNT, WB_RELOC_SCAN, WB_REG_PART, WB_COUNTERS, WB_CFLAGS,
-    WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE,
+    WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE, WB_PAIR_BASE, WB_PAIR_GRAD,
     WB_COUNT
 };
 
@@ -170,6 +170,9 @@ void launch_blend_forward(hipStream_t s, const swgs_plan &p, uint8_t *ws, float 
                           unsigned long long *counters, float l1_weight);
 void launch_blend_backward(hipStream_t s, const swgs_plan &p, uint8_t *ws, const float *dLdC,
                            uint32_t tile_lo, uint32_t tile_hi, unsigned long long *counters);
+// record gradients [9][R] of records [rec_lo, rec_hi): the per-pair terms
+// the backward blend left at the records' emission slots, summed in order
+void launch_pair_grad_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi);
 void launch_loss_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, const swgs_step_cfg *cfg,
                         bool with_reg);
 
