@@ -45,17 +45,6 @@ __device__ __forceinline__ Px eval_splat(float fx, float fy, const float4 a, con
 }
 #pragma clang fp contract(fast)
 
-// In-place updates of loop-carried registers: a <- a + b c and a <- a b.
-// The tied operand keeps the value in one register on both sides of the
-// backward's per-wave branch (the untied form made the register allocator
-// copy T and W back and forth every iteration).
-__device__ __forceinline__ void fmac_inplace(float &a, float b, float c) {
-    asm("v_fmac_f32 %0, %1, %2" : "+v"(a) : "v"(b), "v"(c));
-}
-__device__ __forceinline__ void mul_inplace(float &a, float b) {
-    asm("v_mul_f32 %0, %0, %1" : "+v"(a) : "v"(b));
-}
-
 // DPP move (row-level lane permutation), as float
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_f(float v) {
@@ -372,8 +361,10 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     // W = what lies behind the current splat as seen through it: the colour
     // of the splats already walked (back to front) plus the background
     // through their transmittance.  It follows the blend recurrence
-    // W <- c a + (1 - a) W from W = bg, and dC/da_k = T_k (c_k - W).
-    float W0 = V.bg[0], W1 = V.bg[1], W2 = V.bg[2];
+    // W <- c a + (1 - a) W from W = bg, and dL/da_k = T_k g.(c_k - W) with g
+    // = dL/dC of the pixel; only gW = g.W is needed, and it follows the same
+    // recurrence: gW <- gW + a (g.c - gW).
+    float gW = g0 * V.bg[0] + g1 * V.bg[1] + g2 * V.bg[2];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r16 = lane & 15;
     const int prow = wave * 4 + (lane >> 4);
@@ -408,23 +399,21 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
                 const float ri = __builtin_amdgcn_rcpf(1.0f - alpha);
                 const float Tk = T * ri;                                     // transmittance in front of k
                 const float4 c = sc[k];
-                const float d0 = c.x - W0, d1 = c.y - W1, d2 = c.z - W2;
-                const float da = Tk * (g0 * d0 + g1 * d1 + g2 * d2);
+                const float diff = fmaf(g2, c.z, fmaf(g1, c.y, g0 * c.x)) - gW;
+                const float da = Tk * diff;                                  // dL/dalpha
                 const float ac = contrib ? alpha : 0.0f;
                 const float w = ac * Tk;
                 float v0 = g0 * w, v1 = g1 * w, v2 = g2 * w;
-                // alpha = o g, g = exp(-Q/2): dQ = -alpha/2 dalpha (zero when clamped)
-                const bool lin = contrib && e.og < 0.99f;
-                const float dQ = lin ? -0.5f * e.og * da : 0.0f;
-                float v3 = lin ? e.g * da : 0.0f;
-                float v7 = dQ * e.dx, v8 = dQ * e.dy;
+                // alpha = o g, g = exp(-Q/2): dL/do = g da and dL/dQ =
+                // -o g da / 2, both zero where alpha is clamped; the
+                // partials carry q = -2 dL/dQ (the flush applies -1/2)
+                const float m = (contrib && e.og < 0.99f) ? da : 0.0f;
+                float v3 = e.g * m;
+                const float q = e.og * m;
+                float v7 = q * e.dx, v8 = q * e.dy;
                 float v4 = v7 * e.dx, v5 = v7 * e.dy, v6 = v8 * e.dy;
-                // T <- T / (1 - a) where blended (T x 1 elsewhere);
-                // W <- c a + (1 - a) W = W + a (c - W), a = 0 keeps W
-                mul_inplace(T, contrib ? ri : 1.0f);
-                fmac_inplace(W0, ac, d0);
-                fmac_inplace(W1, ac, d1);
-                fmac_inplace(W2, ac, d2);
+                T = contrib ? Tk : T;
+                gW = fmaf(ac, diff, gW);                                     // a = 0 keeps gW
                 const float y = row_sum16_x8(v0, v1, v2, v3, v4, v5, v6, v7, lane);
                 const float s8 = row_sum16(v8);
                 part_out = r16 < 8 ? y : s8;
@@ -459,13 +448,14 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             const float *pk = reinterpret_cast<const float *>(&part[k][0][0]);
             float v;
             if (t < 2) {
-                // dQ/ddx = 2(A dx + B dy), ddx/du = -1
+                // dQ/ddx = 2(A dx + B dy), ddx/du = -1; partials hold -2 dL/dQ
                 const float4 b = sb[k];
                 const float A = -2.0f * kLn2 * b.x, B = -kLn2 * b.y, C = -2.0f * kLn2 * b.z;
-                v = t == 0 ? -2.0f * (A * pk[7] + B * pk[8]) : -2.0f * (B * pk[7] + C * pk[8]);
+                v = t == 0 ? A * pk[7] + B * pk[8] : B * pk[7] + C * pk[8];
             } else {
+                // conic terms dx^2, 2 dx dy, dy^2 times dL/dQ = -q/2
                 const int src = t < 5 ? t + 2 : (t == 5 ? 3 : t - 6);
-                v = (t == 3 ? 2.0f : 1.0f) * pk[src];
+                v = (t == 3 ? -1.0f : t < 5 ? -0.5f : 1.0f) * pk[src];
             }
             pair_grad[9 * (size_t)sslot[k] + t] = v;
         }
