@@ -269,24 +269,40 @@ __device__ __forceinline__ float xstep(float a, float c, bool bit) {
     return keep + dpp_f<CTRL, 0xf>(send);
 }
 
-// Row sums of eight values at once: after the xor-1, xor-2 and rotate-4
-// exchanges and a rotate-8 add, lane l of every 16-lane row holds the row
-// sum of v[l & 7] (22 VALU operations instead of 32 for eight separate
-// row sums).
-__device__ __forceinline__ float row_sum16_x8(float v0, float v1, float v2, float v3, float v4, float v5,
-                                              float v6, float v7, int lane) {
-    const bool b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1;
-    const float w0 = xstep<0xB1>(v0, v1, b0), w1 = xstep<0xB1>(v2, v3, b0);
-    const float w2 = xstep<0xB1>(v4, v5, b0), w3 = xstep<0xB1>(v6, v7, b0);
-    const float x0 = xstep<0x4E>(w0, w1, b1), x1 = xstep<0x4E>(w2, w3, b1);
-    const float y = xstep<0x124>(x0, x1, b2);
-    return y + dpp_f<0x128, 0xf>(y);
+// One exchange step across the two 32-lane halves (x = 32) or across the
+// two rows of each row pair (x = 16) with gfx950's lane-swap instructions:
+// the result holds a's pair sum in the lower half / even rows and c's in
+// the upper half / odd rows (two instructions per step).
+__device__ __forceinline__ float xswap32(float a, float c) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(c), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float xswap16(float a, float c) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(c), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// Backward batches are BB splats; per splat each wave reduces its 9
-// gradient terms to one value per 16-lane row (a transposed reduction for
-// eight of them, a plain row sum for the ninth) and lanes 0-8 of each row
-// store the nine sums to LDS.
+// Wave sums of eight values at once (a transposed reduction): the half and
+// row-pair swaps leave row r of x0 / x1 holding values (0, 2, 1, 3)[r] /
+// (4, 6, 5, 7)[r], each summed over 4 lanes; an xor-1 exchange puts x0's
+// value on even lanes and x1's on odd ones, and xor-2, rotate-4 and
+// rotate-8 adds finish the sums.  Lane l then holds the wave sum of value
+// 4 (l & 1) + brev2(l >> 4), brev2 = (0, 2, 1, 3); 18 VALU operations.
+__device__ __forceinline__ float wave_sum_x8(float v0, float v1, float v2, float v3, float v4, float v5,
+                                             float v6, float v7, int lane) {
+    const float w0 = xswap32(v0, v1), w1 = xswap32(v2, v3), w2 = xswap32(v4, v5), w3 = xswap32(v6, v7);
+    const float x0 = xswap16(w0, w1), x1 = xswap16(w2, w3);
+    float y = xstep<0xB1>(x0, x1, lane & 1);
+    y += dpp_f<0x4E, 0xf>(y);    // quad_perm [2,3,0,1]
+    y += dpp_f<0x124, 0xf>(y);   // row_ror:4
+    y += dpp_f<0x128, 0xf>(y);   // row_ror:8
+    return y;
+}
+
+// Backward batches are BB splats; per splat each wave reduces eight of its
+// gradient terms over the whole wave and the ninth to one value per 16-lane
+// row, and twelve lanes store them to LDS: floats 0-7 the terms (colour 3,
+// opacity, conic 3, offset x), 8-11 the row sums of the offset-y term.
 constexpr int kTerm = 12;                 // 9 terms padded to 3 x float4
 
 template <int TW, int TH, int BATCH>
@@ -299,14 +315,13 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             float *__restrict__ pair_grad, unsigned long long *__restrict__ counters) {
     constexpr int NT = TW * TH;
     constexpr int NW = NT / 64;           // waves
-    constexpr int NP = 4 * NW;            // row partials per splat
-    constexpr int BB = NW == 1 ? 64 : 32; // splats per LDS batch (partials: BB x NP x 48 B)
+    constexpr int BB = NW == 1 ? 64 : 32; // splats per LDS batch (partials: BB x NW x 48 B)
     constexpr bool CULL = NW > 1;
     __shared__ float4 sa[BB], sb[BB], sc[BB];
     __shared__ uint32_t smask[BB];
     __shared__ uint8_t slist[CULL ? NW : 1][CULL ? BB : 1];
     __shared__ uint32_t sslot[BB];        // emission slot of each batch pair
-    __shared__ float4 part[BB][NP][kTerm / 4];
+    __shared__ float4 part[BB][NW][kTerm / 4];
     __shared__ uint32_t smax;
     __shared__ uint32_t swlast[NW];
     __shared__ unsigned long long cnt_evals;
@@ -367,7 +382,8 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     float gW = g0 * V.bg[0] + g1 * V.bg[1] + g2 * V.bg[2];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r16 = lane & 15;
-    const int prow = wave * 4 + (lane >> 4);
+    // store slot of this lane's reduced value (lanes 0-2 of each row)
+    const int pslot = r16 < 2 ? 4 * r16 + (((lane >> 4) & 1) << 1 | (lane >> 5)) : 8 + (lane >> 4);
 
     for (uint32_t b_end = nmax; b_end > 0;) {
         const uint32_t b_start = b_end > (uint32_t)BB ? b_end - BB : 0;
@@ -414,11 +430,11 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
                 float v4 = v7 * e.dx, v5 = v7 * e.dy, v6 = v8 * e.dy;
                 T = contrib ? Tk : T;
                 gW = fmaf(ac, diff, gW);                                     // a = 0 keeps gW
-                const float y = row_sum16_x8(v0, v1, v2, v3, v4, v5, v6, v7, lane);
+                const float y = wave_sum_x8(v0, v1, v2, v3, v4, v5, v6, v7, lane);
                 const float s8 = row_sum16(v8);
-                part_out = r16 < 8 ? y : s8;
+                part_out = r16 < 2 ? y : s8;
             }
-            if (r16 < 9) reinterpret_cast<float *>(&part[k][prow][0])[r16] = part_out;
+            if (r16 < 3) reinterpret_cast<float *>(&part[k][wave][0])[pslot] = part_out;
         }
         __syncthreads();
         // flush: the row partials of each splat (only from the waves whose
@@ -431,10 +447,10 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             const int k = t % m, j = t / m;
             const uint32_t hit = smask[k];
             float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            for (int q = 0; q < NP; ++q) {
-                // wave q/4 wrote this partial only if the splat reaches its
+            for (int q = 0; q < NW; ++q) {
+                // wave q wrote this partial only if the splat reaches its
                 // block and lies before its pixels' largest `last`
-                if (!((hit >> (q >> 2)) & 1u) || b_start + (uint32_t)k >= swlast[q >> 2]) continue;
+                if (!((hit >> q) & 1u) || b_start + (uint32_t)k >= swlast[q]) continue;
                 const float4 a = part[k][q][j];
                 acc.x += a.x; acc.y += a.y; acc.z += a.z; acc.w += a.w;
             }
@@ -444,14 +460,15 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         for (int q = threadIdx.x; q < 9 * m; q += NT) {
             const int k = q / 9, t = q - 9 * k;
             // summed partials: 0-2 colour, 3 opacity, 4-6 conic terms,
-            // 7-8 offset terms
+            // 7 offset x, 8-11 offset y (four rows)
             const float *pk = reinterpret_cast<const float *>(&part[k][0][0]);
             float v;
             if (t < 2) {
                 // dQ/ddx = 2(A dx + B dy), ddx/du = -1; partials hold -2 dL/dQ
                 const float4 b = sb[k];
                 const float A = -2.0f * kLn2 * b.x, B = -kLn2 * b.y, C = -2.0f * kLn2 * b.z;
-                v = t == 0 ? A * pk[7] + B * pk[8] : B * pk[7] + C * pk[8];
+                const float sy = (pk[8] + pk[9]) + (pk[10] + pk[11]);
+                v = t == 0 ? A * pk[7] + B * sy : B * pk[7] + C * sy;
             } else {
                 // conic terms dx^2, 2 dx dy, dy^2 times dL/dQ = -q/2
                 const int src = t < 5 ? t + 2 : (t == 5 ? 3 : t - 6);
