@@ -131,7 +131,7 @@ void swgs::compute_layout(const LayoutDims &d, Layout &lay, size_t &consts_bytes
     sz[WB_COUNTERS] = 256 * 4 * 8;   // 256 slots x {fwd evals, bwd evals, blended, pad}
     sz[WB_CFLAGS] = R + 16;
     sz[WB_SSIM_PART] = 9 * P * 4;                     // dS/d(mu_x, E[x^2], E[xy]) per pixel and channel
-    sz[WB_SSIM_SUM] = (3 * d.T16 + 256) * 8;          // per (SSIM tile, channel), then 256 chunk sums
+    sz[WB_SSIM_SUM] = (3 * d.Tssim + 256) * 8;          // per (SSIM tile, channel), then 256 chunk sums
     sz[WB_IMAGE] = 3 * P * 4;                         // renders when the caller passes no image buffer
     sz[WB_PAIR_BASE] = R * 4;                         // first emission slot of each record
     sz[WB_PAIR_GRAD] = cap * 9 * 4 + 16;              // 9 gradient terms per (tile, record) pair, emission
@@ -178,7 +178,7 @@ void build_layout(swgs_plan &p) {
     d.nA = p.n_A;
     d.n_list = p.n_A;
     for (auto &g : p.groups) d.n_list += g.n_live;
-    d.T16 = (size_t)p.T16;
+    d.Tssim = (size_t)p.Tssim;
     d.forward_only = p.forward_only;
     compute_layout(d, p.lay, p.consts_bytes);
 }
@@ -311,7 +311,7 @@ std::string swgs::plan_geometry(swgs_plan &p, const swgs_view *views, int n_view
     }
     // per-view geometry in caller order
     p.vdev.resize(n_views);
-    uint64_t rec = 0, tiles = 0, t16 = 0;
+    uint64_t rec = 0, tiles = 0, tssim = 0;
     int64_t pix = 0;
     for (int v = 0; v < n_views; ++v) {
         const swgs_view &w = views[v];
@@ -334,8 +334,8 @@ std::string swgs::plan_geometry(swgs_plan &p, const swgs_view *views, int n_view
         d.tile_base = (uint32_t)tiles;
         d.pix_base = pix;
         d.inv_norm = (float)(1.0 / ((double)n_views * 3.0 * (double)w.width * (double)w.height));
-        d.ssim_tile_base = (uint32_t)t16;
-        t16 += ssim_tiles(w.width, w.height);
+        d.ssim_tile_base = (uint32_t)tssim;
+        tssim += ssim_tiles(w.width, w.height);
         rec += live[vgroup[v]];
         tiles += (uint64_t)d.tiles_x * d.tiles_y;
         pix += (int64_t)w.width * w.height;
@@ -343,7 +343,7 @@ std::string swgs::plan_geometry(swgs_plan &p, const swgs_view *views, int n_view
     if (rec >= 0xFFFFFFF0ull || tiles >= 0xFFFFFFF0ull) return "more than 2^32 records or tiles in one plan";
     p.R = (int64_t)rec;
     p.T = (int64_t)tiles;
-    p.T16 = (int64_t)t16;
+    p.Tssim = (int64_t)tssim;
     p.tile_key_bits = tile_bits(p.T);
     p.P = pix;
     build_layout(p);

@@ -10,8 +10,8 @@
 // with C1 = 0.01^2, C2 = 0.03^2; SSIM is the mean of S over pixels and
 // channels.
 //
-// k_ssim_fwd: one workgroup per (16x16 output tile, channel) stages the
-// 26x26 neighbourhood of C and GT in LDS, runs the separable 11-tap window
+// k_ssim_fwd: one workgroup per (32x32 output tile, channel) stages the
+// 42x42 neighbourhood of C and GT in LDS, runs the separable 11-tap window
 // (rows, then columns) over x, y, x^2, y^2, xy, and writes per pixel the
 // partial derivatives of S with respect to mu_x, E[x^2] and E[xy], plus the
 // tile's sum of S weighted for the loss.
@@ -26,14 +26,22 @@
 namespace swgs {
 namespace {
 
-constexpr int kT = 16;                 // output tile
+constexpr int kT = 32;                 // output tile
 constexpr int kR = 5;                  // window radius
 constexpr int kH = kT + 2 * kR;        // staged neighbourhood
+constexpr int kW = 2 * kR + 1;         // taps
+constexpr int kSeg = 4;                // outputs per work item (both passes)
+constexpr int kSpan = kSeg + 2 * kR;   // inputs per work item
+constexpr int kThreads = 256;
+constexpr int kRowItems = kH * (kT / kSeg);   // row pass: every staged row x 8 segments (336)
+constexpr int kColItems = kT * (kT / kSeg);   // column pass: 32 columns x 8 segments (256)
+static_assert(kColItems == kThreads, "one column item per thread");
+constexpr int kStage = (kH * kH + kThreads - 1) / kThreads;   // staged elements per thread (7)
 constexpr float kC1 = 1e-4f, kC2 = 9e-4f;
 
 // 1D Gaussian weights (sigma 1.5, normalised), computed once on the host
 struct Taps {
-    float w[2 * kR + 1];
+    float w[kW];
 };
 
 // view owning an SSIM tile
@@ -46,106 +54,136 @@ __device__ __forceinline__ int view_of_ssim_tile(const ViewDev *views, int n_vie
     return a;
 }
 
-// Both kernels work in two separable passes over the staged neighbourhood,
-// two outputs per thread to cut LDS traffic: the row pass makes outputs
-// (r, c0), (r, c0 + 1) of every staged row from 12 staged columns; the
-// column pass makes outputs (r0, c), (r0 + 1, c) from 12 row sums.
-constexpr int kRowItems = kH * (kT / 2);   // row-pass work items (208)
-constexpr int kColItems = (kT / 2) * kT;   // column-pass work items (128)
+struct SsimTile {
+    int ch, x0, y0;
+    uint32_t t_local;
+    const ViewDev *V;
+};
 
-__global__ void __launch_bounds__(kT *kT)
+// work item (channel, tile), channel-major, dealt to the XCDs in contiguous
+// ranges so halo rows of neighbouring tiles share an L2
+__device__ __forceinline__ SsimTile ssim_tile(const ViewDev *views, int n_views, uint32_t t_lo) {
+    SsimTile r;
+    const uint32_t nt = gridDim.x / 3;
+    const uint32_t item = xcd_order(blockIdx.x, gridDim.x);
+    r.ch = (int)(item / nt);
+    r.t_local = item - (uint32_t)r.ch * nt;
+    const uint32_t t = t_lo + r.t_local;
+    r.V = &views[view_of_ssim_tile(views, n_views, t)];
+    const uint32_t lt = t - r.V->ssim_tile_base;
+    const int ntx = (r.V->width + kT - 1) / kT;
+    r.x0 = (int)(lt % (uint32_t)ntx) * kT;
+    r.y0 = (int)(lt / (uint32_t)ntx) * kT;
+    return r;
+}
+
+// Both passes give each work item kSeg consecutive outputs from kSpan
+// staged inputs, every input weighted into the outputs whose window holds
+// it (taps in increasing order per output).
+__global__ void __launch_bounds__(kThreads)
 k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const float *__restrict__ img,
            const float *__restrict__ tgt, float *__restrict__ part, double *__restrict__ tile_sum, float lambda,
            Taps taps) {
-    __shared__ __align__(16) float2 sxy[kH][kH];               // (x, y) over the staged neighbourhood
-    __shared__ __align__(16) float4 hq[kH][kT];                // row sums of x, y, x^2, y^2
-    __shared__ float hxy[kH][kT];                // row sums of x y
-    __shared__ double red[kT * kT / 64];
-    // work item (channel, tile), channel-major, dealt to the XCDs in
-    // contiguous ranges so halo rows of neighbouring tiles share an L2
-    const uint32_t nt = gridDim.x / 3;
-    const uint32_t item = xcd_order(blockIdx.x, gridDim.x);
-    const int ch = (int)(item / nt);
-    const uint32_t t_local = item - (uint32_t)ch * nt;
-    const uint32_t t = t_lo + t_local;
-    const ViewDev &V = views[view_of_ssim_tile(views, n_views, t)];
-    const uint32_t lt = t - V.ssim_tile_base;
-    const int ntx = (V.width + kT - 1) / kT;
-    const int x0 = (int)(lt % (uint32_t)ntx) * kT, y0 = (int)(lt / (uint32_t)ntx) * kT;
+    __shared__ __align__(16) float2 sxy[kH][kH];   // (x, y) over the staged neighbourhood
+    __shared__ __align__(16) float4 hq[kH][kT];    // row sums of x, y, x^2, y^2
+    __shared__ float hxy[kH][kT];                  // row sums of x y
+    __shared__ double red[kThreads / 64];
+    const SsimTile tl = ssim_tile(views, n_views, t_lo);
+    const ViewDev &V = *tl.V;
     const size_t HW = (size_t)V.width * V.height;
-    const float *X = img + 3 * (size_t)V.pix_base + (size_t)ch * HW;
-    const float *Y = tgt + 3 * (size_t)V.pix_base + (size_t)ch * HW;
-    for (int i = threadIdx.x; i < kH * kH; i += kT * kT) {
-        const int r = i / kH, c = i % kH;
-        const int yy = y0 + r - kR, xx = x0 + c - kR;
-        const bool in = xx >= 0 && xx < V.width && yy >= 0 && yy < V.height;
-        const size_t o = (size_t)yy * V.width + xx;
-        sxy[r][c] = make_float2(in ? X[o] : 0.0f, in ? Y[o] : 0.0f);
-    }
-    __syncthreads();
-    if (threadIdx.x < kRowItems) {
-        const int r = threadIdx.x / (kT / 2), c0 = 2 * (threadIdx.x % (kT / 2));
-        float u[2 * kR + 2], v[2 * kR + 2];
+    const float *X = img + 3 * (size_t)V.pix_base + (size_t)tl.ch * HW;
+    const float *Y = tgt + 3 * (size_t)V.pix_base + (size_t)tl.ch * HW;
+    {
+        // all of a thread's loads in flight before its LDS stores
+        float2 v[kStage];
 #pragma unroll
-        for (int k = 0; k < 2 * kR + 2; k += 2) {
-            const float4 e = *reinterpret_cast<const float4 *>(&sxy[r][c0 + k]);
-            u[k] = e.x; v[k] = e.y; u[k + 1] = e.z; v[k + 1] = e.w;
+        for (int u = 0; u < kStage; ++u) {
+            const int i = threadIdx.x + u * kThreads;
+            const int r = i / kH, c = i - r * kH;
+            const int yy = tl.y0 + r - kR, xx = tl.x0 + c - kR;
+            const bool in = i < kH * kH && xx >= 0 && xx < V.width && yy >= 0 && yy < V.height;
+            const size_t o = in ? (size_t)yy * V.width + xx : 0;
+            v[u] = make_float2(in ? X[o] : 0.0f, in ? Y[o] : 0.0f);
         }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            float a = 0.0f, b = 0.0f, aa = 0.0f, bb = 0.0f, ab = 0.0f;
+        for (int u = 0; u < kStage; ++u) {
+            const int i = threadIdx.x + u * kThreads;
+            if (i < kH * kH) (&sxy[0][0])[i] = v[u];
+        }
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < kRowItems; it += kThreads) {
+        const int r = it / (kT / kSeg), c0 = kSeg * (it % (kT / kSeg));
+        float a[kSeg], b[kSeg], aa[kSeg], bb[kSeg], ab[kSeg];
 #pragma unroll
-            for (int k = 0; k <= 2 * kR; ++k) {
-                const float w = taps.w[k], uu = u[j + k], vv = v[j + k];
-                a = fmaf(w, uu, a);
-                b = fmaf(w, vv, b);
-                aa = fmaf(w * uu, uu, aa);
-                bb = fmaf(w * vv, vv, bb);
-                ab = fmaf(w * uu, vv, ab);
+        for (int j = 0; j < kSeg; ++j) a[j] = b[j] = aa[j] = bb[j] = ab[j] = 0.0f;
+#pragma unroll
+        for (int p = 0; p < kSpan; p += 2) {
+            const float4 e = *reinterpret_cast<const float4 *>(&sxy[r][c0 + p]);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float x = h ? e.z : e.x, y = h ? e.w : e.y;
+                const float xx = x * x, yy = y * y, xy = x * y;
+#pragma unroll
+                for (int j = 0; j < kSeg; ++j) {
+                    const int k = p + h - j;
+                    if (k < 0 || k >= kW) continue;
+                    const float w = taps.w[k];
+                    a[j] = fmaf(w, x, a[j]);
+                    b[j] = fmaf(w, y, b[j]);
+                    aa[j] = fmaf(w, xx, aa[j]);
+                    bb[j] = fmaf(w, yy, bb[j]);
+                    ab[j] = fmaf(w, xy, ab[j]);
+                }
             }
-            hq[r][c0 + j] = make_float4(a, b, aa, bb);
-            hxy[r][c0 + j] = ab;
+        }
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) {
+            hq[r][c0 + j] = make_float4(a[j], b[j], aa[j], bb[j]);
+            hxy[r][c0 + j] = ab[j];
         }
     }
     __syncthreads();
     double s_val = 0.0;
-    if (threadIdx.x < kColItems) {
-        const int c = threadIdx.x % kT, r0 = 2 * (threadIdx.x / kT);
-        float4 q[2 * kR + 2];
-        float e[2 * kR + 2];
+    {
+        const int c = threadIdx.x % kT, r0 = kSeg * (threadIdx.x / kT);
+        float mx[kSeg], my[kSeg], exx[kSeg], eyy[kSeg], exy[kSeg];
 #pragma unroll
-        for (int k = 0; k < 2 * kR + 2; ++k) {
-            q[k] = hq[r0 + k][c];
-            e[k] = hxy[r0 + k][c];
-        }
-        float *P = part + 9 * (size_t)V.pix_base + (size_t)ch * 3 * HW;
+        for (int j = 0; j < kSeg; ++j) mx[j] = my[j] = exx[j] = eyy[j] = exy[j] = 0.0f;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            float mx = 0.0f, my = 0.0f, exx = 0.0f, eyy = 0.0f, exy = 0.0f;
+        for (int p = 0; p < kSpan; ++p) {
+            const float4 q = hq[r0 + p][c];
+            const float e = hxy[r0 + p][c];
 #pragma unroll
-            for (int k = 0; k <= 2 * kR; ++k) {
+            for (int j = 0; j < kSeg; ++j) {
+                const int k = p - j;
+                if (k < 0 || k >= kW) continue;
                 const float w = taps.w[k];
-                mx = fmaf(w, q[j + k].x, mx);
-                my = fmaf(w, q[j + k].y, my);
-                exx = fmaf(w, q[j + k].z, exx);
-                eyy = fmaf(w, q[j + k].w, eyy);
-                exy = fmaf(w, e[j + k], exy);
+                mx[j] = fmaf(w, q.x, mx[j]);
+                my[j] = fmaf(w, q.y, my[j]);
+                exx[j] = fmaf(w, q.z, exx[j]);
+                eyy[j] = fmaf(w, q.w, eyy[j]);
+                exy[j] = fmaf(w, e, exy[j]);
             }
-            const int x = x0 + c, y = y0 + r0 + j;
-            if (x < V.width && y < V.height) {
-                const float A = 2.0f * mx * my + kC1;
-                const float B = 2.0f * (exy - mx * my) + kC2;
-                const float C = mx * mx + my * my + kC1;
-                const float D = (exx - mx * mx) + (eyy - my * my) + kC2;
-                const float rC = __builtin_amdgcn_rcpf(C), rD = __builtin_amdgcn_rcpf(D);
-                const float rCD = rC * rD;
-                const float S = A * B * rCD;
-                const size_t o = (size_t)y * V.width + x;
-                P[o] = 2.0f * my * (B - A) * rCD - 2.0f * mx * S * rC + 2.0f * mx * S * rD;
-                P[o + HW] = -S * rD;
-                P[o + 2 * HW] = 2.0f * A * rCD;
-                s_val += (double)S;
-            }
+        }
+        float *P = part + 9 * (size_t)V.pix_base + (size_t)tl.ch * 3 * HW;
+        const int x = tl.x0 + c;
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) {
+            const int y = tl.y0 + r0 + j;
+            if (x >= V.width || y >= V.height) continue;
+            const float A = 2.0f * mx[j] * my[j] + kC1;
+            const float B = 2.0f * (exy[j] - mx[j] * my[j]) + kC2;
+            const float C = mx[j] * mx[j] + my[j] * my[j] + kC1;
+            const float D = (exx[j] - mx[j] * mx[j]) + (eyy[j] - my[j] * my[j]) + kC2;
+            const float rC = __builtin_amdgcn_rcpf(C), rD = __builtin_amdgcn_rcpf(D);
+            const float rCD = rC * rD;
+            const float S = A * B * rCD;
+            const size_t o = (size_t)y * V.width + x;
+            P[o] = 2.0f * my[j] * (B - A) * rCD - 2.0f * mx[j] * S * rC + 2.0f * mx[j] * S * rD;
+            P[o + HW] = -S * rD;
+            P[o + 2 * HW] = 2.0f * A * rCD;
+            s_val += (double)S;
         }
     }
     // tile sum of S, weighted lambda / (V 3 H W) = lambda * inv_norm
@@ -153,76 +191,102 @@ k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s_val;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double a = 0.0;
-        for (int w = 0; w < kT * kT / 64; ++w) a += red[w];
-        tile_sum[3 * (size_t)t_local + ch] = a * (double)lambda * (double)V.inv_norm;
+        double acc = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) acc += red[w];
+        tile_sum[3 * (size_t)tl.t_local + tl.ch] = acc * (double)lambda * (double)V.inv_norm;
     }
 }
 
-__global__ void __launch_bounds__(kT *kT)
+__global__ void __launch_bounds__(kThreads)
 k_ssim_bwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const float *__restrict__ img,
            const float *__restrict__ tgt, const float *__restrict__ part, float *__restrict__ dLdC,
            float lambda, Taps taps) {
-    __shared__ __align__(16) float4 sp[kH][kH];                // the three map derivatives (w unused)
-    __shared__ __align__(16) float4 hs[kH][kT];                // their row sums
-    const uint32_t nt = gridDim.x / 3;
-    const uint32_t item = xcd_order(blockIdx.x, gridDim.x);
-    const int ch = (int)(item / nt);
-    const uint32_t t = t_lo + (item - (uint32_t)ch * nt);
-    const ViewDev &V = views[view_of_ssim_tile(views, n_views, t)];
-    const uint32_t lt = t - V.ssim_tile_base;
-    const int ntx = (V.width + kT - 1) / kT;
-    const int x0 = (int)(lt % (uint32_t)ntx) * kT, y0 = (int)(lt / (uint32_t)ntx) * kT;
+    __shared__ __align__(16) float4 sp[kH][kH];    // the three map derivatives (w unused)
+    __shared__ __align__(16) float4 hs[kH][kT];    // their row sums
+    const SsimTile tl = ssim_tile(views, n_views, t_lo);
+    const ViewDev &V = *tl.V;
     const size_t HW = (size_t)V.width * V.height;
-    const float *P = part + 9 * (size_t)V.pix_base + (size_t)ch * 3 * HW;
-    for (int i = threadIdx.x; i < kH * kH; i += kT * kT) {
-        const int r = i / kH, c = i % kH;
-        const int yy = y0 + r - kR, xx = x0 + c - kR;
-        const bool in = xx >= 0 && xx < V.width && yy >= 0 && yy < V.height;
-        const size_t o = (size_t)yy * V.width + xx;
-        sp[r][c] = in ? make_float4(P[o], P[o + HW], P[o + 2 * HW], 0.0f) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const float *P = part + 9 * (size_t)V.pix_base + (size_t)tl.ch * 3 * HW;
+    {
+        // all of a thread's loads in flight before its LDS stores
+        float4 v[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int i = threadIdx.x + u * kThreads;
+            const int r = i / kH, c = i - r * kH;
+            const int yy = tl.y0 + r - kR, xx = tl.x0 + c - kR;
+            const bool in = i < kH * kH && xx >= 0 && xx < V.width && yy >= 0 && yy < V.height;
+            const size_t o = in ? (size_t)yy * V.width + xx : 0;
+            v[u] = in ? make_float4(P[o], P[o + HW], P[o + 2 * HW], 0.0f) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int i = threadIdx.x + u * kThreads;
+            if (i < kH * kH) (&sp[0][0])[i] = v[u];
+        }
     }
     __syncthreads();
-    if (threadIdx.x < kRowItems) {
-        const int r = threadIdx.x / (kT / 2), c0 = 2 * (threadIdx.x % (kT / 2));
-        float4 e[2 * kR + 2];
+    for (int it = threadIdx.x; it < kRowItems; it += kThreads) {
+        const int r = it / (kT / kSeg), c0 = kSeg * (it % (kT / kSeg));
+        float a[kSeg], b[kSeg], g[kSeg];
 #pragma unroll
-        for (int k = 0; k < 2 * kR + 2; ++k) e[k] = sp[r][c0 + k];
+        for (int j = 0; j < kSeg; ++j) a[j] = b[j] = g[j] = 0.0f;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            float a = 0.0f, b = 0.0f, g = 0.0f;
+        for (int p = 0; p < kSpan; ++p) {
+            const float4 e = sp[r][c0 + p];
 #pragma unroll
-            for (int k = 0; k <= 2 * kR; ++k) {
+            for (int j = 0; j < kSeg; ++j) {
+                const int k = p - j;
+                if (k < 0 || k >= kW) continue;
                 const float w = taps.w[k];
-                a = fmaf(w, e[j + k].x, a);
-                b = fmaf(w, e[j + k].y, b);
-                g = fmaf(w, e[j + k].z, g);
+                a[j] = fmaf(w, e.x, a[j]);
+                b[j] = fmaf(w, e.y, b[j]);
+                g[j] = fmaf(w, e.z, g[j]);
             }
-            hs[r][c0 + j] = make_float4(a, b, g, 0.0f);
         }
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) hs[r][c0 + j] = make_float4(a[j], b[j], g[j], 0.0f);
     }
     __syncthreads();
-    if (threadIdx.x >= kColItems) return;
-    const int c = threadIdx.x % kT, r0 = 2 * (threadIdx.x / kT);
-    float4 q[2 * kR + 2];
+    const int c = threadIdx.x % kT, r0 = kSeg * (threadIdx.x / kT);
+    const int x = tl.x0 + c;
+    // this thread's pixels: their image, target and dL/dC loads go out
+    // before the column pass
+    size_t o[kSeg];
+    float xi[kSeg], ti[kSeg], gi[kSeg];
 #pragma unroll
-    for (int k = 0; k < 2 * kR + 2; ++k) q[k] = hs[r0 + k][c];
+    for (int j = 0; j < kSeg; ++j) {
+        const int y = tl.y0 + r0 + j;
+        const bool in = x < V.width && y < V.height;
+        o[j] = in ? 3 * (size_t)V.pix_base + (size_t)tl.ch * HW + (size_t)y * V.width + x : 0;
+        xi[j] = in ? img[o[j]] : 0.0f;
+        ti[j] = in ? tgt[o[j]] : 0.0f;
+        gi[j] = in ? dLdC[o[j]] : 0.0f;
+    }
+    float a[kSeg], b[kSeg], g[kSeg];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        float a = 0.0f, b = 0.0f, g = 0.0f;
+    for (int j = 0; j < kSeg; ++j) a[j] = b[j] = g[j] = 0.0f;
 #pragma unroll
-        for (int k = 0; k <= 2 * kR; ++k) {
+    for (int p = 0; p < kSpan; ++p) {
+        const float4 q = hs[r0 + p][c];
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) {
+            const int k = p - j;
+            if (k < 0 || k >= kW) continue;
             const float w = taps.w[k];
-            a = fmaf(w, q[j + k].x, a);
-            b = fmaf(w, q[j + k].y, b);
-            g = fmaf(w, q[j + k].z, g);
+            a[j] = fmaf(w, q.x, a[j]);
+            b[j] = fmaf(w, q.y, b[j]);
+            g[j] = fmaf(w, q.z, g[j]);
         }
-        const int x = x0 + c, y = y0 + r0 + j;
-        if (x >= V.width || y >= V.height) continue;
-        const size_t o = 3 * (size_t)V.pix_base + (size_t)ch * HW + (size_t)y * V.width + x;
+    }
+    if (x >= V.width) return;
+    const float scale = lambda * V.inv_norm;
+#pragma unroll
+    for (int j = 0; j < kSeg; ++j) {
+        if (tl.y0 + r0 + j >= V.height) continue;
         // d/dC of lambda (1 - SSIM_v) / V with SSIM_v = sum S / (3 H W):
         // -lambda inv_norm (W*Sm + 2 x W*Sxx + y W*Sxy), inv_norm = 1 / (V 3 H W)
-        dLdC[o] -= lambda * V.inv_norm * (a + 2.0f * img[o] * b + tgt[o] * g);
+        dLdC[o[j]] = gi[j] - scale * (a[j] + 2.0f * xi[j] * b[j] + ti[j] * g[j]);
     }
 }
 
@@ -259,9 +323,9 @@ k_ssim_final(const double *__restrict__ sums, double lambda, double *__restrict_
 
 Taps window_taps() {
     Taps t;
-    double w[2 * kR + 1], sum = 0.0;
+    double w[kW], sum = 0.0;
     for (int k = -kR; k <= kR; ++k) sum += (w[k + kR] = std::exp(-(double)(k * k) / (2.0 * 1.5 * 1.5)));
-    for (int k = 0; k <= 2 * kR; ++k) t.w[k] = (float)(w[k] / sum);
+    for (int k = 0; k < kW; ++k) t.w[k] = (float)(w[k] / sum);
     return t;
 }
 
@@ -275,21 +339,21 @@ void launch_ssim(hipStream_t s, const swgs_plan &p, uint8_t *ws, int view_lo, in
                  const float *targets, float lambda) {
     if (!images || !targets) return;   // callers always pass both (the window step renders into the workspace)
     const uint32_t t_lo = p.vdev[view_lo].ssim_tile_base;
-    const uint32_t t_hi = view_hi < (int)p.views.size() ? p.vdev[view_hi].ssim_tile_base : (uint32_t)p.T16;
+    const uint32_t t_hi = view_hi < (int)p.views.size() ? p.vdev[view_hi].ssim_tile_base : (uint32_t)p.Tssim;
     if (t_hi <= t_lo) return;
     const dim3 grid(3 * (t_hi - t_lo));
     double *tsum = wsp<double>(ws, p, WB_SSIM_SUM);
-    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(kT * kT), 0, s, wsp<ViewDev>(ws, p, WB_VIEWS), (int)p.views.size(),
+    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(kThreads), 0, s, wsp<ViewDev>(ws, p, WB_VIEWS), (int)p.views.size(),
                        t_lo, images, targets, wsp<float>(ws, p, WB_SSIM_PART), tsum + 3 * (size_t)t_lo, lambda,
                        window_taps());
-    hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(kT * kT), 0, s, wsp<ViewDev>(ws, p, WB_VIEWS), (int)p.views.size(),
+    hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(kThreads), 0, s, wsp<ViewDev>(ws, p, WB_VIEWS), (int)p.views.size(),
                        t_lo, images, targets, wsp<float>(ws, p, WB_SSIM_PART), wsp<float>(ws, p, WB_DLDC), lambda,
                        window_taps());
 }
 
 void launch_ssim_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, float lambda) {
     double *tsum = wsp<double>(ws, p, WB_SSIM_SUM);
-    const int n = 3 * (int)p.T16;
+    const int n = 3 * (int)p.Tssim;
     double *sums = tsum + n;
     hipLaunchKernelGGL(k_ssim_partial, dim3(kSumBlocks), dim3(256), 0, s, tsum, n, sums);
     hipLaunchKernelGGL(k_ssim_final, dim3(1), dim3(256), 0, s, sums, (double)lambda, wsp<double>(ws, p, WB_STATS));

@@ -72,7 +72,7 @@ struct Layout {
 // tiles, pixels, pair capacity, pool slots, optimisable slots, window set,
 // live-list entries.
 struct LayoutDims {
-    size_t V = 0, G = 0, R = 0, T = 0, P = 0, cap = 0, S = 0, NG = 0, nA = 0, n_list = 0, T16 = 0;
+    size_t V = 0, G = 0, R = 0, T = 0, P = 0, cap = 0, S = 0, NG = 0, nA = 0, n_list = 0, Tssim = 0;
     bool forward_only = false;
 };
 
@@ -110,7 +110,7 @@ struct swgs_plan {
     std::vector<int32_t> group_views;             // view indices ordered by group
     uint32_t n_A = 0;                             // |A|
     uint32_t list_A_base = 0;
-    int64_t R = 0, P = 0, T = 0, T16 = 0;     // records, pixels, tiles, 16x16 SSIM tiles
+    int64_t R = 0, P = 0, T = 0, Tssim = 0;   // records, pixels, tiles, SSIM tiles
     int tile_key_bits = 1;
     int loss_blocks = 0;
     swgs::Layout lay;

@@ -587,10 +587,11 @@ def test_window_step_end_to_end_loss_matches_oracle(sw, ctx):
 def test_dssim_term_and_image_gradient_match_oracle(sw, ctx, mode):
     """The D-SSIM image term (lambda 0.2) and the full dL/dC it leaves for the
     backward, on views of mixed and ragged sizes (down to smaller than the
-    11x11 window), in every launch structure."""
+    11x11 window; 100x75 has interior SSIM tiles whose halo reaches into
+    neighbours on every side), in every launch structure."""
     say("dssim", mode)
     pool, _ = tiny(n=900)
-    views = S.ring_views([0, 1], 2, 0, 0, sizes=[(64, 48), (37, 23)]) + S.ring_views([2], 1, 7, 5)
+    views = S.ring_views([0, 1], 3, 0, 0, sizes=[(64, 48), (37, 23), (100, 75)]) + S.ring_views([2], 1, 7, 5)
     tgt_h = S.random_images(views, 12)
     dp, pl = plan_for(sw, ctx, pool, views)
     m = {"batched": sw.SWGS_MODE_BATCHED, "plain": sw.SWGS_MODE_PLAIN, "graph": sw.SWGS_MODE_GRAPH}[mode]
