@@ -138,13 +138,22 @@ def main():
         cfg = swgs.step_cfg(mode=mode, **cfg_base)
         stats = torch.zeros(8, dtype=torch.float64, device=dev)
         step = 0
-        for _ in range(args.warmup):
+        counts = None
+        for w in range(args.warmup):
+            # the batched form's last warm-up step counts the blend pairs (in
+            # the forward's counting build); the timed steps run uncounted
+            count = mode_name == "batched" and w == args.warmup - 1
+            if count:
+                plan.set_timing(swgs.SWGS_TIMING_COUNT)
             plan.window_step(cfg, targets, step + 1, step, 2, stats=stats)
+            if count:
+                counts = plan.timing()[1]
+                plan.set_timing(0)
             step += 1
         torch.cuda.synchronize()
         timing = None
         if mode_name == "batched":
-            plan.set_timing(True)
+            plan.set_timing(swgs.SWGS_TIMING_EVENTS)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(args.steps):
@@ -153,8 +162,8 @@ def main():
         torch.cuda.synchronize()
         el = time.perf_counter() - t
         if mode_name == "batched":
-            timing = plan.timing()
-            plan.set_timing(False)
+            timing = (plan.timing()[0], counts)
+            plan.set_timing(0)
         st = stats.cpu().numpy()
         if st[6] != 0:
             raise RuntimeError(f"{mode_name}: pair capacity overflow")
@@ -203,17 +212,21 @@ def main():
     if tune_table:
         out["autotune_ms_fwd_bwd"] = {f"{t[0]}x{t[1]}/lds{l}": ms for t, l, ms in tune_table}
     if "batched" in results and results["batched"]["timing"]:
-        tm, (ev_f, ev_b, n_bl) = results["batched"]["timing"]
+        tm, counts = results["batched"]["timing"]
         per_step = {k: round(v[0] / max(1, args.steps), 4) for k, v in tm.items()}
         out["kernel_ms_per_step"] = per_step
         dom = max(tm, key=lambda k: tm[k][0])
         n_launch = max(1, tm[dom][1])
         avg_s = tm[dom][0] / n_launch / 1e3
-        blend_work = {"blend_fwd": (ev_f * FLOPS_EVAL + n_bl * FLOPS_FWD_BLEND) / max(1, tm["blend_fwd"][1]),
-                      "blend_bwd": (ev_b * FLOPS_EVAL + n_bl * FLOPS_BWD_BLEND) / max(1, tm["blend_bwd"][1])}
-        out["blend_pairs_per_step"] = {"fwd_evaluated": ev_f // args.steps, "bwd_evaluated": ev_b // args.steps,
-                                       "blended": n_bl // args.steps}
-        if dom in ("blend_fwd", "blend_bwd"):
+        blend_work = {}
+        if counts is not None:
+            # pairs of one step; launches per step from the timed run
+            ev_f, ev_b, n_bl = counts
+            per = lambda k: max(1, tm[k][1]) / max(1, args.steps)
+            blend_work = {"blend_fwd": (ev_f * FLOPS_EVAL + n_bl * FLOPS_FWD_BLEND) / per("blend_fwd"),
+                          "blend_bwd": (ev_b * FLOPS_EVAL + n_bl * FLOPS_BWD_BLEND) / per("blend_bwd")}
+            out["blend_pairs_per_step"] = {"fwd_evaluated": ev_f, "bwd_evaluated": ev_b, "blended": n_bl}
+        if dom in blend_work:
             ach = blend_work[dom] / avg_s / 1e12
             out["roofline"] = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": PEAK_FP32_NONPACKED,
                                "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_NONPACKED, 4),

@@ -243,23 +243,26 @@ swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *plan, void *workspace
                              int64_t adam_t, uint64_t step, uint64_t seed, double *stats);
 
 /* ------------------------------------------------------------- timing
- * Measurement support.  When timing is on, every launch of a kernel class
- * made by the eager modes (not inside a captured graph) is bracketed by HIP
- * events recorded on the context stream, and the blend kernels count the
- * (pixel, list entry) pairs they evaluate.  swgs_plan_set_timing
- * synchronises, resets the records and switches timing on (on != 0) or off.
- * swgs_plan_timing synchronises, returns per class the summed kernel time
- * (ms[9], host) and the number of bracketed launches (launches[9], host),
- * and, if evals (host uint64[3]) is not NULL, the (pixel, list entry) pairs
- * evaluated by the forward [0] and the backward [1] blend and the pairs the
- * forward blended [2] (the backward differentiates exactly those); then
- * resets.  Classes: 0 gating,
+ * Measurement support for the eager modes (nothing is recorded inside a
+ * captured graph).  swgs_plan_set_timing synchronises, resets the records
+ * and sets `flags`: SWGS_TIMING_EVENTS brackets every launch of a kernel
+ * class with HIP events on the context stream; SWGS_TIMING_COUNT makes the
+ * blend kernels count the (pixel, list entry) pairs they evaluate (the
+ * forward then runs its counting build, a few instructions per entry
+ * slower, so time and count in separate runs); 0 switches both off; other
+ * bits are rejected.  swgs_plan_timing synchronises, returns per class the
+ * summed kernel time (ms[9], host) and the number of bracketed launches
+ * (launches[9], host), and, if evals (host uint64[3]) is not NULL, the
+ * (pixel, list entry) pairs evaluated by the forward [0] and the backward
+ * [1] blend and the pairs the forward blended [2] (the backward
+ * differentiates exactly those); then resets.  Classes: 0 gating,
  * 1 preprocess, 2 depth sort + pair emission + tile sort + ranges,
  * 3 forward blend, 4 backward blend, 5 record-gradient reduce + backward
  * preprocess, 6 Adam + SGLD,
  * 7 relocation, 8 D-SSIM (forward and gradient). */
+enum { SWGS_TIMING_EVENTS = 1, SWGS_TIMING_COUNT = 2 };
 swgs_status swgs_plan_set_timing(swgs_context *ctx, swgs_plan *plan, void *workspace, size_t ws_bytes,
-                                 int32_t on);
+                                 int32_t flags);
 swgs_status swgs_plan_timing(swgs_context *ctx, swgs_plan *plan, void *workspace, size_t ws_bytes,
                              double *ms, int64_t *launches, uint64_t *evals);
 

@@ -71,11 +71,11 @@ def tune(ctx: "swgs.Context", pool: "swgs.Pool", views, reps: int = 3, use_cache
         table.append((list(tile), lds, round(ms, 3)))
         if log:
             # one more pass with per-kernel events for the log
-            plan.set_timing(True)
+            plan.set_timing(swgs.SWGS_TIMING_EVENTS | swgs.SWGS_TIMING_COUNT)
             plan.forward()
             plan.backward(dl)
             tm, ev = plan.timing()
-            plan.set_timing(False)
+            plan.set_timing(0)
             per = " ".join(f"{k}={v[0]:.2f}" for k, v in tm.items() if v[1])
             log(f"autotune {tile[0]}x{tile[1]} lds {lds}: {ms:.2f} ms fwd+bwd [{per}] evals {ev[0]:.3g}/{ev[1]:.3g} "
                 f"blended {ev[2]:.3g}")

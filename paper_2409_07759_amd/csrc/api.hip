@@ -216,7 +216,7 @@ int tile_bits(int64_t T) {
 }
 
 unsigned long long *counters_of(swgs_plan &p, uint8_t *ws) {
-    return p.timing ? wsp<unsigned long long>(ws, p, WB_COUNTERS) : nullptr;
+    return p.counting ? wsp<unsigned long long>(ws, p, WB_COUNTERS) : nullptr;
 }
 
 // ------------------------------------------------------------ launch blocks
@@ -722,16 +722,17 @@ swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *p, void *workspace, s
             if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
             if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
             launch_set_step(s, reinterpret_cast<uint8_t *>(wsp<StepDev>(ws, *p, WB_STEP)), adam_t, step, seed);
-            const bool was_timing = p->timing;
-            p->timing = false;              // no event records inside a graph
+            const bool was_timing = p->timing, was_counting = p->counting;
+            p->timing = p->counting = false;   // no event records or counters inside a graph
             hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-            if (ce != hipSuccess) { p->timing = was_timing; return fail(ctx, SWGS_ERR_HIP, std::string("begin capture: ") + hipGetErrorString(ce)); }
+            if (ce != hipSuccess) { p->timing = was_timing; p->counting = was_counting; return fail(ctx, SWGS_ERR_HIP, std::string("begin capture: ") + hipGetErrorString(ce)); }
             launch_fill_f64(s, sdev, 0.0, 8);
             seq_window_batched(s, *p, ws, *cfg, targets, images);
             launch_advance_step(s, reinterpret_cast<uint8_t *>(wsp<StepDev>(ws, *p, WB_STEP)));
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(s, &g);
             p->timing = was_timing;
+            p->counting = was_counting;
             if (e != hipSuccess) return fail(ctx, SWGS_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
             p->graph = g;
             HIP_TRY(ctx, hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0));
@@ -773,12 +774,14 @@ swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *p, void *workspace, s
     return SWGS_OK;
 }
 
-swgs_status swgs_plan_set_timing(swgs_context *ctx, swgs_plan *p, void *workspace, size_t ws_bytes, int32_t on) {
+swgs_status swgs_plan_set_timing(swgs_context *ctx, swgs_plan *p, void *workspace, size_t ws_bytes, int32_t flags) {
     if (!ctx || !p) return SWGS_ERR_INVALID_ARG;
+    if (flags & ~(SWGS_TIMING_EVENTS | SWGS_TIMING_COUNT)) return fail(ctx, SWGS_ERR_INVALID_ARG, "unknown timing flags");
     swgs_status st = check_ws(ctx, p, workspace, ws_bytes);
     if (st) return st;
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    p->timing = on != 0;
+    p->timing = (flags & SWGS_TIMING_EVENTS) != 0;
+    p->counting = (flags & SWGS_TIMING_COUNT) != 0;
     for (int k = 0; k < TK_N; ++k) p->ev_used[k] = 0;
     launch_fill_u32(ctx->stream, reinterpret_cast<uint32_t *>(wsp<unsigned long long>(static_cast<uint8_t *>(workspace), *p, WB_COUNTERS)), 0, 2 * 1024);
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));

@@ -123,7 +123,7 @@ __device__ __forceinline__ int view_of_tile(const ViewDev *views, int n_views, u
     return a;
 }
 
-template <int TW, int TH, int BATCH>
+template <int TW, int TH, int BATCH, bool COUNT>
 __global__ void __launch_bounds__(TW *TH)
 k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_val,
             const float4 *__restrict__ splat, const ViewDev *__restrict__ views,
@@ -152,11 +152,11 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     const float fx = (float)x, fy = (float)y;
     const uint2 rg = ranges[tile];
     const uint32_t n = rg.y - rg.x;
-    uint32_t nblend = 0;
 
     float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
     uint32_t last = 0;
-    uint32_t stop_at = inside ? n : 0;   // list entries this pixel evaluates
+    uint32_t stop_at = inside ? n : 0;   // list entries this pixel evaluates (counted builds)
+    uint32_t nblend = 0;                 // entries it blends (counted builds)
     bool done = !inside;
     for (uint32_t b0 = 0; b0 < n; b0 += BATCH) {
         if (__syncthreads_and(done)) break;
@@ -178,21 +178,25 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         // would take T below 1e-4 (that splat is not blended)
         for (int i = 0; i < cnt; ++i) {
             const int k = CULL ? (int)slist[CULL ? wave : 0][i] : i;
+            const uint32_t idx = b0 + (uint32_t)k + 1;
             const Px e = eval_splat(fx, fy, sa[k], sb[k]);
             const float alpha = fminf(0.99f, e.og);
-            const float Tn = T * (1.0f - alpha);
+            const float w0 = alpha * T;
+            const float Tn = __fsub_rn(T, w0);             // T (1 - alpha), sharing alpha T
             const bool pass = !done && alpha >= (1.0f / 255.0f);
             const bool stop = pass && Tn < 1e-4f;
             const bool use = pass && !stop;
-            const float w = use ? alpha * T : 0.0f;
+            const float w = use ? w0 : 0.0f;
             const float4 c = sc[k];
             c0 = fmaf(c.x, w, c0);
             c1 = fmaf(c.y, w, c1);
             c2 = fmaf(c.z, w, c2);
             T = use ? Tn : T;
-            last = use ? b0 + (uint32_t)k + 1 : last;
-            nblend += use ? 1u : 0u;
-            stop_at = stop ? b0 + (uint32_t)k + 1 : stop_at;
+            last = use ? idx : last;
+            if (COUNT) {
+                stop_at = stop ? idx : stop_at;
+                nblend += use ? 1u : 0u;
+            }
             done = done || stop;
         }
     }
@@ -219,7 +223,7 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             sq = d0 * d0 + d1 * d1 + d2 * d2;
         }
     }
-    if (counters) {
+    if (COUNT) {
         if (threadIdx.x == 0) { cnt_evals = 0; cnt_blend = 0; }
         __syncthreads();
         atomicAdd(&cnt_evals, (unsigned long long)stop_at);
@@ -602,7 +606,8 @@ k_pair_grad_reduce(const uint32_t *__restrict__ order, const uint32_t *__restric
 template <int TW, int TH, int BATCH>
 void fwd_launch(hipStream_t s, const swgs_plan &p, uint8_t *ws, float *images, const float *targets,
                 uint32_t tile_lo, uint32_t tile_hi, unsigned long long *counters, float l1_weight) {
-    hipLaunchKernelGGL((k_blend_fwd<TW, TH, BATCH>), dim3(tile_hi - tile_lo), dim3(TW * TH), 0, s,
+    auto kern = counters ? k_blend_fwd<TW, TH, BATCH, true> : k_blend_fwd<TW, TH, BATCH, false>;
+    hipLaunchKernelGGL(kern, dim3(tile_hi - tile_lo), dim3(TW * TH), 0, s,
                        wsp<uint2>(ws, p, WB_TILE_RANGE), wsp<uint32_t>(ws, p, WB_PAIR_VAL),
                        wsp<float4>(ws, p, WB_SPLAT), wsp<ViewDev>(ws, p, WB_VIEWS),
                        (int)p.views.size(), tile_lo, images, wsp<float>(ws, p, WB_T_FINAL),

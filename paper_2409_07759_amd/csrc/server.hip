@@ -223,6 +223,7 @@ std::string launch_lane(swgs_server *s, Lane &L, size_t cap) {
     p.pair_cap = (int64_t)cap;
     p.forward_only = true;
     p.timing = false;
+    p.counting = false;
     std::string err = plan_geometry(p, views.data(), V, frames, vgroup, live, 0);
     if (!err.empty()) return err;
     for (size_t g = 0; g < frames.size(); ++g) p.groups[g].list_base = s->list_base[frames[g]];

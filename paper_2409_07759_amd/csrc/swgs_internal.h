@@ -129,8 +129,10 @@ struct swgs_plan {
     // buffers that live outside the workspace (absolute device pointers; a
     // null entry means "at lay.off[] in the workspace")
     uint8_t *ext[swgs::WB_COUNT] = {};
-    // event timing of kernel classes (off unless enabled; never inside a graph)
+    // event timing of kernel classes and blend pair counters (off unless
+    // enabled; never inside a graph)
     bool timing = false;
+    bool counting = false;
     std::vector<hipEvent_t> ev[9];
     size_t ev_used[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 };

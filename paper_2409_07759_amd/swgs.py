@@ -25,6 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 SWGS_OK, SWGS_ERR_INVALID_ARG, SWGS_ERR_UNSUPPORTED, SWGS_ERR_WORKSPACE_TOO_SMALL, SWGS_ERR_CAPACITY, SWGS_ERR_HIP = range(6)
 SWGS_MODE_PLAIN, SWGS_MODE_BATCHED, SWGS_MODE_GRAPH = range(3)
+SWGS_TIMING_EVENTS, SWGS_TIMING_COUNT = 1, 2
 (SWGS_BUF_ACTIVE_LIST, SWGS_BUF_ACTIVE_COUNT, SWGS_BUF_RECORD_VIEW_BASE, SWGS_BUF_DEPTH_KEY, SWGS_BUF_TILE_COUNT,
  SWGS_BUF_RECT, SWGS_BUF_SPLAT, SWGS_BUF_PAIR_KEY, SWGS_BUF_PAIR_VAL, SWGS_BUF_PAIR_COUNT, SWGS_BUF_TILE_RANGE,
  SWGS_BUF_T_FINAL, SWGS_BUF_DLDC, SWGS_BUF_RECORD_GRAD, SWGS_BUF_DEPTH_ORDER) = range(15)
@@ -313,9 +314,10 @@ class Plan:
                                             ptr(targets), ptr(images), int(adam_t), int(step), int(seed),
                                             ptr(stats)))
 
-    def set_timing(self, on: bool):
+    def set_timing(self, flags: int):
+        """SWGS_TIMING_EVENTS | SWGS_TIMING_COUNT, or 0 (off)."""
         with self.ctx:
-            self.ctx.check(swgs_plan_set_timing(self.ctx.h, self.h, ptr(self.ws), self.ws_bytes, int(bool(on))))
+            self.ctx.check(swgs_plan_set_timing(self.ctx.h, self.h, ptr(self.ws), self.ws_bytes, int(flags)))
 
     def timing(self):
         """{class: (total ms, launches)} and (fwd evaluated, bwd evaluated, blended) pairs since the last reset."""

@@ -650,6 +650,35 @@ def test_invalid_arguments_are_rejected(sw, ctx):
     with pytest.raises(sw.SwgsError) as e:
         sw.Plan(ctx, dp, views, tile=(4, 4))
     assert e.value.status == sw.SWGS_ERR_UNSUPPORTED
+    with pytest.raises(sw.SwgsError) as e:
+        pl.set_timing(4)
+    assert e.value.status == sw.SWGS_ERR_INVALID_ARG
+
+
+def test_counted_forward_matches_uncounted(sw, ctx):
+    """The forward's counting build (timing flag COUNT) renders the same
+    bits as the uncounted one; its blended-pair count matches the oracle's
+    contributor counts (to 0.1%: a pixel whose skip/stop decision sits on a
+    threshold may count differently in FP32 and FP64) and the evaluated
+    count bounds it."""
+    say("counted forward")
+    pool, views = tiny(n=1500)
+    dp, pl = plan_for(sw, ctx, pool, views)
+    a = host(pl.forward()).copy()
+    pl.set_timing(sw.SWGS_TIMING_COUNT)
+    b = host(pl.forward()).copy()
+    _, (ev_f, ev_b, n_bl) = pl.timing()
+    pl.set_timing(0)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    P0 = pool.params.astype(np.float64)
+    evals = blended = 0
+    for v in views:
+        vis, rec, rect = O.preprocess(P0, 0, pool.start, pool.expire, v, 16, 16)
+        pix = np.arange(v.width * v.height)
+        _, _, cnt, _, _ = O.render_records(vis, rec, v, pix)
+        blended += int(cnt.sum())
+    say("counts", ev_f, ev_b, n_bl, "oracle blended", blended)
+    assert blended > 0 and abs(n_bl - blended) <= 1e-3 * blended and ev_f >= n_bl and ev_b == 0
 
 
 def test_extreme_shapes_tile_invariant_and_match_oracle(sw, ctx):
