@@ -20,8 +20,10 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kMaxDigitBits = 11;
+constexpr int kMaxDigitBits = 8;
 constexpr int kMaxBins = 1 << kMaxDigitBits;
+constexpr int kChunkRounds = 8;                   // rounds of kBlock elements per LDS chunk
+constexpr int kChunk = kBlock * kChunkRounds;
 
 __device__ __forceinline__ uint32_t resolve_n(const uint32_t *d_n, uint32_t n_fixed, uint32_t cap) {
     uint32_t n = d_n ? *d_n : n_fixed;
@@ -74,44 +76,43 @@ k_digit_scan(uint32_t *__restrict__ hist, int nblocks, uint32_t *__restrict__ to
     if (threadIdx.x == 0) totals[d] = carry;
 }
 
+// Stable scatter of one pass.  The block walks its range in chunks of
+// kChunk elements: a chunk histogram and its scan give every digit its run
+// inside the chunk; kChunkRounds rounds of kBlock elements (in order, so the
+// placement is stable) rank equal digits within a wave by ballot match
+// masks and put each element at its place in an LDS copy of the chunk
+// ordered by digit; the chunk is then written out run by run, so
+// consecutive threads write consecutive addresses of one digit's run.
 __global__ void __launch_bounds__(kBlock)
 k_scatter(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, const uint32_t *d_n,
           uint32_t n_fixed, uint32_t cap, int shift, int dbits, const uint32_t *__restrict__ hist,
           const uint32_t *__restrict__ totals, uint32_t *__restrict__ keys_out,
           uint32_t *__restrict__ vals_out) {
     const int bins = 1 << dbits;
-    __shared__ uint32_t base[kMaxBins];
-    __shared__ uint32_t wcnt[kWaves][kMaxBins];
+    __shared__ uint32_t gbase[kMaxBins];          // next global position of each digit for this block
+    __shared__ uint32_t coff[kMaxBins];           // start of each digit's run inside the chunk
+    __shared__ uint32_t ccnt[kMaxBins];           // elements of each digit placed so far in the chunk
+    __shared__ uint32_t wcnt[kWaves][kMaxBins];   // per-round, per-wave digit counts
     __shared__ uint32_t wsum[kWaves];
+    __shared__ uint32_t skey[kChunk], sval[kChunk];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
     // digit bases: exclusive prefix of the digit totals + this block's offset
     {
-        constexpr int per = kMaxBins / kBlock;
-        uint32_t loc[per];
-        uint32_t s = 0;
-        for (int k = 0; k < per; ++k) {
-            int d = threadIdx.x * per + k;
-            uint32_t v = d < bins ? totals[d] : 0;
-            loc[k] = s;
-            s += v;
-        }
-        uint32_t x = s;
+        const uint32_t v = (int)threadIdx.x < bins ? totals[threadIdx.x] : 0;
+        uint32_t x = v;
         for (int o = 1; o < 64; o <<= 1) {
-            uint32_t y = __shfl_up(x, o, 64);
+            const uint32_t y = __shfl_up(x, o, 64);
             if (lane >= o) x += y;
         }
         if (lane == 63) wsum[wave] = x;
         __syncthreads();
         uint32_t before = 0;
         for (int w = 0; w < wave; ++w) before += wsum[w];
-        before += x - s;
-        for (int k = 0; k < per; ++k) {
-            int d = threadIdx.x * per + k;
-            if (d < bins) base[d] = before + loc[k] + hist[(size_t)d * gridDim.x + blockIdx.x];
+        if ((int)threadIdx.x < bins) {
+            gbase[threadIdx.x] = before + x - v + hist[(size_t)threadIdx.x * gridDim.x + blockIdx.x];
+            for (int w = 0; w < kWaves; ++w) wcnt[w][threadIdx.x] = 0;
         }
-        for (int w = 0; w < kWaves; ++w)
-            for (int d = threadIdx.x; d < bins; d += kBlock) wcnt[w][d] = 0;
         __syncthreads();
     }
 
@@ -121,45 +122,81 @@ k_scatter(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, 
     const uint32_t hi = min(n, lo + L);
     const uint32_t mask = (uint32_t)bins - 1;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (uint32_t t0 = lo; t0 < hi; t0 += kBlock) {
-        const uint32_t i = t0 + threadIdx.x;
-        const bool ok = i < hi;
-        uint32_t k = 0, v = 0, d = 0;
-        if (ok) {
-            k = keys[i];
-            v = vals[i];
-            d = (k >> shift) & mask;
+    for (uint32_t c0 = lo; c0 < hi; c0 += kChunk) {
+        const uint32_t cn = min((uint32_t)kChunk, hi - c0);
+        uint32_t k[kChunkRounds], v[kChunkRounds], dg[kChunkRounds];
+#pragma unroll
+        for (int r = 0; r < kChunkRounds; ++r) {
+            const uint32_t i = (uint32_t)(r * kBlock) + threadIdx.x;
+            const bool ok = i < cn;
+            k[r] = ok ? keys[c0 + i] : 0u;
+            v[r] = ok ? vals[c0 + i] : 0u;
+            dg[r] = ok ? (k[r] >> shift) & mask : (uint32_t)bins;   // bins = no element
         }
-        // lanes holding the same digit
-        uint64_t peers = __ballot(ok);
-        for (int b = 0; b < dbits; ++b) {
-            uint64_t m = __ballot(ok && ((d >> b) & 1u));
-            peers &= ((d >> b) & 1u) ? m : ~m;
-        }
-        const uint32_t rank = (uint32_t)__popcll(peers & lt);
-        const bool leader = ok && ((peers & lt) == 0);
-        if (leader) wcnt[wave][d] = (uint32_t)__popcll(peers);
+        // chunk histogram and its exclusive scan
+        if ((int)threadIdx.x < bins) ccnt[threadIdx.x] = 0;
         __syncthreads();
-        if (ok) {
-            uint32_t pos = base[d] + rank;
-            for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
-            keys_out[pos] = k;
-            vals_out[pos] = v;
-        }
+#pragma unroll
+        for (int r = 0; r < kChunkRounds; ++r)
+            if (dg[r] < (uint32_t)bins) atomicAdd(&ccnt[dg[r]], 1u);
         __syncthreads();
-        if (leader) {
-            // the last wave's leader of each digit advances the base; every
-            // leader clears its own count afterwards
-            uint32_t tot = 0;
-            bool last = true;
-            for (int w = wave + 1; w < kWaves; ++w) last &= (wcnt[w][d] == 0);
-            if (last) {
-                for (int w = 0; w < kWaves; ++w) tot += wcnt[w][d];
-                base[d] += tot;
+        {
+            const uint32_t c = (int)threadIdx.x < bins ? ccnt[threadIdx.x] : 0;
+            uint32_t x = c;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o, 64);
+                if (lane >= o) x += y;
             }
+            if (lane == 63) wsum[wave] = x;
+            __syncthreads();
+            uint32_t before = 0;
+            for (int w = 0; w < wave; ++w) before += wsum[w];
+            if ((int)threadIdx.x < bins) {
+                coff[threadIdx.x] = before + x - c;
+                ccnt[threadIdx.x] = 0;
+            }
+            __syncthreads();
+        }
+        // stable placement, one round of kBlock elements at a time
+#pragma unroll
+        for (int r = 0; r < kChunkRounds; ++r) {
+            const uint32_t d = dg[r];
+            const bool ok = d < (uint32_t)bins;
+            uint64_t peers = __ballot(ok);
+            for (int b = 0; b < dbits; ++b) {
+                const uint64_t m = __ballot(ok && ((d >> b) & 1u));
+                peers &= ((d >> b) & 1u) ? m : ~m;
+            }
+            const uint32_t rank = (uint32_t)__popcll(peers & lt);
+            if (ok && (peers & lt) == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
+            __syncthreads();
+            if (ok) {
+                uint32_t pos = coff[d] + ccnt[d] + rank;
+                for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+                skey[pos] = k[r];
+                sval[pos] = v[r];
+            }
+            __syncthreads();
+            if ((int)threadIdx.x < bins) {
+                uint32_t t = 0;
+                for (int w = 0; w < kWaves; ++w) {
+                    t += wcnt[w][threadIdx.x];
+                    wcnt[w][threadIdx.x] = 0;
+                }
+                ccnt[threadIdx.x] += t;
+            }
+            __syncthreads();
+        }
+        // write the chunk out, run by run
+        for (uint32_t p = threadIdx.x; p < cn; p += kBlock) {
+            const uint32_t key = skey[p];
+            const uint32_t d = (key >> shift) & mask;
+            const uint32_t o = gbase[d] + (p - coff[d]);
+            keys_out[o] = key;
+            vals_out[o] = sval[p];
         }
         __syncthreads();
-        if (leader) wcnt[wave][d] = 0;
+        if ((int)threadIdx.x < bins) gbase[threadIdx.x] += ccnt[threadIdx.x];
         __syncthreads();
     }
 }
