@@ -247,7 +247,8 @@ void seq_forward(hipStream_t s, swgs_plan &p, uint8_t *ws, int view, float *imag
         // emitted in that order stably by tile: (tile, depth, record) order
         radix_sort_pairs(s, wsp<uint32_t>(ws, p, WB_DEPTH_KEY) + rec_lo, wsp<uint32_t>(ws, p, WB_REC_IDX) + rec_lo,
                          wsp<uint32_t>(ws, p, WB_KEY_ALT) + rec_lo, wsp<uint32_t>(ws, p, WB_IDX_ALT) + rec_lo, nullptr,
-                         rec_hi - rec_lo, rec_hi - rec_lo, 32, hist, tot);
+                         rec_hi - rec_lo, rec_hi - rec_lo, 32, hist, tot, wsp<uint32_t>(ws, p, WB_TILE_COUNT),
+                         wsp<uint32_t>(ws, p, WB_PAIR_OFFSET));
         launch_pair_offsets(s, p, ws, rec_lo, rec_hi);
         launch_emit_pairs(s, p, ws, rec_lo, rec_hi);
         uint32_t *pc = wsp<uint32_t>(ws, p, WB_PAIR_COUNT);

@@ -183,39 +183,66 @@ k_preprocess(const float *__restrict__ params, int n_slots, int deg, const Group
     }
 }
 
-// pair emission in depth order: thread per sorted record
+// Pair emission in depth order.  A wave takes 64 consecutive records of
+// the depth order, whose pair slots form one contiguous stretch, and its
+// lanes write the stretch together: the record of a slot is the last of
+// the 64 whose first slot is at or below it (a binary search over the
+// lanes' offsets), and the slot's tile is the record's rect tile at the
+// slot's row-major index.  Stores are coalesced, and a record covering
+// many tiles spreads over the wave instead of holding it up.
 __global__ void __launch_bounds__(kBlock)
 k_emit_pairs(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ offsets,
-             const uint32_t *__restrict__ tile_count, const uint2 *__restrict__ rect,
+             const uint32_t *__restrict__ total_ptr, const uint2 *__restrict__ rect,
              const uint32_t *__restrict__ rec_view_base, int n_views, const ViewDev *__restrict__ views,
-             uint32_t lo, uint32_t hi, uint32_t cap, uint32_t *__restrict__ pair_key,
-             uint32_t *__restrict__ pair_val, uint32_t *__restrict__ pair_base) {
-    const uint32_t p = lo + blockIdx.x * kBlock + threadIdx.x;
-    if (p >= hi) return;
-    const uint32_t r = sorted_rec[p];
-    const uint32_t c = tile_count[r];
-    if (c == 0) return;
-    uint32_t off = offsets[p - lo];
-    // the record's pairs take slots off .. off + c - 1, its rect's tiles in
-    // row-major order (the backward finds a pair's slot from this base)
-    if (pair_base) pair_base[r] = off;
-    // view of record r: last view whose base <= r
-    int a = 0, b = n_views;
-    while (b - a > 1) {
-        int m = (a + b) >> 1;
-        if (rec_view_base[m] <= r) a = m; else b = m;
-    }
-    const ViewDev &V = views[a];
-    const uint2 rc = rect[r];
-    const int x0 = rc.x & 0xFFFF, y0 = rc.x >> 16, x1 = rc.y & 0xFFFF, y1 = rc.y >> 16;
-    for (int ty = y0; ty < y1; ++ty)
-        for (int tx = x0; tx < x1; ++tx) {
-            if (off < cap) {
-                pair_key[off] = V.tile_base + (uint32_t)(ty * V.tiles_x + tx);
-                pair_val[off] = r;
-            }
-            ++off;
+             uint32_t n, uint32_t cap, uint32_t *__restrict__ pair_key, uint32_t *__restrict__ pair_val,
+             uint32_t *__restrict__ pair_base) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t j0 = blockIdx.x * kBlock + (threadIdx.x & ~63u);   // the wave's first record
+    if (j0 >= n) return;                                                 // whole waves only
+    const uint32_t j = j0 + (uint32_t)lane;
+    const bool has = j < n;
+    const uint32_t total = *total_ptr;
+    const uint32_t off = has ? offsets[j] : total;
+    const uint32_t end = j0 + 64 < n ? offsets[j0 + 64] : total;
+    uint32_t r = 0, xy0 = 0, w = 1, tbase = 0, tiles_x = 1;
+    if (has) {
+        r = sorted_rec[j];
+        // view of record r: last view whose base <= r
+        int a = 0, b = n_views;
+        while (b - a > 1) {
+            const int m = (a + b) >> 1;
+            if (rec_view_base[m] <= r) a = m; else b = m;
         }
+        tbase = views[a].tile_base;
+        tiles_x = (uint32_t)views[a].tiles_x;
+        const uint2 rc = rect[r];
+        xy0 = rc.x;
+        w = max((rc.y & 0xFFFFu) - (rc.x & 0xFFFFu), 1u);
+        // the record's pairs take slots off .. off + count - 1 (the
+        // backward finds a pair's slot from this base)
+        if (pair_base) pair_base[r] = off;
+    }
+    const uint32_t start = __shfl(off, 0, 64);
+    for (uint32_t base = start; base < end; base += 64) {   // uniform trip count: all lanes shuffle
+        const uint32_t slot = base + (uint32_t)lane;
+        int l = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+            const uint32_t o = __shfl(off, l + step, 64);
+            if (o <= slot) l += step;
+        }
+        const uint32_t lr = __shfl(r, l, 64), lxy = __shfl(xy0, l, 64), lw = __shfl(w, l, 64);
+        const uint32_t lbase = __shfl(tbase, l, 64), ltx = __shfl(tiles_x, l, 64);
+        const uint32_t loc = slot - __shfl(off, l, 64);
+        uint32_t q = (uint32_t)((float)loc / (float)lw);       // loc / lw, corrected below
+        if (q * lw > loc) --q;
+        else if ((q + 1) * lw <= loc) ++q;
+        const uint32_t tx = (lxy & 0xFFFFu) + (loc - q * lw), ty = (lxy >> 16) + q;
+        if (slot < end && slot < cap) {
+            pair_key[slot] = lbase + ty * ltx + tx;
+            pair_val[slot] = lr;
+        }
+    }
 }
 
 __global__ void k_pair_total(const uint32_t *__restrict__ total, uint32_t cap, uint32_t *__restrict__ pair_count) {
@@ -288,12 +315,12 @@ void launch_preprocess(hipStream_t s, const swgs_plan &p, uint8_t *ws, int view_
 }
 
 void launch_pair_offsets(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi) {
-    // offsets of the records sorted by depth (positions rec_lo..rec_hi of the
-    // sorted index array), and the pair total + overflow flag
+    // the tile counts of the records in depth order (left in PAIR_OFFSET by
+    // the depth sort's last pass) become, in place, their first pair slots;
+    // then the pair total + overflow flag
     uint32_t *pc = wsp<uint32_t>(ws, p, WB_PAIR_COUNT);
-    exclusive_scan_gather_u32(s, wsp<uint32_t>(ws, p, WB_TILE_COUNT), wsp<uint32_t>(ws, p, WB_REC_IDX) + rec_lo,
-                              wsp<uint32_t>(ws, p, WB_PAIR_OFFSET), rec_hi - rec_lo, pc + 2,
-                              wsp<uint32_t>(ws, p, WB_SORT_TOTAL));
+    uint32_t *off = wsp<uint32_t>(ws, p, WB_PAIR_OFFSET);
+    exclusive_scan_u32(s, off, off, rec_hi - rec_lo, pc + 2, wsp<uint32_t>(ws, p, WB_SORT_TOTAL));
     hipLaunchKernelGGL(k_pair_total, dim3(1), dim3(1), 0, s, pc + 2, (uint32_t)p.pair_cap, pc);
 }
 
@@ -301,11 +328,10 @@ void launch_emit_pairs(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t 
     if (rec_hi <= rec_lo) return;
     const uint32_t n = rec_hi - rec_lo;
     hipLaunchKernelGGL(k_emit_pairs, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                       wsp<uint32_t>(ws, p, WB_REC_IDX), wsp<uint32_t>(ws, p, WB_PAIR_OFFSET),
-                       wsp<uint32_t>(ws, p, WB_TILE_COUNT), wsp<uint2>(ws, p, WB_RECT),
+                       wsp<uint32_t>(ws, p, WB_REC_IDX) + rec_lo, wsp<uint32_t>(ws, p, WB_PAIR_OFFSET),
+                       wsp<uint32_t>(ws, p, WB_PAIR_COUNT) + 2, wsp<uint2>(ws, p, WB_RECT),
                        wsp<uint32_t>(ws, p, WB_REC_VIEW_BASE), (int)p.views.size(), wsp<ViewDev>(ws, p, WB_VIEWS),
-                       rec_lo, rec_hi, (uint32_t)p.pair_cap, wsp<uint32_t>(ws, p, WB_PAIR_KEY),
-                       wsp<uint32_t>(ws, p, WB_PAIR_VAL),
+                       n, (uint32_t)p.pair_cap, wsp<uint32_t>(ws, p, WB_PAIR_KEY), wsp<uint32_t>(ws, p, WB_PAIR_VAL),
                        p.forward_only ? nullptr : wsp<uint32_t>(ws, p, WB_PAIR_BASE));
 }
 

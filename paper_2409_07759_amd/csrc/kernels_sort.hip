@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(kBlock)
 k_scatter(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, const uint32_t *d_n,
           uint32_t n_fixed, uint32_t cap, int shift, int dbits, const uint32_t *__restrict__ hist,
           const uint32_t *__restrict__ totals, uint32_t *__restrict__ keys_out,
-          uint32_t *__restrict__ vals_out) {
+          uint32_t *__restrict__ vals_out, const uint32_t *__restrict__ gsrc, uint32_t *__restrict__ gout) {
     const int bins = 1 << dbits;
     __shared__ uint32_t gbase[kMaxBins];          // next global position of each digit for this block
     __shared__ uint32_t coff[kMaxBins];           // start of each digit's run inside the chunk
@@ -194,6 +194,7 @@ k_scatter(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, 
             const uint32_t o = gbase[d] + (p - coff[d]);
             keys_out[o] = key;
             vals_out[o] = sval[p];
+            if (gout) gout[o] = gsrc[sval[p]];
         }
         __syncthreads();
         if ((int)threadIdx.x < bins) gbase[threadIdx.x] += ccnt[threadIdx.x];
@@ -249,8 +250,8 @@ k_scan_sums(uint32_t *__restrict__ sums, uint32_t nb, uint32_t *__restrict__ tot
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_scan_write(const uint32_t *__restrict__ in, const uint32_t *__restrict__ idx, uint32_t n,
-             const uint32_t *__restrict__ sums, uint32_t *__restrict__ out) {
+k_scan_write(const uint32_t *in, const uint32_t *__restrict__ idx, uint32_t n,
+             const uint32_t *__restrict__ sums, uint32_t *out) {   // in may equal out (in-place scan)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __shared__ uint32_t wsum[kWaves];
     uint32_t carry = sums[blockIdx.x];
@@ -278,7 +279,8 @@ k_scan_write(const uint32_t *__restrict__ in, const uint32_t *__restrict__ idx, 
 
 void radix_sort_pairs(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
                       uint32_t *vals_alt, const uint32_t *d_n, uint32_t n_fixed, uint32_t cap,
-                      int bits, uint32_t *hist, uint32_t *totals) {
+                      int bits, uint32_t *hist, uint32_t *totals, const uint32_t *gather_src,
+                      uint32_t *gather_out) {
     if (bits < 1) bits = 1;
     if (bits > 32) bits = 32;
     // smallest even pass count whose digits fit in kMaxDigitBits
@@ -295,8 +297,9 @@ void radix_sort_pairs(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *k
         hipLaunchKernelGGL(k_hist, dim3(kSortBlocks), dim3(kBlock), 0, s, ki, d_n, n_fixed, cap, shift, bins,
                            hist);
         hipLaunchKernelGGL(k_digit_scan, dim3(bins), dim3(kBlock), 0, s, hist, kSortBlocks, totals);
+        const bool last = p + 1 == passes;
         hipLaunchKernelGGL(k_scatter, dim3(kSortBlocks), dim3(kBlock), 0, s, ki, vi, d_n, n_fixed, cap, shift,
-                           w, hist, totals, ko, vo);
+                           w, hist, totals, ko, vo, last ? gather_src : nullptr, last ? gather_out : nullptr);
         shift += w;
         uint32_t *t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
@@ -305,8 +308,7 @@ void radix_sort_pairs(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *k
 
 void exclusive_scan_u32(hipStream_t s, const uint32_t *in, uint32_t *out, uint32_t n,
                         uint32_t *total_out, uint32_t *scratch) {
-    // scratch: at least ceil(n / kScanChunk) + 1 words; idx via the
-    // gather variant below
+    // scratch: at least ceil(n / kScanChunk) + 1 words; in may equal out
     const uint32_t nb = (n + kScanChunk - 1) / kScanChunk;
     if (nb == 0) {
         launch_fill_u32(s, total_out, 0, 1);
@@ -318,16 +320,5 @@ void exclusive_scan_u32(hipStream_t s, const uint32_t *in, uint32_t *out, uint32
                        out);
 }
 
-void exclusive_scan_gather_u32(hipStream_t s, const uint32_t *in, const uint32_t *idx, uint32_t *out,
-                               uint32_t n, uint32_t *total_out, uint32_t *scratch) {
-    const uint32_t nb = (n + kScanChunk - 1) / kScanChunk;
-    if (nb == 0) {
-        launch_fill_u32(s, total_out, 0, 1);
-        return;
-    }
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, in, idx, n, scratch);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, scratch, nb, total_out);
-    hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(kBlock), 0, s, in, idx, n, scratch, out);
-}
 
 }  // namespace swgs

@@ -154,14 +154,15 @@ void launch_tile_ranges(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t
 // Radix sort (kernels_sort.hip): stable LSD sort of (key, val) uint32 pairs,
 // n given on the device (*d_n, clamped to cap) over bits [0, bits).
 // On return the sorted data is in (keys, vals); alt buffers are scratch.
+// With gather_out, the last pass also writes gather_out[i] =
+// gather_src[vals[i]] for every sorted position i.
 void radix_sort_pairs(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
                       uint32_t *vals_alt, const uint32_t *d_n, uint32_t n_fixed, uint32_t cap,
-                      int bits, uint32_t *hist, uint32_t *totals);
+                      int bits, uint32_t *hist, uint32_t *totals, const uint32_t *gather_src = nullptr,
+                      uint32_t *gather_out = nullptr);
+// exclusive scan (in may equal out); *total_out = sum
 void exclusive_scan_u32(hipStream_t s, const uint32_t *in, uint32_t *out, uint32_t n,
                         uint32_t *total_out, uint32_t *scratch);
-// same over in[idx[i]]
-void exclusive_scan_gather_u32(hipStream_t s, const uint32_t *in, const uint32_t *idx, uint32_t *out,
-                               uint32_t n, uint32_t *total_out, uint32_t *scratch);
 
 // Blend (kernels_blend.hip)
 // counters (nullable): [0] pixel x list entries evaluated by the forward,
