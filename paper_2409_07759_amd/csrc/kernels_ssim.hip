@@ -37,6 +37,12 @@ constexpr int kRowItems = kH * (kT / kSeg);   // row pass: every staged row x 8 
 constexpr int kColItems = kT * (kT / kSeg);   // column pass: 32 columns x 8 segments (256)
 static_assert(kColItems == kThreads, "one column item per thread");
 constexpr int kStage = (kH * kH + kThreads - 1) / kThreads;   // staged elements per thread (7)
+// LDS row pitches: in the row pass consecutive lanes take consecutive rows,
+// so a row's pitch in dwords is kept an odd multiple of 4 and the 16-byte
+// accesses of 8 consecutive lanes fall on disjoint banks
+constexpr int kHP = kH;                // float2 staging: 84 dwords per row
+constexpr int kHP4 = kH + 1;           // float4 staging: 172 dwords per row
+constexpr int kTP = kT + 1;            // row sums: 132 dwords (float4) / 33 (float) per row
 constexpr float kC1 = 1e-4f, kC2 = 9e-4f;
 
 // 1D Gaussian weights (sigma 1.5, normalised), computed once on the host
@@ -84,9 +90,9 @@ __global__ void __launch_bounds__(kThreads)
 k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const float *__restrict__ img,
            const float *__restrict__ tgt, float *__restrict__ part, double *__restrict__ tile_sum, float lambda,
            Taps taps) {
-    __shared__ __align__(16) float2 sxy[kH][kH];   // (x, y) over the staged neighbourhood
-    __shared__ __align__(16) float4 hq[kH][kT];    // row sums of x, y, x^2, y^2
-    __shared__ float hxy[kH][kT];                  // row sums of x y
+    __shared__ __align__(16) float2 sxy[kH][kHP];  // (x, y) over the staged neighbourhood
+    __shared__ __align__(16) float4 hq[kH][kTP];   // row sums of x, y, x^2, y^2
+    __shared__ float hxy[kH][kTP];                 // row sums of x y
     __shared__ double red[kThreads / 64];
     const SsimTile tl = ssim_tile(views, n_views, t_lo);
     const ViewDev &V = *tl.V;
@@ -108,12 +114,12 @@ k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
             const int i = threadIdx.x + u * kThreads;
-            if (i < kH * kH) (&sxy[0][0])[i] = v[u];
+            if (i < kH * kH) sxy[i / kH][i % kH] = v[u];
         }
     }
     __syncthreads();
     for (int it = threadIdx.x; it < kRowItems; it += kThreads) {
-        const int r = it / (kT / kSeg), c0 = kSeg * (it % (kT / kSeg));
+        const int r = it % kH, c0 = kSeg * (it / kH);    // consecutive lanes: consecutive rows
         float a[kSeg], b[kSeg], aa[kSeg], bb[kSeg], ab[kSeg];
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) a[j] = b[j] = aa[j] = bb[j] = ab[j] = 0.0f;
@@ -201,8 +207,8 @@ __global__ void __launch_bounds__(kThreads)
 k_ssim_bwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const float *__restrict__ img,
            const float *__restrict__ tgt, const float *__restrict__ part, float *__restrict__ dLdC,
            float lambda, Taps taps) {
-    __shared__ __align__(16) float4 sp[kH][kH];    // the three map derivatives (w unused)
-    __shared__ __align__(16) float4 hs[kH][kT];    // their row sums
+    __shared__ __align__(16) float4 sp[kH][kHP4];  // the three map derivatives (w unused)
+    __shared__ __align__(16) float4 hs[kH][kTP];   // their row sums
     const SsimTile tl = ssim_tile(views, n_views, t_lo);
     const ViewDev &V = *tl.V;
     const size_t HW = (size_t)V.width * V.height;
@@ -222,12 +228,12 @@ k_ssim_bwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
             const int i = threadIdx.x + u * kThreads;
-            if (i < kH * kH) (&sp[0][0])[i] = v[u];
+            if (i < kH * kH) sp[i / kH][i % kH] = v[u];
         }
     }
     __syncthreads();
     for (int it = threadIdx.x; it < kRowItems; it += kThreads) {
-        const int r = it / (kT / kSeg), c0 = kSeg * (it % (kT / kSeg));
+        const int r = it % kH, c0 = kSeg * (it / kH);    // consecutive lanes: consecutive rows
         float a[kSeg], b[kSeg], g[kSeg];
 #pragma unroll
         for (int j = 0; j < kSeg; ++j) a[j] = b[j] = g[j] = 0.0f;
