@@ -282,16 +282,46 @@ swgs_status swgs_mature(swgs_context *ctx, const swgs_pool *pool, int32_t st,
 /* Bytes of a mature record for `count` Gaussians of SH degree d. */
 size_t swgs_record_bytes(int64_t count, int32_t sh_degree);
 
+/* ------------------------------------------------------------- codec
+ * The compact per-frame update (Sec. 5.2 Eq. 4, Sec. 5.6.2 and Table 6,
+ * Sec. 5.5): re-encode a mature record (`record`, device, version 1) into a
+ * version-2 record in `out` (device, capacity bytes) carrying per Gaussian
+ * only its mean, log-scale, rotation, opacity and SH DC term -- the higher
+ * SH bands are not streamed -- either in FP32 (enc SWGS_ENC_FP32, 56 bytes)
+ * or at Table 6's precisions (SWGS_ENC_Q: FP16 mean and log-scale saturated
+ * to +-65504, round to nearest even; 8-bit rotation code
+ * rint(c 127.5 + 127.5) of each component c of q/|q| in IEEE FP32 with the
+ * zero quaternion sent as the identity; 8-bit opacity code round(sigma 255)
+ * decided on the logit against the thresholds fl32(logit((k - 1/2)/255)),
+ * k = 1..255; SH DC in FP32: 29 bytes).  keep in [0, count) keeps the keep
+ * entries of largest opacity logit (ties to the lower entry) and marks the
+ * others empty (Sec. 5.5's tail-drop); keep < 0 keeps all.
+ * Layout (little endian): int32 header[16] = {magic 'SWGS', 2, st, count,
+ * kept, enc, swin, flags, slot0, birth0, start0, expire0, source SH degree,
+ * 0, 0, 0}; then, each array at a 16-byte boundary: [flags & 1] uint32
+ * slot[count], int32 birth[count], start[count], expire[count] (present
+ * unless every entry shares one lifespan and the slots are slot0 + k);
+ * [flags & 2] uint32 keep mask[ceil(count/32)] (bit k & 31 of word k >> 5);
+ * the kept entries' attributes in entry order, planar: mean[3][kept],
+ * scale[3][kept], quat[4][kept], opacity[kept], dc[3][kept].
+ * out == NULL: only *bytes_out (host) receives the size.  Synchronises. */
+enum { SWGS_ENC_FP32 = 1, SWGS_ENC_Q = 2 };
+swgs_status swgs_encode_update(swgs_context *ctx, const void *record, size_t record_bytes, int32_t enc,
+                               int64_t keep, void *out, size_t capacity, size_t *bytes_out);
+
 /* ------------------------------------------------------------- update
  * Algorithm 2's client-side update (Sec. 4.3): write the entries of a mature
- * record (device memory, record_bytes bytes, the layout swgs_mature writes)
- * into `pool`.  slot_base < 0: entry k goes to slot record.slot[k], the slot
+ * record (device memory, record_bytes bytes, the layout swgs_mature writes,
+ * or the compact layout of swgs_encode_update) into `pool`.  A compact
+ * record writes the five streamed attributes, zeroes the pool's higher SH
+ * rows, and gives entries the tail-drop removed the empty lifespan
+ * [birth, birth) (never drawn; parameters untouched).  slot_base < 0: entry k goes to slot record.slot[k], the slot
  * it was emitted from (Algorithm 2 replaces slice birth mod swin of the
  * client buffer, which is that slot range); slot_base >= 0: entry k goes to
  * slot slot_base + k (appending the update to a pool that keeps every frame
  * resident).  Parameters, start and expire, and birth if pool->birth is not
- * NULL, are overwritten.  Synchronises twice: to read and check the 32-byte
- * header (magic, version, SH degree, size) and, after the scatter, to check
+ * NULL, are overwritten.  Synchronises twice: to read and check the header
+ * (magic, version, SH degree of a full record, size) and, after the scatter, to check
  * that every entry's slot lies inside the pool (SWGS_ERR_INVALID_ARG names
  * how many did not; those entries are skipped, the others written).
  * *count_out (host, nullable) receives the entry count. */

@@ -860,6 +860,82 @@ swgs_status swgs_mature(swgs_context *ctx, const swgs_pool *pool, int32_t st, vo
     return SWGS_OK;
 }
 
+// version-2 (compact) records: header int32[16], see swgs_encode_update
+static swgs_status apply_update_v2(swgs_context *ctx, const swgs_pool *pool, const void *record, size_t record_bytes,
+                                   int64_t slot_base, int64_t *count_out) {
+    hipStream_t s = ctx->stream;
+    if (record_bytes < 64) return fail(ctx, SWGS_ERR_INVALID_ARG, "record shorter than its 64-byte header");
+    int32_t h[16];
+    HIP_TRY(ctx, hipMemcpyAsync(h, record, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (h[3] < 0 || h[4] < 0 || h[4] > h[3]) return fail(ctx, SWGS_ERR_INVALID_ARG, "bad entry counts in the record");
+    if (h[5] != SWGS_ENC_FP32 && h[5] != SWGS_ENC_Q) return fail(ctx, SWGS_ERR_INVALID_ARG, "unknown record encoding");
+    if (h[7] & ~3) return fail(ctx, SWGS_ERR_INVALID_ARG, "unknown record flags");
+    if (!(h[7] & 2) && h[4] != h[3]) return fail(ctx, SWGS_ERR_INVALID_ARG, "entries dropped without a keep mask");
+    size_t need = 0;
+    decode_layout(h, &need);
+    if (record_bytes < need) return fail(ctx, SWGS_ERR_INVALID_ARG, "record_bytes smaller than the record's entries");
+    const uint32_t n = (uint32_t)h[3];
+    if (slot_base >= 0 && slot_base + (int64_t)n > (int64_t)pool->n_slots)
+        return fail(ctx, SWGS_ERR_INVALID_ARG, "slot_base + count exceeds n_slots");
+    const uint32_t words = (n + 31) / 32;
+    void *scr = nullptr;
+    HIP_TRY(ctx, ctx_scratch(ctx, 4 * ((size_t)words + words / 4096 + 64), &scr));
+    uint32_t *sc = static_cast<uint32_t *>(scr);
+    uint32_t *bad = sc;
+    launch_fill_u32(s, bad, 0, 1);
+    launch_decode(s, *pool, rows_for(pool->sh_degree), static_cast<const uint8_t *>(record), h, slot_base, sc + 8, bad);
+    uint32_t nbad = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&nbad, bad, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (count_out) *count_out = n;
+    if (nbad) return fail(ctx, SWGS_ERR_INVALID_ARG, std::to_string(nbad) + " record entries name slots outside the pool");
+    return SWGS_OK;
+}
+
+swgs_status swgs_encode_update(swgs_context *ctx, const void *record, size_t record_bytes, int32_t enc, int64_t keep,
+                               void *out, size_t capacity, size_t *bytes_out) {
+    if (!ctx) return SWGS_ERR_INVALID_ARG;
+    if (!record || record_bytes < 32) return fail(ctx, SWGS_ERR_INVALID_ARG, "record is NULL or shorter than its header");
+    if (enc != SWGS_ENC_FP32 && enc != SWGS_ENC_Q) return fail(ctx, SWGS_ERR_INVALID_ARG, "unknown encoding");
+    hipStream_t s = ctx->stream;
+    int32_t h[8];
+    HIP_TRY(ctx, hipMemcpyAsync(h, record, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (h[0] != 0x53475753 || h[1] != 1) return fail(ctx, SWGS_ERR_INVALID_ARG, "not a version-1 update record");
+    if (h[3] < 0) return fail(ctx, SWGS_ERR_INVALID_ARG, "negative entry count in the record");
+    if (h[4] < 0 || h[4] > 3 || h[5] != rows_for(h[4])) return fail(ctx, SWGS_ERR_INVALID_ARG, "bad SH degree / row count");
+    const uint32_t n = (uint32_t)h[3];
+    if (record_bytes < swgs_record_bytes(n, h[4])) return fail(ctx, SWGS_ERR_INVALID_ARG, "record_bytes smaller than the record's entries");
+    const uint32_t kept = keep < 0 || keep >= (int64_t)n ? n : (uint32_t)keep;
+    void *scr = nullptr;
+    HIP_TRY(ctx, ctx_scratch(ctx, 4 * encode_scratch_words(n), &scr));
+    uint32_t *sc = static_cast<uint32_t *>(scr);
+    const uint8_t *src = static_cast<const uint8_t *>(record);
+    launch_encode_uniform(s, src, n, sc);
+    uint32_t nonuniform = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&nonuniform, sc, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    const bool uniform = nonuniform == 0;
+    const size_t need = encoded_bytes(n, kept, enc, uniform, kept < n);
+    if (bytes_out) *bytes_out = need;
+    if (!out) return SWGS_OK;   // size query
+    if (capacity < need) return fail(ctx, SWGS_ERR_INVALID_ARG, "capacity " + std::to_string(capacity) + " < " + std::to_string(need));
+    int32_t head[16] = {0x53475753, 2, h[2], (int32_t)n, (int32_t)kept, enc, h[6], (uniform ? 0 : 1) | (kept < n ? 2 : 0),
+                        0, 0, 0, 0, h[4], 0, 0, 0};
+    if (uniform && n) {
+        int32_t first[4];   // slot, birth, start, expire of entry 0
+        for (int i = 0; i < 4; ++i)
+            HIP_TRY(ctx, hipMemcpyAsync(&first[i], src + 32 + 4 * (size_t)n * i, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        for (int i = 0; i < 4; ++i) head[8 + i] = first[i];
+    }
+    launch_encode(s, src, n, h[5], enc, kept, uniform, head, static_cast<uint8_t *>(out), sc + 8);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipStreamSynchronize(s));   // the header is copied from this frame
+    return SWGS_OK;
+}
+
 swgs_status swgs_apply_update(swgs_context *ctx, const swgs_pool *pool, const void *record, size_t record_bytes,
                               int64_t slot_base, int64_t *count_out) {
     if (!ctx) return SWGS_ERR_INVALID_ARG;
@@ -870,7 +946,8 @@ swgs_status swgs_apply_update(swgs_context *ctx, const swgs_pool *pool, const vo
     int32_t h[8];
     HIP_TRY(ctx, hipMemcpyAsync(h, record, sizeof h, hipMemcpyDeviceToHost, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
-    if (h[0] != 0x53475753 || h[1] != 1) return fail(ctx, SWGS_ERR_INVALID_ARG, "not a version-1 update record");
+    if (h[0] == 0x53475753 && h[1] == 2) return apply_update_v2(ctx, pool, record, record_bytes, slot_base, count_out);
+    if (h[0] != 0x53475753 || h[1] != 1) return fail(ctx, SWGS_ERR_INVALID_ARG, "not a version-1 or version-2 update record");
     if (h[3] < 0) return fail(ctx, SWGS_ERR_INVALID_ARG, "negative entry count in the record");
     if (h[4] != pool->sh_degree || h[5] != rows_for(pool->sh_degree))
         return fail(ctx, SWGS_ERR_INVALID_ARG, "record SH degree " + std::to_string(h[4]) + " differs from the pool's");

@@ -173,6 +173,16 @@ void launch_blend_forward(hipStream_t s, const swgs_plan &p, uint8_t *ws, float 
                           unsigned long long *counters, float l1_weight);
 void launch_blend_backward(hipStream_t s, const swgs_plan &p, uint8_t *ws, const float *dLdC,
                            uint32_t tile_lo, uint32_t tile_hi, unsigned long long *counters);
+// Compact update record (kernels_codec.hip)
+size_t encoded_bytes(uint32_t n, uint32_t m, int enc, bool uniform, bool masked);
+size_t encode_scratch_words(uint32_t n);
+void launch_encode_uniform(hipStream_t s, const uint8_t *src, uint32_t n, uint32_t *flag);
+void launch_encode(hipStream_t s, const uint8_t *src, uint32_t n, int F, int enc, uint32_t keep, bool uniform,
+                   const int32_t header[16], uint8_t *out, uint32_t *scratch);
+bool decode_layout(const int32_t h[16], size_t *need);
+void launch_decode(hipStream_t s, const swgs_pool &pool, int F, const uint8_t *rec, const int32_t h[16],
+                   int64_t slot_base, uint32_t *scratch, uint32_t *bad);
+
 // record gradients [9][R] of records [rec_lo, rec_hi): the per-pair terms
 // the backward blend left at the records' emission slots, summed in order
 void launch_pair_grad_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi);

@@ -26,6 +26,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 SWGS_OK, SWGS_ERR_INVALID_ARG, SWGS_ERR_UNSUPPORTED, SWGS_ERR_WORKSPACE_TOO_SMALL, SWGS_ERR_CAPACITY, SWGS_ERR_HIP = range(6)
 SWGS_MODE_PLAIN, SWGS_MODE_BATCHED, SWGS_MODE_GRAPH = range(3)
 SWGS_TIMING_EVENTS, SWGS_TIMING_COUNT = 1, 2
+SWGS_ENC_FP32, SWGS_ENC_Q = 1, 2
 (SWGS_BUF_ACTIVE_LIST, SWGS_BUF_ACTIVE_COUNT, SWGS_BUF_RECORD_VIEW_BASE, SWGS_BUF_DEPTH_KEY, SWGS_BUF_TILE_COUNT,
  SWGS_BUF_RECT, SWGS_BUF_SPLAT, SWGS_BUF_PAIR_KEY, SWGS_BUF_PAIR_VAL, SWGS_BUF_PAIR_COUNT, SWGS_BUF_TILE_RANGE,
  SWGS_BUF_T_FINAL, SWGS_BUF_DLDC, SWGS_BUF_RECORD_GRAD, SWGS_BUF_DEPTH_ORDER) = range(15)
@@ -99,6 +100,7 @@ _sigs = {
     "swgs_plan_set_timing": ([P, P, P, SZ, I32], ctypes.c_int),
     "swgs_plan_timing": ([P, P, P, SZ, P, P, P], ctypes.c_int),
     "swgs_apply_update": ([P, P, P, SZ, I64, P], ctypes.c_int),
+    "swgs_encode_update": ([P, P, SZ, I32, I64, P, SZ, P], ctypes.c_int),
     "swgs_server_create": ([P, P, P, P, SZ, P], ctypes.c_int),
     "swgs_server_destroy": ([P], ctypes.c_int),
     "swgs_server_submit": ([P, P, I32], ctypes.c_int),
@@ -351,6 +353,21 @@ def mature(ctx: Context, pool: Pool, st: int):
     with ctx:
         ctx.check(swgs_mature(ctx.h, ctypes.byref(cp), int(st), ptr(rec), cap, ctypes.byref(cnt), ctypes.byref(nb)))
     return rec[:nb.value], cnt.value
+
+
+def encode_update(ctx: Context, record, enc: int = SWGS_ENC_Q, keep: int = -1):
+    """The compact per-frame update of a mature record (uint8 device tensor):
+    mean, log-scale, rotation, opacity and SH DC per Gaussian, in FP32
+    (SWGS_ENC_FP32) or at Table 6's precisions (SWGS_ENC_Q); keep >= 0 keeps
+    only the `keep` most opaque entries.  Returns a uint8 device tensor."""
+    nb = ctypes.c_size_t()
+    with ctx:
+        ctx.check(swgs_encode_update(ctx.h, ptr(record), int(record.numel()), int(enc), int(keep), None, 0,
+                                     ctypes.byref(nb)))
+        out = torch.empty(nb.value, dtype=torch.uint8, device=ctx.device)
+        ctx.check(swgs_encode_update(ctx.h, ptr(record), int(record.numel()), int(enc), int(keep), ptr(out),
+                                     nb.value, ctypes.byref(nb)))
+    return out[:nb.value]
 
 
 def parse_record(rec: np.ndarray):
