@@ -328,6 +328,39 @@ swgs_status swgs_encode_update(swgs_context *ctx, const void *record, size_t rec
 swgs_status swgs_apply_update(swgs_context *ctx, const swgs_pool *pool, const void *record,
                               size_t record_bytes, int64_t slot_base, int64_t *count_out);
 
+/* ------------------------------------------------------------- player
+ * Client-side playback of the update stream (Algorithm 2, Sec. 4.3).  The
+ * caller owns `buffer` (num_gs slots, parameters at the buffer's SH degree,
+ * start/expire, optional birth).  swgs_player_push is the stream read: it
+ * checks the record (version 1 or 2, host memory, `bytes` bytes) and that
+ * its slots lie in the buffer, copies it into a pinned staging slot and
+ * starts its host-to-device transfer on the player's own copy stream
+ * (default priority), so the transfer overlaps rendering on the context
+ * stream; the record is due at the birth frame of its first entry.  It
+ * fails with SWGS_ERR_CAPACITY when queue_depth records are queued and not
+ * yet applied (advance first), and waits for an applied record's decode to
+ * finish before reusing its staging slot.  swgs_player_advance(frame) is one
+ * tick of the update thread: every queued record due at `frame` or earlier
+ * is decoded into the buffer on the context stream after its transfer, in
+ * push order, without a host synchronisation (*applied, host, nullable,
+ * receives how many); renders issued later on the context stream see the
+ * new slices.  A record pushed after its frame was ticked is applied at the
+ * next tick (the paper's loop matches the frame exactly and would skip it).
+ * swgs_player_queued reports the records waiting and the total applied.
+ * swgs_player_destroy synchronises both streams and frees the staging. */
+typedef struct swgs_player swgs_player;
+typedef struct {
+    int32_t struct_size;       /* sizeof(swgs_player_opts) */
+    int32_t queue_depth;       /* records in flight: 1..64 */
+    int64_t max_record_bytes;  /* largest record pushed (>= 64) */
+} swgs_player_opts;
+swgs_status swgs_player_create(swgs_context *ctx, const swgs_pool *buffer, const swgs_player_opts *opts,
+                               swgs_player **out);
+swgs_status swgs_player_push(swgs_player *player, const void *record, size_t bytes);
+swgs_status swgs_player_advance(swgs_player *player, int32_t frame, int32_t *applied);
+swgs_status swgs_player_queued(const swgs_player *player, int32_t *queued, int64_t *applied_total);
+void swgs_player_destroy(swgs_player *player);
+
 /* ------------------------------------------------------------ serving
  * A render server over a resident pool.  Sec. 4.3's client keeps the
  * sliding pool on the device and renders, for a requested frame, the slots

@@ -65,6 +65,10 @@ class SwgsServerOpts(ctypes.Structure):
                 ("lds_batch", ctypes.c_int32), ("max_batch_pixels", ctypes.c_int64), ("pair_ratio", ctypes.c_double)]
 
 
+class SwgsPlayerOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("queue_depth", ctypes.c_int32), ("max_record_bytes", ctypes.c_int64)]
+
+
 class SwgsRequest(ctypes.Structure):
     _fields_ = [("view", SwgsView), ("image", ctypes.c_void_p), ("arrival", ctypes.c_double),
                 ("ready", ctypes.c_double), ("status", ctypes.c_int32), ("batch", ctypes.c_int32)]
@@ -101,6 +105,11 @@ _sigs = {
     "swgs_plan_timing": ([P, P, P, SZ, P, P, P], ctypes.c_int),
     "swgs_apply_update": ([P, P, P, SZ, I64, P], ctypes.c_int),
     "swgs_encode_update": ([P, P, SZ, I32, I64, P, SZ, P], ctypes.c_int),
+    "swgs_player_create": ([P, P, P, P], ctypes.c_int),
+    "swgs_player_push": ([P, P, SZ], ctypes.c_int),
+    "swgs_player_advance": ([P, I32, P], ctypes.c_int),
+    "swgs_player_queued": ([P, P, P], ctypes.c_int),
+    "swgs_player_destroy": ([P], None),
     "swgs_server_create": ([P, P, P, P, SZ, P], ctypes.c_int),
     "swgs_server_destroy": ([P], ctypes.c_int),
     "swgs_server_submit": ([P, P, I32], ctypes.c_int),
@@ -368,6 +377,49 @@ def encode_update(ctx: Context, record, enc: int = SWGS_ENC_Q, keep: int = -1):
         ctx.check(swgs_encode_update(ctx.h, ptr(record), int(record.numel()), int(enc), int(keep), ptr(out),
                                      nb.value, ctypes.byref(nb)))
     return out[:nb.value]
+
+
+class Player:
+    """Client playback of the update stream (Algorithm 2): push() records
+    (host bytes) as they arrive, advance(frame) once per frame; the buffer
+    pool then holds the slices live at that frame."""
+
+    def __init__(self, ctx: Context, buffer: Pool, queue_depth: int = 4, max_record_bytes: int = 1 << 20):
+        self.ctx, self.buffer = ctx, buffer
+        o = SwgsPlayerOpts(ctypes.sizeof(SwgsPlayerOpts), int(queue_depth), int(max_record_bytes))
+        self._cp = buffer.c()
+        h = ctypes.c_void_p()
+        with ctx:
+            ctx.check(swgs_player_create(ctx.h, ctypes.byref(self._cp), ctypes.byref(o), ctypes.byref(h)))
+        self.h = h
+
+    def push(self, record):
+        a = np.ascontiguousarray(np.frombuffer(bytes(record), np.uint8) if isinstance(record, (bytes, bytearray))
+                                 else record, dtype=np.uint8)
+        with self.ctx:
+            self.ctx.check(swgs_player_push(self.h, a.ctypes.data_as(ctypes.c_void_p), a.nbytes))
+
+    def advance(self, frame: int) -> int:
+        n = ctypes.c_int32()
+        with self.ctx:
+            self.ctx.check(swgs_player_advance(self.h, int(frame), ctypes.byref(n)))
+        return n.value
+
+    def queued(self):
+        q, a = ctypes.c_int32(), ctypes.c_int64()
+        self.ctx.check(swgs_player_queued(self.h, ctypes.byref(q), ctypes.byref(a)))
+        return q.value, a.value
+
+    def close(self):
+        if self.h:
+            swgs_player_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def parse_record(rec: np.ndarray):

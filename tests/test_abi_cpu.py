@@ -58,7 +58,8 @@ def test_struct_layouts_match_a_c_compiler(tmp_path):
         pytest.skip("gcc not available")
     structs = {"swgs_pool": swgs.SwgsPool, "swgs_view": swgs.SwgsView, "swgs_plan_opts": swgs.SwgsPlanOpts,
                "swgs_step_cfg": swgs.SwgsStepCfg, "swgs_server_opts": swgs.SwgsServerOpts,
-               "swgs_request": swgs.SwgsRequest, "swgs_serve_stats": swgs.SwgsServeStats}
+               "swgs_request": swgs.SwgsRequest, "swgs_serve_stats": swgs.SwgsServeStats,
+               "swgs_player_opts": swgs.SwgsPlayerOpts}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "swgs.h"', "int main(void) {"]
     for cname, ct in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
