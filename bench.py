@@ -69,6 +69,7 @@ def parse():
     ap.add_argument("--serve-lanes", type=int, default=3)
     ap.add_argument("--serve-max-batch", type=int, default=16)
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
+    ap.add_argument("--stream-frames", type=int, default=10, help="frames of the update-stream run; 0: skip it")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run 3 device-to-device copies of this many MiB (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -235,6 +236,8 @@ def main():
         else:
             out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                "frac": None, "traffic": None, "avg_launch_ms": round(avg_s * 1e3, 4)}
+    if args.stream_frames > 0:
+        out["stream"] = run_stream(args, ctx)
     if args.serve_rates.strip():
         del student, teacher, targets
         torch.cuda.empty_cache()
@@ -303,6 +306,119 @@ def latency_summary(arr, ready, status, t_lo):
     return dict(p50_ms=round(float(np.percentile(lat, 50)), 3), p99_ms=round(float(np.percentile(lat, 99)), 3),
                 mean_ms=round(float(lat.mean()), 3), frames_per_s=round(float(m.sum() / span), 2),
                 completed=int(m.sum()), failed=int(((arr >= t_lo) & (status != 0)).sum()))
+
+
+def run_stream(args, ctx):
+    """The update stream of a 200K-Gaussian model with swin 5 (Sec. 5.2's
+    configuration: 40K Gaussians per frame): record sizes per frame (full,
+    FP32 DC-only, Table 6), GPU encode and decode times, client playback
+    (Algorithm 2) with the next record's transfer overlapped with rendering
+    against a serialized client, and the rate-distortion of Table 6's
+    quantisation and Sec. 5.5's tail-drop (PSNR of the client render against
+    the FP32 DC-only client)."""
+    import numpy as np
+    import torch
+
+    from paper_2409_07759_amd import swgs
+    from paper_2409_07759_amd import synth as S
+    num_gs, swin, deg, st0, n = 200_000, 5, args.sh_degree, 7, args.stream_frames
+    pool = S.steady_window_pool(num_gs, swin, deg, st0, seed=11)
+    dp = swgs.Pool.from_synth(pool)
+    W, H = args.width, args.height
+
+    def client():
+        # the client's first read: the live window at st0 (DC-only buffer)
+        return swgs.Pool(np.ascontiguousarray(pool.params[:14, :num_gs]), pool.birth[:num_gs].copy(),
+                         pool.start[:num_gs].copy(), pool.expire[:num_gs].copy(), 0, swin, 0, "cuda", train=False)
+
+    encs = {"fp32": (swgs.SWGS_ENC_FP32, -1), "table6": (swgs.SWGS_ENC_Q, -1)}
+    for f in (0.75, 0.5, 0.25):
+        encs[f"table6_keep{f}"] = (swgs.SWGS_ENC_Q, f)
+    recs = {k: [] for k in encs}
+    full_bytes, t_enc = [], {k: 0.0 for k in encs}
+    for st in range(st0 + 1, st0 + 1 + n):
+        rec, cnt = swgs.mature(ctx, dp, st)
+        full_bytes.append(rec.numel())
+        for k, (e, kf) in encs.items():
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out = swgs.encode_update(ctx, rec, e, -1 if kf < 0 else int(cnt * kf))
+            torch.cuda.synchronize()
+            t_enc[k] += time.perf_counter() - t
+            recs[k].append(out)
+    frames = list(range(st0, st0 + n))          # record i is due at frame st0 + i
+    cap = 4 * num_gs * 8
+    view = lambda fr: S.ring_views([fr], 1, W, H)[0]
+
+    def render(buf, fr):
+        pl = swgs.Plan(ctx, buf, [view(fr)], pair_capacity=cap)
+        img = pl.forward()
+        pl.close()
+        return img
+
+    # client playback: push the next record (transfer on the copy stream) and render the current frame
+    host_recs = [r.cpu().numpy() for r in recs["table6"]]
+    buf = client()
+    player = swgs.Player(ctx, buf, queue_depth=4, max_record_bytes=max(h.nbytes for h in host_recs))
+    player.push(host_recs[0])
+    render(buf, frames[0])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i, fr in enumerate(frames):
+        if i + 1 < n:
+            player.push(host_recs[i + 1])
+        player.advance(fr)
+        render(buf, fr)
+    torch.cuda.synchronize()
+    t_play = (time.perf_counter() - t) / n
+    player.close()
+    # serialized client: synchronous transfer, apply, render
+    buf2 = client()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    t_h2d = t_dec = 0.0
+    for i, fr in enumerate(frames):
+        a = time.perf_counter()
+        d = torch.from_numpy(host_recs[i]).cuda()
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        swgs.apply_update(ctx, buf2, d)
+        c = time.perf_counter()
+        render(buf2, fr)
+        t_h2d += b - a
+        t_dec += c - b
+    torch.cuda.synchronize()
+    t_ser = (time.perf_counter() - t) / n
+    same = bool(torch.equal(render(buf, frames[-1]), render(buf2, frames[-1])))
+    # rate-distortion at the last frame (every slice replaced once n >= swin)
+    imgs = {}
+    for k in encs:
+        b = client()
+        for r in recs[k]:
+            swgs.apply_update(ctx, b, r)
+        imgs[k] = render(b, frames[-1])
+    ref = imgs["fp32"]
+    rd = {}
+    for k, img in imgs.items():
+        mse = float(torch.mean((img - ref) ** 2))
+        rd[k] = {"mb_per_frame": round(float(np.mean([r.numel() for r in recs[k]])) / 1e6, 4),
+                 "psnr_vs_fp32_db": None if mse == 0 else round(10 * math.log10(1.0 / mse), 2)}
+    res = {"workload": f"{num_gs} Gaussians, swin {swin} ({num_gs // swin} per frame), trainer SH degree {deg}, "
+                       f"DC-only client; {n} frames from frame {st0}; client renders one {W}x{H} view per frame",
+           "bytes_per_frame": {"full_record": int(np.mean(full_bytes)),
+                               "fp32_dc": int(np.mean([r.numel() for r in recs["fp32"]])),
+                               "table6": int(np.mean([r.numel() for r in recs["table6"]]))},
+           "paper_mb_per_frame": {"fp32_dc": 2.1, "table6": 1.2},
+           "encode_ms": {k: round(1e3 * v / n, 3) for k, v in t_enc.items()},
+           "playback_ms_per_frame": {"player_overlapped": round(1e3 * t_play, 3), "serialized": round(1e3 * t_ser, 3),
+                                     "serialized_transfer": round(1e3 * t_h2d / n, 3),
+                                     "serialized_apply": round(1e3 * t_dec / n, 3)},
+           "player_equals_serialized": same,
+           "rate_distortion": rd}
+    log(f"stream: {res['bytes_per_frame']}, playback {res['playback_ms_per_frame']}, rd {rd}")
+    del dp
+    torch.cuda.empty_cache()
+    return res
 
 
 def run_serving(args, ctx, tile, lds):
