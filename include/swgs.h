@@ -328,6 +328,38 @@ swgs_status swgs_encode_update(swgs_context *ctx, const void *record, size_t rec
 swgs_status swgs_apply_update(swgs_context *ctx, const swgs_pool *pool, const void *record,
                               size_t record_bytes, int64_t slot_base, int64_t *count_out);
 
+/* ------------------------------------------------------------ trainer
+ * The paper's training loop over one window (Algorithm 1's train_swin):
+ * each iteration samples one (frame, camera) view of the window, renders
+ * it, and runs loss, backward, Adam + SGLD on the Gaussians live in its
+ * frame and relocation every cfg->relocate_period iterations (Sec. 4.4,
+ * Sec. 3.2).  swgs_trainer_create makes one single-view plan per entry of
+ * `views` (host array; opts as for swgs_plan_create, pair_capacity large
+ * enough for every view) sharing one workspace; the pool's lifespans must
+ * not change while the trainer lives (destroy it before mature()).
+ * swgs_trainer_run runs `iterations` iterations numbered iter0, iter0 + 1,
+ * ...: iteration i uses view swgs_trainer_view(seed, i, n_views), Adam
+ * bias-correction step t = i + 1, and i as the step keying the SGLD noise,
+ * the relocation draw and the relocation cadence (i % relocate_period == 0);
+ * targets (host array of n_views device pointers) hold each view's ground
+ * truth [3][H][W].  cfg->mode is ignored (each iteration is one batched
+ * window step).  stats (device, nullable) receives 8 doubles per
+ * iteration, as swgs_window_step reports them; views_out (host, nullable)
+ * the view of each iteration.  Nothing synchronises.
+ * swgs_trainer_view: floor(x0 n_views / 2^32) with x0 the first word of
+ * Philox4x32-10 at counter (i_lo, i_hi, 0, 0x504D4153) keyed by the seed.
+ * swgs_schedule_expire: Algorithm 1's schedule_expire after the genesis
+ * window -- optimisable block k of num_gs/swin slots expires at frame k
+ * (k >= 1), block 0 at swin -- so one slice matures per frame. */
+typedef struct swgs_trainer swgs_trainer;
+swgs_status swgs_trainer_create(swgs_context *ctx, const swgs_pool *pool, const swgs_view *views, int32_t n_views,
+                                const swgs_plan_opts *opts, swgs_trainer **out);
+swgs_status swgs_trainer_run(swgs_trainer *trainer, const swgs_step_cfg *cfg, const float *const *targets,
+                             int64_t iterations, int64_t iter0, uint64_t seed, double *stats, int32_t *views_out);
+void swgs_trainer_destroy(swgs_trainer *trainer);
+int32_t swgs_trainer_view(uint64_t seed, int64_t iteration, int32_t n_views);
+swgs_status swgs_schedule_expire(swgs_context *ctx, const swgs_pool *pool);
+
 /* ------------------------------------------------------------- player
  * Client-side playback of the update stream (Algorithm 2, Sec. 4.3).  The
  * caller owns `buffer` (num_gs slots, parameters at the buffer's SH degree,

@@ -105,6 +105,11 @@ _sigs = {
     "swgs_plan_timing": ([P, P, P, SZ, P, P, P], ctypes.c_int),
     "swgs_apply_update": ([P, P, P, SZ, I64, P], ctypes.c_int),
     "swgs_encode_update": ([P, P, SZ, I32, I64, P, SZ, P], ctypes.c_int),
+    "swgs_trainer_create": ([P, P, P, I32, P, P], ctypes.c_int),
+    "swgs_trainer_run": ([P, P, P, I64, I64, U64, P, P], ctypes.c_int),
+    "swgs_trainer_destroy": ([P], None),
+    "swgs_trainer_view": ([U64, I64, I32], ctypes.c_int32),
+    "swgs_schedule_expire": ([P, P], ctypes.c_int),
     "swgs_player_create": ([P, P, P, P], ctypes.c_int),
     "swgs_player_push": ([P, P, SZ], ctypes.c_int),
     "swgs_player_advance": ([P, I32, P], ctypes.c_int),
@@ -377,6 +382,62 @@ def encode_update(ctx: Context, record, enc: int = SWGS_ENC_Q, keep: int = -1):
         ctx.check(swgs_encode_update(ctx.h, ptr(record), int(record.numel()), int(enc), int(keep), ptr(out),
                                      nb.value, ctypes.byref(nb)))
     return out[:nb.value]
+
+
+class Trainer:
+    """The paper's loop over one window (Algorithm 1's train_swin): one
+    single-view plan per (frame, camera) in `views`; run() samples a view per
+    iteration and steps on it.  The pool's lifespans must stay fixed while
+    the trainer lives (close it before mature())."""
+
+    def __init__(self, ctx: Context, pool: Pool, views, tile=(16, 16), lds_batch=0, headroom=1.5):
+        self.ctx, self.pool, self.views = ctx, pool, list(views)
+        # one pair capacity for all views: the largest measured count, with headroom
+        k = 0
+        for v in self.views:
+            probe = Plan(ctx, pool, [v], tile=tile, lds_batch=lds_batch, pair_capacity=1 << 16)
+            k = max(k, probe.measure())
+            probe.close()
+        self.pair_capacity = int(k * headroom) + 65536
+        opts = SwgsPlanOpts(ctypes.sizeof(SwgsPlanOpts), tile[0], tile[1], lds_batch, 0, self.pair_capacity)
+        self._cp = pool.c()
+        self._cv = c_views(self.views)
+        h = ctypes.c_void_p()
+        with ctx:
+            ctx.check(swgs_trainer_create(ctx.h, ctypes.byref(self._cp), self._cv, len(self.views), ctypes.byref(opts),
+                                          ctypes.byref(h)))
+        self.h = h
+
+    def run(self, cfg, targets, iterations: int, iter0: int, seed: int, stats=None):
+        """targets: one device tensor per view.  Returns the sampled view of
+        each iteration (numpy int32)."""
+        tp = (ctypes.c_void_p * len(self.views))(*[t.data_ptr() for t in targets])
+        vo = np.zeros(max(1, iterations), np.int32)
+        with self.ctx:
+            self.ctx.check(swgs_trainer_run(self.h, ctypes.byref(cfg), tp, int(iterations), int(iter0), int(seed),
+                                            ptr(stats), vo.ctypes.data_as(ctypes.c_void_p)))
+        return vo[:iterations]
+
+    def close(self):
+        if self.h:
+            swgs_trainer_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def trainer_view(seed: int, iteration: int, n_views: int) -> int:
+    return int(swgs_trainer_view(int(seed), int(iteration), int(n_views)))
+
+
+def schedule_expire(ctx: Context, pool: Pool):
+    cp = pool.c()
+    with ctx:
+        ctx.check(swgs_schedule_expire(ctx.h, ctypes.byref(cp)))
 
 
 class Player:

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2409_07759_amd import swgs
@@ -94,3 +95,21 @@ def test_no_cpu_fallback_in_the_product_path():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in src and "from oracle" not in src, f
+
+
+def test_trainer_view_sampling_is_philox_mapped():
+    """The trainer's view of iteration i: floor(x0 n / 2^32), x0 the first
+    word of Philox4x32-10 at counter (i_lo, i_hi, 0, 'SAMP') keyed by the
+    seed -- against the oracle's Philox (pinned by the published
+    known-answer vectors); uniform over the views."""
+    import oracle as O
+    from paper_2409_07759_amd import swgs
+    for seed in (0, 11, 0x1234_5678_9ABC_DEF0):
+        for n in (1, 6, 180):
+            for i in list(range(50)) + [2 ** 32 + 3, 2 ** 40 + 17]:
+                x = O.philox4x32_10([i & 0xFFFFFFFF, i >> 32, 0, 0x504D4153],
+                                    [seed & 0xFFFFFFFF, seed >> 32])
+                assert swgs.trainer_view(seed, i, n) == (int(x[0]) * n) >> 32, (seed, n, i)
+    counts = np.bincount([swgs.trainer_view(5, i, 8) for i in range(8000)], minlength=8)
+    chi2 = float(((counts - 1000) ** 2 / 1000).sum())
+    assert chi2 < 24.3      # 7 degrees of freedom, p = 0.001
