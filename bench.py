@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--serve-max-batch", type=int, default=16)
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--stream-frames", type=int, default=10, help="frames of the update-stream run; 0: skip it")
+    ap.add_argument("--literal-iters", type=int, default=200,
+                    help="timed iterations of the paper's one-view-per-iteration loop; 0: skip it")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run 3 device-to-device copies of this many MiB (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -236,6 +238,8 @@ def main():
         else:
             out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                                "frac": None, "traffic": None, "avg_launch_ms": round(avg_s * 1e3, 4)}
+    if args.literal_iters > 0:
+        out["literal_loop"] = run_literal(args, ctx, student, views, targets, (tw, th), results)
     if args.stream_frames > 0:
         out["stream"] = run_stream(args, ctx)
     if args.serve_rates.strip():
@@ -306,6 +310,47 @@ def latency_summary(arr, ready, status, t_lo):
     return dict(p50_ms=round(float(np.percentile(lat, 50)), 3), p99_ms=round(float(np.percentile(lat, 99)), 3),
                 mean_ms=round(float(lat.mean()), 3), frames_per_s=round(float(m.sum() / span), 2),
                 completed=int(m.sum()), failed=int(((arr >= t_lo) & (status != 0)).sum()))
+
+
+def run_literal(args, ctx, student, views, targets, tile, results):
+    """The paper's own loop (Algorithm 1's train_swin) on the same window:
+    one sampled (frame, camera) per iteration (Adam + SGLD + relocation at
+    its cadence), against the window step that takes all views at once."""
+    import torch
+
+    from paper_2409_07759_amd import swgs
+    dp = swgs.Pool.from_synth(student)
+    t0 = time.time()
+    tr = swgs.Trainer(ctx, dp, views, tile=tile, lds_batch=args.lds_batch)
+    t_setup = time.time() - t0
+    HW = [3 * v.width * v.height for v in views]
+    offs = [0]
+    for n in HW:
+        offs.append(offs[-1] + n)
+    tgts = [targets[offs[i]:offs[i + 1]] for i in range(len(views))]
+    cfg = swgs.step_cfg(window_start=views[0].frame, relocate_period=100)
+    tr.run(cfg, tgts, 10, 0, 5)
+    torch.cuda.synchronize()
+    n = args.literal_iters
+    stats = torch.zeros(8 * n, dtype=torch.float64, device="cuda")
+    t = time.perf_counter()
+    tr.run(cfg, tgts, n, 10, 5, stats=stats)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    tr.close()
+    ips = n / el
+    st = stats.view(n, 8).cpu()
+    res = {"iterations_per_s": round(ips, 2), "ms_per_iteration": round(1e3 * el / n, 3),
+           "views": len(views), "setup_s": round(t_setup, 2),
+           "paper_window_2000_iterations_s": round(2000 / ips, 3),
+           "views_per_s": round(ips, 1),
+           "window_step_views_per_s": round(len(views) * results.get("graph", results[list(results)[0]])["steps_per_s"], 1),
+           "loss_first_last": [round(float(st[0, 3]), 5), round(float(st[-1, 3]), 5)],
+           "overflow": bool(st[:, 6].max() > 0)}
+    log(f"literal loop: {res}")
+    del dp
+    torch.cuda.empty_cache()
+    return res
 
 
 def run_stream(args, ctx):
