@@ -327,11 +327,14 @@ void launch_pair_offsets(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_
 void launch_emit_pairs(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi) {
     if (rec_hi <= rec_lo) return;
     const uint32_t n = rec_hi - rec_lo;
+    // into the buffers the tile sort reads its input from
+    const bool alt = radix_input_in_alt(p.tile_key_bits);
     hipLaunchKernelGGL(k_emit_pairs, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
                        wsp<uint32_t>(ws, p, WB_REC_IDX) + rec_lo, wsp<uint32_t>(ws, p, WB_PAIR_OFFSET),
                        wsp<uint32_t>(ws, p, WB_PAIR_COUNT) + 2, wsp<uint2>(ws, p, WB_RECT),
                        wsp<uint32_t>(ws, p, WB_REC_VIEW_BASE), (int)p.views.size(), wsp<ViewDev>(ws, p, WB_VIEWS),
-                       n, (uint32_t)p.pair_cap, wsp<uint32_t>(ws, p, WB_PAIR_KEY), wsp<uint32_t>(ws, p, WB_PAIR_VAL),
+                       n, (uint32_t)p.pair_cap, wsp<uint32_t>(ws, p, alt ? WB_PAIR_KEY_ALT : WB_PAIR_KEY),
+                       wsp<uint32_t>(ws, p, alt ? WB_PAIR_VAL_ALT : WB_PAIR_VAL),
                        p.forward_only ? nullptr : wsp<uint32_t>(ws, p, WB_PAIR_BASE));
 }
 

@@ -277,17 +277,27 @@ k_scan_write(const uint32_t *in, const uint32_t *__restrict__ idx, uint32_t n,
 
 }  // namespace
 
+int radix_passes(int bits) {
+    if (bits < 1) bits = 1;
+    if (bits > 32) bits = 32;
+    return (bits + kMaxDigitBits - 1) / kMaxDigitBits;   // fewest passes whose digits fit
+}
+
+bool radix_input_in_alt(int bits) { return radix_passes(bits) & 1; }
+
 void radix_sort_pairs(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
                       uint32_t *vals_alt, const uint32_t *d_n, uint32_t n_fixed, uint32_t cap,
                       int bits, uint32_t *hist, uint32_t *totals, const uint32_t *gather_src,
                       uint32_t *gather_out) {
     if (bits < 1) bits = 1;
     if (bits > 32) bits = 32;
-    // smallest even pass count whose digits fit in kMaxDigitBits
-    int passes = 2;
-    while ((bits + passes - 1) / passes > kMaxDigitBits) passes += 2;
+    const int passes = radix_passes(bits);
     const int dbits = (bits + passes - 1) / passes;
-    uint32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+    // an odd pass count starts from the alternate buffers, so that the
+    // last pass writes (keys, vals)
+    const bool odd = passes & 1;
+    uint32_t *ki = odd ? keys_alt : keys, *vi = odd ? vals_alt : vals;
+    uint32_t *ko = odd ? keys : keys_alt, *vo = odd ? vals : vals_alt;
     int shift = 0;
     for (int p = 0; p < passes; ++p) {
         int w = dbits;

@@ -12,9 +12,12 @@
 //
 // k_ssim_fwd: one workgroup per (32x32 output tile, channel) stages the
 // 42x42 neighbourhood of C and GT in LDS, runs the separable 11-tap window
-// (rows, then columns) over x, y, x^2, y^2, xy, and writes per pixel the
+// (rows, then columns) over x, y, x^2 + y^2 and xy (S takes E[x^2] and
+// E[y^2] only through their sum, in var_x + var_y), and writes per pixel the
 // partial derivatives of S with respect to mu_x, E[x^2] and E[xy], plus the
-// tile's sum of S weighted for the loss.
+// tile's sum of S weighted for the loss.  In both kernels the staged inputs
+// and the row sums share one LDS buffer: the row pass holds its sums in
+// registers until every thread is done reading the staging.
 // k_ssim_bwd: the window is symmetric, so the adjoint of a window sum is the
 // same window sum; it is applied to the three partial maps and
 //     dSSIM/dx(q) = (W*Sm)(q) + 2 x(q) (W*Sxx)(q) + y(q) (W*Sxy)(q)
@@ -36,13 +39,17 @@ constexpr int kThreads = 256;
 constexpr int kRowItems = kH * (kT / kSeg);   // row pass: every staged row x 8 segments (336)
 constexpr int kColItems = kT * (kT / kSeg);   // column pass: 32 columns x 8 segments (256)
 static_assert(kColItems == kThreads, "one column item per thread");
+constexpr int kItemRounds = (kRowItems + kThreads - 1) / kThreads;   // row items per thread (2)
 constexpr int kStage = (kH * kH + kThreads - 1) / kThreads;   // staged elements per thread (7)
 // LDS row pitches: in the row pass consecutive lanes take consecutive rows,
 // so a row's pitch in dwords is kept an odd multiple of 4 and the 16-byte
 // accesses of 8 consecutive lanes fall on disjoint banks
-constexpr int kHP = kH;                // float2 staging: 84 dwords per row
-constexpr int kHP4 = kH + 1;           // float4 staging: 172 dwords per row
-constexpr int kTP = kT + 1;            // row sums: 132 dwords (float4) / 33 (float) per row
+constexpr int kHP = kH;                // forward staging (x, y): 84 dwords per row
+constexpr int kPP = kH + 2;            // backward staging, one plane per map: 44 dwords per row
+constexpr int kTP = kT + 1;            // row sums (float4): 132 dwords per row
+constexpr int kLds = kH * kTP;         // float4 elements of the shared buffer (22176 B)
+static_assert(kH * kHP * 2 <= 4 * kLds && 3 * kH * kPP <= 4 * kLds, "staging fits the shared buffer");
+static_assert((kT - kSeg) + 16 <= kPP && kSpan <= 16, "16-float row reads stay in the plane row");
 constexpr float kC1 = 1e-4f, kC2 = 9e-4f;
 
 // 1D Gaussian weights (sigma 1.5, normalised), computed once on the host
@@ -90,10 +97,10 @@ __global__ void __launch_bounds__(kThreads)
 k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const float *__restrict__ img,
            const float *__restrict__ tgt, float *__restrict__ part, double *__restrict__ tile_sum, float lambda,
            Taps taps) {
-    __shared__ __align__(16) float2 sxy[kH][kHP];  // (x, y) over the staged neighbourhood
-    __shared__ __align__(16) float4 hq[kH][kTP];   // row sums of x, y, x^2, y^2
-    __shared__ float hxy[kH][kTP];                 // row sums of x y
+    __shared__ __align__(16) float4 lds[kLds];
     __shared__ double red[kThreads / 64];
+    float2(*sxy)[kHP] = reinterpret_cast<float2(*)[kHP]>(lds);   // (x, y) over the staged neighbourhood
+    float4(*hq)[kTP] = reinterpret_cast<float4(*)[kTP]>(lds);    // row sums of x, y, x^2 + y^2, x y
     const SsimTile tl = ssim_tile(views, n_views, t_lo);
     const ViewDev &V = *tl.V;
     const size_t HW = (size_t)V.width * V.height;
@@ -118,18 +125,22 @@ k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
         }
     }
     __syncthreads();
-    for (int it = threadIdx.x; it < kRowItems; it += kThreads) {
-        const int r = it % kH, c0 = kSeg * (it / kH);    // consecutive lanes: consecutive rows
-        float a[kSeg], b[kSeg], aa[kSeg], bb[kSeg], ab[kSeg];
+    float4 rs[kItemRounds][kSeg];
 #pragma unroll
-        for (int j = 0; j < kSeg; ++j) a[j] = b[j] = aa[j] = bb[j] = ab[j] = 0.0f;
+    for (int u = 0; u < kItemRounds; ++u) {
+        const int it = threadIdx.x + u * kThreads;
+        if (it >= kRowItems) break;
+        const int r = it % kH, c0 = kSeg * (it / kH);    // consecutive lanes: consecutive rows
+        float a[kSeg], b[kSeg], ss[kSeg], ab[kSeg];
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) a[j] = b[j] = ss[j] = ab[j] = 0.0f;
 #pragma unroll
         for (int p = 0; p < kSpan; p += 2) {
             const float4 e = *reinterpret_cast<const float4 *>(&sxy[r][c0 + p]);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const float x = h ? e.z : e.x, y = h ? e.w : e.y;
-                const float xx = x * x, yy = y * y, xy = x * y;
+                const float sq = fmaf(x, x, y * y), xy = x * y;
 #pragma unroll
                 for (int j = 0; j < kSeg; ++j) {
                     const int k = p + h - j;
@@ -137,29 +148,33 @@ k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
                     const float w = taps.w[k];
                     a[j] = fmaf(w, x, a[j]);
                     b[j] = fmaf(w, y, b[j]);
-                    aa[j] = fmaf(w, xx, aa[j]);
-                    bb[j] = fmaf(w, yy, bb[j]);
+                    ss[j] = fmaf(w, sq, ss[j]);
                     ab[j] = fmaf(w, xy, ab[j]);
                 }
             }
         }
 #pragma unroll
-        for (int j = 0; j < kSeg; ++j) {
-            hq[r][c0 + j] = make_float4(a[j], b[j], aa[j], bb[j]);
-            hxy[r][c0 + j] = ab[j];
-        }
+        for (int j = 0; j < kSeg; ++j) rs[u][j] = make_float4(a[j], b[j], ss[j], ab[j]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kItemRounds; ++u) {
+        const int it = threadIdx.x + u * kThreads;
+        if (it >= kRowItems) break;
+        const int r = it % kH, c0 = kSeg * (it / kH);
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) hq[r][c0 + j] = rs[u][j];
     }
     __syncthreads();
     double s_val = 0.0;
     {
         const int c = threadIdx.x % kT, r0 = kSeg * (threadIdx.x / kT);
-        float mx[kSeg], my[kSeg], exx[kSeg], eyy[kSeg], exy[kSeg];
+        float mx[kSeg], my[kSeg], ess[kSeg], exy[kSeg];
 #pragma unroll
-        for (int j = 0; j < kSeg; ++j) mx[j] = my[j] = exx[j] = eyy[j] = exy[j] = 0.0f;
+        for (int j = 0; j < kSeg; ++j) mx[j] = my[j] = ess[j] = exy[j] = 0.0f;
 #pragma unroll
         for (int p = 0; p < kSpan; ++p) {
             const float4 q = hq[r0 + p][c];
-            const float e = hxy[r0 + p][c];
 #pragma unroll
             for (int j = 0; j < kSeg; ++j) {
                 const int k = p - j;
@@ -167,9 +182,8 @@ k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
                 const float w = taps.w[k];
                 mx[j] = fmaf(w, q.x, mx[j]);
                 my[j] = fmaf(w, q.y, my[j]);
-                exx[j] = fmaf(w, q.z, exx[j]);
-                eyy[j] = fmaf(w, q.w, eyy[j]);
-                exy[j] = fmaf(w, e, exy[j]);
+                ess[j] = fmaf(w, q.z, ess[j]);
+                exy[j] = fmaf(w, q.w, exy[j]);
             }
         }
         float *P = part + 9 * (size_t)V.pix_base + (size_t)tl.ch * 3 * HW;
@@ -178,10 +192,11 @@ k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
         for (int j = 0; j < kSeg; ++j) {
             const int y = tl.y0 + r0 + j;
             if (x >= V.width || y >= V.height) continue;
-            const float A = 2.0f * mx[j] * my[j] + kC1;
-            const float B = 2.0f * (exy[j] - mx[j] * my[j]) + kC2;
-            const float C = mx[j] * mx[j] + my[j] * my[j] + kC1;
-            const float D = (exx[j] - mx[j] * mx[j]) + (eyy[j] - my[j] * my[j]) + kC2;
+            const float mxy = mx[j] * my[j], m2 = mx[j] * mx[j] + my[j] * my[j];
+            const float A = 2.0f * mxy + kC1;
+            const float B = 2.0f * (exy[j] - mxy) + kC2;
+            const float C = m2 + kC1;
+            const float D = (ess[j] - m2) + kC2;               // var_x + var_y + C2
             const float rC = __builtin_amdgcn_rcpf(C), rD = __builtin_amdgcn_rcpf(D);
             const float rCD = rC * rD;
             const float S = A * B * rCD;
@@ -207,15 +222,16 @@ __global__ void __launch_bounds__(kThreads)
 k_ssim_bwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const float *__restrict__ img,
            const float *__restrict__ tgt, const float *__restrict__ part, float *__restrict__ dLdC,
            float lambda, Taps taps) {
-    __shared__ __align__(16) float4 sp[kH][kHP4];  // the three map derivatives (w unused)
-    __shared__ __align__(16) float4 hs[kH][kTP];   // their row sums
+    __shared__ __align__(16) float4 lds[kLds];
+    float(*sp)[kH][kPP] = reinterpret_cast<float(*)[kH][kPP]>(lds);   // the three map derivatives, planar
+    float4(*hs)[kTP] = reinterpret_cast<float4(*)[kTP]>(lds);         // their row sums (w unused)
     const SsimTile tl = ssim_tile(views, n_views, t_lo);
     const ViewDev &V = *tl.V;
     const size_t HW = (size_t)V.width * V.height;
     const float *P = part + 9 * (size_t)V.pix_base + (size_t)tl.ch * 3 * HW;
     {
         // all of a thread's loads in flight before its LDS stores
-        float4 v[kStage];
+        float v[3][kStage];
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
             const int i = threadIdx.x + u * kThreads;
@@ -223,35 +239,57 @@ k_ssim_bwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
             const int yy = tl.y0 + r - kR, xx = tl.x0 + c - kR;
             const bool in = i < kH * kH && xx >= 0 && xx < V.width && yy >= 0 && yy < V.height;
             const size_t o = in ? (size_t)yy * V.width + xx : 0;
-            v[u] = in ? make_float4(P[o], P[o + HW], P[o + 2 * HW], 0.0f) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) v[m][u] = in ? P[o + m * HW] : 0.0f;
         }
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
             const int i = threadIdx.x + u * kThreads;
-            if (i < kH * kH) sp[i / kH][i % kH] = v[u];
+            if (i >= kH * kH) continue;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) sp[m][i / kH][i % kH] = v[m][u];
         }
     }
     __syncthreads();
-    for (int it = threadIdx.x; it < kRowItems; it += kThreads) {
+    float4 rs[kItemRounds][kSeg];
+#pragma unroll
+    for (int u = 0; u < kItemRounds; ++u) {
+        const int it = threadIdx.x + u * kThreads;
+        if (it >= kRowItems) break;
         const int r = it % kH, c0 = kSeg * (it / kH);    // consecutive lanes: consecutive rows
-        float a[kSeg], b[kSeg], g[kSeg];
+        float acc[3][kSeg];
 #pragma unroll
-        for (int j = 0; j < kSeg; ++j) a[j] = b[j] = g[j] = 0.0f;
+        for (int m = 0; m < 3; ++m) {
+            // the item's kSpan inputs of plane m as four 16-byte reads (the
+            // last two floats are not used)
+            float e[16];
 #pragma unroll
-        for (int p = 0; p < kSpan; ++p) {
-            const float4 e = sp[r][c0 + p];
+            for (int q = 0; q < 4; ++q) {
+                const float4 f = *reinterpret_cast<const float4 *>(&sp[m][r][c0 + 4 * q]);
+                e[4 * q] = f.x;
+                e[4 * q + 1] = f.y;
+                e[4 * q + 2] = f.z;
+                e[4 * q + 3] = f.w;
+            }
 #pragma unroll
             for (int j = 0; j < kSeg; ++j) {
-                const int k = p - j;
-                if (k < 0 || k >= kW) continue;
-                const float w = taps.w[k];
-                a[j] = fmaf(w, e.x, a[j]);
-                b[j] = fmaf(w, e.y, b[j]);
-                g[j] = fmaf(w, e.z, g[j]);
+                float t = 0.0f;
+#pragma unroll
+                for (int k = 0; k < kW; ++k) t = fmaf(taps.w[k], e[j + k], t);
+                acc[m][j] = t;
             }
         }
 #pragma unroll
-        for (int j = 0; j < kSeg; ++j) hs[r][c0 + j] = make_float4(a[j], b[j], g[j], 0.0f);
+        for (int j = 0; j < kSeg; ++j) rs[u][j] = make_float4(acc[0][j], acc[1][j], acc[2][j], 0.0f);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kItemRounds; ++u) {
+        const int it = threadIdx.x + u * kThreads;
+        if (it >= kRowItems) break;
+        const int r = it % kH, c0 = kSeg * (it / kH);
+#pragma unroll
+        for (int j = 0; j < kSeg; ++j) hs[r][c0 + j] = rs[u][j];
     }
     __syncthreads();
     const int c = threadIdx.x % kT, r0 = kSeg * (threadIdx.x / kT);

@@ -152,10 +152,15 @@ void launch_emit_pairs(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t 
 void launch_tile_ranges(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t tile_lo, uint32_t tile_hi);
 
 // Radix sort (kernels_sort.hip): stable LSD sort of (key, val) uint32 pairs,
-// n given on the device (*d_n, clamped to cap) over bits [0, bits).
-// On return the sorted data is in (keys, vals); alt buffers are scratch.
+// n given on the device (*d_n, clamped to cap) over bits [0, bits), in
+// radix_passes(bits) passes of at most 8 bits.  The input is read from
+// (keys_alt, vals_alt) when radix_input_in_alt(bits) (an odd pass count),
+// else from (keys, vals); on return the sorted data is in (keys, vals) and
+// the other pair holds scratch.  32-bit keys take 4 passes (input in keys).
 // With gather_out, the last pass also writes gather_out[i] =
 // gather_src[vals[i]] for every sorted position i.
+int radix_passes(int bits);
+bool radix_input_in_alt(int bits);
 void radix_sort_pairs(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
                       uint32_t *vals_alt, const uint32_t *d_n, uint32_t n_fixed, uint32_t cap,
                       int bits, uint32_t *hist, uint32_t *totals, const uint32_t *gather_src = nullptr,
