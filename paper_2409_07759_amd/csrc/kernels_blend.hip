@@ -7,7 +7,12 @@
 //     stop before T (1 - alpha) < 1e-4,  C += c alpha T,  T *= 1 - alpha.
 // The record stores the conic pre-scaled by -log2(e)/2 so exp(-Q/2) is one
 // v_exp_f32, and the screen position split into an integer part and
-// 0.5 - fraction so the pixel offset keeps ~1e-7 px of precision.
+// 0.5 - fraction; staging turns it into the offset of the first pixel of
+// the 64x64-aligned block holding the tile, (x0 - integer part) +
+// (0.5 - fraction) (the difference of integers is exact), so a lane's offset
+// is its pixel index inside that block plus one staged value.  Every tile
+// shape lies inside one such block, so the rounding, and with it every
+// image bit, does not depend on the tile shape.
 //
 // The backward walks the same list back to front from each pixel's last
 // contributor, recovering the transmittance in front of each splat by
@@ -32,10 +37,16 @@ constexpr int kCounterSlots = 256;
 struct Px {
     float dx, dy, g, og;  // offsets, 2^p2 (= exp(-Q/2)), o * g
 };
-__device__ __forceinline__ Px eval_splat(float fx, float fy, const float4 a, const float4 b) {
+// staged offsets, from the splat centre, of the first pixel of the
+// 64x64-aligned block holding the tile at (tx0, ty0)
+__device__ __forceinline__ float4 block_offset(const float4 a, int tx0, int ty0) {
+    return make_float4(((float)(tx0 & ~63) - a.x) + a.z, ((float)(ty0 & ~63) - a.y) + a.w, 0.0f, 0.0f);
+}
+// (lx, ly): the pixel's index inside its 64x64-aligned block, as floats
+__device__ __forceinline__ Px eval_splat(float lx, float ly, const float4 a, const float4 b) {
     Px r;
-    r.dx = (fx - a.x) + a.z;
-    r.dy = (fy - a.y) + a.w;
+    r.dx = lx + a.x;
+    r.dy = ly + a.y;
     // p2 = A' dx^2 + B' dx dy + C' dy^2 (A', B', C' = -log2(e) (A/2, B, C/2))
     const float t = fmaf(b.y, r.dy, b.x * r.dx);
     const float p2 = fmaf(b.z * r.dy, r.dy, t * r.dx);
@@ -79,6 +90,11 @@ __device__ __forceinline__ float4 cull_box(const float4 a, const float4 b) {
     return make_float4(a.x + 0.5f - a.z, a.y + 0.5f - a.w, rx, ry);
 }
 
+// staged entry at a byte offset (16 x its index) of a float4 LDS array
+__device__ __forceinline__ float4 at16(const float4 *base, int off) {
+    return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + off);
+}
+
 // true if the box can reach a pixel centre of the wave's 8x8 block
 __device__ __forceinline__ bool box_hits(const float4 bx, float wx0, float wy0) {
     return (bx.x + bx.z >= wx0) & (bx.x - bx.z <= wx0 + 7.0f) & (bx.y + bx.w >= wy0) & (bx.y - bx.w <= wy0 + 7.0f);
@@ -98,16 +114,17 @@ __device__ __forceinline__ uint32_t box_wave_mask(const float4 bx, int tx0, int 
 }
 
 // Each wave compacts, in ascending order, the batch entries whose mask has
-// its bit set; returns the count (wave-uniform).
+// its bit set, as entry index x 16 (the byte offset of the entry's float4 in
+// the staging arrays); returns the count (wave-uniform).
 template <int CAP>
-__device__ __forceinline__ int wave_list(const uint32_t *smask, int m, int wave, int lane, uint8_t *list) {
+__device__ __forceinline__ int wave_list(const uint32_t *smask, int m, int wave, int lane, uint16_t *list) {
     int cnt = 0;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int c = 0; c < m; c += 64) {
         const int k = c + lane;
         const bool hit = k < m && ((smask[k] >> wave) & 1u);
         const uint64_t b = __ballot(hit);
-        if (hit) list[cnt + __popcll(b & lt)] = (uint8_t)k;
+        if (hit) list[cnt + __popcll(b & lt)] = (uint16_t)(16 * k);
         cnt += __popcll(b);
     }
     return cnt;
@@ -132,11 +149,12 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             const float *__restrict__ targets, float *__restrict__ dLdC, double *__restrict__ loss_part,
             unsigned long long *__restrict__ counters, float l1_weight) {
     constexpr int NT = TW * TH;
+    static_assert(64 % TW == 0 && 64 % TH == 0, "a tile lies inside one 64x64-aligned block");
     constexpr bool CULL = NT > 64;        // per-wave support-box lists
     constexpr int NW = NT / 64;
     __shared__ float4 sa[BATCH], sb[BATCH], sc[BATCH];
     __shared__ uint32_t smask[CULL ? BATCH : 1];
-    __shared__ uint8_t slist[CULL ? NW : 1][CULL ? BATCH : 1];
+    __shared__ uint16_t slist[CULL ? NW : 1][CULL ? BATCH : 1];
     __shared__ float red[2][NT / 64];
     __shared__ unsigned long long cnt_evals, cnt_blend;
     const uint32_t lt_idx = xcd_order(blockIdx.x, gridDim.x);   // neighbouring tiles share an XCD's L2
@@ -149,7 +167,7 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     const int x = tx * TW + lx, y = ty * TH + ly;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const bool inside = x < V.width && y < V.height;
-    const float fx = (float)x, fy = (float)y;
+    const float lxf = (float)(x & 63), lyf = (float)(y & 63);
     const uint2 rg = ranges[tile];
     const uint32_t n = rg.y - rg.x;
 
@@ -164,7 +182,7 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             if (b0 + k < n) {
                 const uint32_t r = pair_val[rg.x + b0 + k];
                 const float4 a = splat[3 * (size_t)r], b = splat[3 * (size_t)r + 1];
-                sa[k] = a;
+                sa[k] = block_offset(a, tx * TW, ty * TH);
                 sb[k] = b;
                 sc[k] = splat[3 * (size_t)r + 2];
                 if (CULL) smask[k] = box_wave_mask<TW, TH>(cull_box(a, b), tx * TW, ty * TH);
@@ -175,11 +193,13 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         const int cnt = CULL ? wave_list<BATCH>(smask, m, wave, lane, slist[CULL ? wave : 0]) : m;
         // branch-free per lane: a splat is blended when alpha >= 1/255 and
         // the pixel has not stopped; the stop test fires on the splat that
-        // would take T below 1e-4 (that splat is not blended)
+        // would take T below 1e-4 (that splat is not blended).  The last
+        // blended entry of the batch is kept as its byte offset (-16: none)
+        int last_off = -16;
         for (int i = 0; i < cnt; ++i) {
-            const int k = CULL ? (int)slist[CULL ? wave : 0][i] : i;
-            const uint32_t idx = b0 + (uint32_t)k + 1;
-            const Px e = eval_splat(fx, fy, sa[k], sb[k]);
+            const int off = CULL ? (int)slist[CULL ? wave : 0][i] : 16 * i;
+            const uint32_t idx = b0 + (uint32_t)(off >> 4) + 1;
+            const Px e = eval_splat(lxf, lyf, at16(sa, off), at16(sb, off));
             const float alpha = fminf(0.99f, e.og);
             const float w0 = alpha * T;
             const float Tn = __fsub_rn(T, w0);             // T (1 - alpha), sharing alpha T
@@ -187,18 +207,19 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             const bool stop = pass && Tn < 1e-4f;
             const bool use = pass && !stop;
             const float w = use ? w0 : 0.0f;
-            const float4 c = sc[k];
+            const float4 c = at16(sc, off);
             c0 = fmaf(c.x, w, c0);
             c1 = fmaf(c.y, w, c1);
             c2 = fmaf(c.z, w, c2);
             T = use ? Tn : T;
-            last = use ? idx : last;
+            last_off = use ? off : last_off;
             if (COUNT) {
                 stop_at = stop ? idx : stop_at;
                 nblend += use ? 1u : 0u;
             }
             done = done || stop;
         }
+        if (last_off >= 0) last = b0 + (uint32_t)(last_off >> 4) + 1;
     }
     float l1 = 0.0f, sq = 0.0f;
     if (inside) {
@@ -318,12 +339,13 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             const uint2 *__restrict__ rect, const uint32_t *__restrict__ pair_base,
             float *__restrict__ pair_grad, unsigned long long *__restrict__ counters) {
     constexpr int NT = TW * TH;
+    static_assert(64 % TW == 0 && 64 % TH == 0, "a tile lies inside one 64x64-aligned block");
     constexpr int NW = NT / 64;           // waves
-    constexpr int BB = NW == 1 ? 64 : 32; // splats per LDS batch (partials: BB x NW x 48 B)
+    constexpr int BB = 64;                // splats per LDS batch (partials: BB x NW x 48 B)
     constexpr bool CULL = NW > 1;
     __shared__ float4 sa[BB], sb[BB], sc[BB];
     __shared__ uint32_t smask[BB];
-    __shared__ uint8_t slist[CULL ? NW : 1][CULL ? BB : 1];
+    __shared__ uint16_t slist[CULL ? NW : 1][CULL ? BB : 1];
     __shared__ uint32_t sslot[BB];        // emission slot of each batch pair
     __shared__ float4 part[BB][NW][kTerm / 4];
     __shared__ uint32_t smax;
@@ -338,7 +360,7 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     lane_pixel<TW, TH>(threadIdx.x, lx, ly);
     const int x = tx * TW + lx, y = ty * TH + ly;
     const bool inside = x < V.width && y < V.height;
-    const float fx = (float)x, fy = (float)y;
+    const float lxf = (float)(x & 63), lyf = (float)(y & 63);
     const uint2 rg = ranges[tile];
 
     float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
@@ -396,7 +418,7 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             const uint32_t r = pair_val[rg.x + b_start + k];
             sslot[k] = slot_of(r);
             const float4 a = splat[3 * (size_t)r], b = splat[3 * (size_t)r + 1];
-            sa[k] = a;
+            sa[k] = block_offset(a, tx * TW, ty * TH);
             sb[k] = b;
             sc[k] = splat[3 * (size_t)r + 2];
             smask[k] = CULL ? box_wave_mask<TW, TH>(cull_box(a, b), tx * TW, ty * TH) : 1u;
@@ -404,13 +426,15 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         __syncthreads();
         const int wm = (int)min((uint32_t)m, wlast > b_start ? wlast - b_start : 0u);
         const int cnt = CULL ? wave_list<BB>(smask, wm, wave, lane, slist[CULL ? wave : 0]) : wm;
+        // entries of this batch before the pixel's last contributor, as a
+        // byte-offset bound (entry k is before it iff 16 k < lim)
+        const int lim = 16 * ((int)min(lst, b_end) - (int)min(lst, b_start));
         for (int i = cnt - 1; i >= 0; --i) {
-            const int k = CULL ? (int)slist[CULL ? wave : 0][i] : i;
-            const uint32_t idx = b_start + (uint32_t)k;
+            const int off = CULL ? (int)slist[CULL ? wave : 0][i] : 16 * i;
             // contrib = the forward blended this splat here
-            const Px e = eval_splat(fx, fy, sa[k], sb[k]);
+            const Px e = eval_splat(lxf, lyf, at16(sa, off), at16(sb, off));
             const float alpha = fminf(0.99f, e.og);
-            const bool contrib = idx < lst && alpha >= (1.0f / 255.0f);
+            const bool contrib = off < lim && alpha >= (1.0f / 255.0f);
             // T and W change only where the splat was blended: a wave with
             // no such pixel skips the gradient (branch-free inside) and
             // stores zero partials
@@ -418,7 +442,7 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             if (__ballot(contrib) != 0) {
                 const float ri = __builtin_amdgcn_rcpf(1.0f - alpha);
                 const float Tk = T * ri;                                     // transmittance in front of k
-                const float4 c = sc[k];
+                const float4 c = at16(sc, off);
                 const float diff = fmaf(g2, c.z, fmaf(g1, c.y, g0 * c.x)) - gW;
                 const float da = Tk * diff;                                  // dL/dalpha
                 const float ac = contrib ? alpha : 0.0f;
@@ -438,47 +462,48 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
                 const float s8 = row_sum16(v8);
                 part_out = r16 < 2 ? y : s8;
             }
-            if (r16 < 3) reinterpret_cast<float *>(&part[k][wave][0])[pslot] = part_out;
+            if (r16 < 3) reinterpret_cast<float *>(&part[0][wave][0])[(off >> 4) * (NW * kTerm) + pslot] = part_out;
         }
         __syncthreads();
-        // flush: the row partials of each splat (only from the waves whose
-        // block it reaches) are summed per term group (3 float4 groups, one
-        // thread per (splat, group)), then nine neighbouring threads store
-        // the pair's terms d/d(u, v, A, B, C, o, r, g, b), conic unscaled
-        // (A = -2 A' ln2, B = -B' ln2, C = -2 C' ln2), as one 36-byte row at
-        // its emission slot: no atomics, and a fixed summation order
+        // flush: one thread per (splat, term group) sums the group's row
+        // partials over the waves whose block the splat reaches (in wave
+        // order) and stores its terms of the pair's 36-byte row
+        // d/d(u, v, A, B, C, o, r, g, b) at the pair's emission slot, conic
+        // unscaled (A = -2 A' ln2, B = -B' ln2, C = -2 C' ln2): no atomics,
+        // and a fixed summation order.  Groups: 0 colour 3 + opacity,
+        // 1 conic terms 3 (+ offset x), 2 offset y (four rows) with offset x.
         for (int t = threadIdx.x; t < 3 * m; t += NT) {
             const int k = t % m, j = t / m;
             const uint32_t hit = smask[k];
             float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            float sx = 0.0f;
             for (int q = 0; q < NW; ++q) {
                 // wave q wrote this partial only if the splat reaches its
                 // block and lies before its pixels' largest `last`
                 if (!((hit >> q) & 1u) || b_start + (uint32_t)k >= swlast[q]) continue;
                 const float4 a = part[k][q][j];
                 acc.x += a.x; acc.y += a.y; acc.z += a.z; acc.w += a.w;
+                if (j == 2) sx += part[k][q][1].w;
             }
-            part[k][0][j] = acc;
-        }
-        __syncthreads();
-        for (int q = threadIdx.x; q < 9 * m; q += NT) {
-            const int k = q / 9, t = q - 9 * k;
-            // summed partials: 0-2 colour, 3 opacity, 4-6 conic terms,
-            // 7 offset x, 8-11 offset y (four rows)
-            const float *pk = reinterpret_cast<const float *>(&part[k][0][0]);
-            float v;
-            if (t < 2) {
+            float *row = pair_grad + 9 * (size_t)sslot[k];
+            if (j == 0) {
+                row[5] = acc.w;
+                row[6] = acc.x;
+                row[7] = acc.y;
+                row[8] = acc.z;
+            } else if (j == 1) {
+                // conic terms dx^2, 2 dx dy, dy^2 times dL/dQ = -q/2
+                row[2] = -0.5f * acc.x;
+                row[3] = -acc.y;
+                row[4] = -0.5f * acc.z;
+            } else {
                 // dQ/ddx = 2(A dx + B dy), ddx/du = -1; partials hold -2 dL/dQ
                 const float4 b = sb[k];
                 const float A = -2.0f * kLn2 * b.x, B = -kLn2 * b.y, C = -2.0f * kLn2 * b.z;
-                const float sy = (pk[8] + pk[9]) + (pk[10] + pk[11]);
-                v = t == 0 ? A * pk[7] + B * sy : B * pk[7] + C * sy;
-            } else {
-                // conic terms dx^2, 2 dx dy, dy^2 times dL/dQ = -q/2
-                const int src = t < 5 ? t + 2 : (t == 5 ? 3 : t - 6);
-                v = (t == 3 ? -1.0f : t < 5 ? -0.5f : 1.0f) * pk[src];
+                const float sy = (acc.x + acc.y) + (acc.z + acc.w);
+                row[0] = A * sx + B * sy;
+                row[1] = B * sx + C * sy;
             }
-            pair_grad[9 * (size_t)sslot[k] + t] = v;
         }
         __syncthreads();
         b_end = b_start;
