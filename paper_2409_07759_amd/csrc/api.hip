@@ -99,6 +99,7 @@ void swgs::compute_layout(const LayoutDims &d, Layout &lay, size_t &consts_bytes
     sz[WB_DEPTH_KEY] = R * 4;
     sz[WB_TILE_COUNT] = R * 4;
     sz[WB_RECT] = R * 8;
+    sz[WB_RECT_SORTED] = R * 8;
     sz[WB_SPLAT] = R * kSplatFloats * 4;
     sz[WB_PAIR_KEY] = cap * 4;
     sz[WB_PAIR_VAL] = cap * 4;
@@ -247,8 +248,8 @@ void seq_forward(hipStream_t s, swgs_plan &p, uint8_t *ws, int view, float *imag
         // emitted in that order stably by tile: (tile, depth, record) order
         radix_sort_pairs(s, wsp<uint32_t>(ws, p, WB_DEPTH_KEY) + rec_lo, wsp<uint32_t>(ws, p, WB_REC_IDX) + rec_lo,
                          wsp<uint32_t>(ws, p, WB_KEY_ALT) + rec_lo, wsp<uint32_t>(ws, p, WB_IDX_ALT) + rec_lo, nullptr,
-                         rec_hi - rec_lo, rec_hi - rec_lo, 32, hist, tot, wsp<uint32_t>(ws, p, WB_TILE_COUNT),
-                         wsp<uint32_t>(ws, p, WB_PAIR_OFFSET));
+                         rec_hi - rec_lo, rec_hi - rec_lo, 32, hist, tot, wsp<uint2>(ws, p, WB_RECT),
+                         wsp<uint2>(ws, p, WB_RECT_SORTED), wsp<uint32_t>(ws, p, WB_PAIR_OFFSET));
         launch_pair_offsets(s, p, ws, rec_lo, rec_hi);
         launch_emit_pairs(s, p, ws, rec_lo, rec_hi);
         uint32_t *pc = wsp<uint32_t>(ws, p, WB_PAIR_COUNT);

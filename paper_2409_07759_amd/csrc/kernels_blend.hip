@@ -567,10 +567,10 @@ k_loss_final(const double *__restrict__ sums, double inv_3p, double *__restrict_
 // sums as one 36-byte row.
 constexpr int kReduceRounds = 8;
 constexpr int kReduceRecs = 4 * 7 * kReduceRounds;   // 4 waves
-constexpr int kReduceChunk = 1024;                   // pairs per LDS stage
+constexpr int kReduceChunk = 512;                    // pairs per LDS stage (18 KB: 8 blocks per CU)
 constexpr int kReduceVec = (9 * kReduceChunk + 3) / 4 + 1;
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 8)
 k_pair_grad_reduce(const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
                    const uint32_t *__restrict__ pair_count, const float *__restrict__ pair_grad, uint32_t cap,
                    uint32_t n, float *__restrict__ rec_grad) {
@@ -616,7 +616,14 @@ k_pair_grad_reduce(const uint32_t *__restrict__ order, const uint32_t *__restric
             const uint32_t jj = (uint32_t)(7 * (kReduceRounds * wave + q) + g);
             if (g < 7 && jj < nb) {
                 const uint32_t s0 = max(bound[jj], base), s1 = min(bound[jj + 1], base + cnt);
-                for (uint32_t i = s0; i < s1; ++i) acc[q] += buf[shift + 9 * (i - base) + t];
+                // rows added in slot order, four reads in flight at a time
+                const float *row = buf + shift + 9 * (s0 - base) + t;
+                uint32_t i = s0;
+                for (; i + 4 <= s1; i += 4, row += 36) {
+                    const float v0 = row[0], v1 = row[9], v2 = row[18], v3 = row[27];
+                    acc[q] = (((acc[q] + v0) + v1) + v2) + v3;
+                }
+                for (; i < s1; ++i, row += 9) acc[q] += row[0];
             }
         }
         __syncthreads();

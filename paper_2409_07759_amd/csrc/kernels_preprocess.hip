@@ -189,10 +189,11 @@ k_preprocess(const float *__restrict__ params, int n_slots, int deg, const Group
 // the 64 whose first slot is at or below it (a binary search over the
 // lanes' offsets), and the slot's tile is the record's rect tile at the
 // slot's row-major index.  Stores are coalesced, and a record covering
-// many tiles spreads over the wave instead of holding it up.
+// many tiles spreads over the wave instead of holding it up.  The rects
+// come in depth order (gathered by the depth sort's last pass).
 __global__ void __launch_bounds__(kBlock)
 k_emit_pairs(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ offsets,
-             const uint32_t *__restrict__ total_ptr, const uint2 *__restrict__ rect,
+             const uint32_t *__restrict__ total_ptr, const uint2 *__restrict__ rect_sorted,
              const uint32_t *__restrict__ rec_view_base, int n_views, const ViewDev *__restrict__ views,
              uint32_t n, uint32_t cap, uint32_t *__restrict__ pair_key, uint32_t *__restrict__ pair_val,
              uint32_t *__restrict__ pair_base) {
@@ -215,7 +216,7 @@ k_emit_pairs(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict
         }
         tbase = views[a].tile_base;
         tiles_x = (uint32_t)views[a].tiles_x;
-        const uint2 rc = rect[r];
+        const uint2 rc = rect_sorted[j];
         xy0 = rc.x;
         w = max((rc.y & 0xFFFFu) - (rc.x & 0xFFFFu), 1u);
         // the record's pairs take slots off .. off + count - 1 (the
@@ -331,7 +332,7 @@ void launch_emit_pairs(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t 
     const bool alt = radix_input_in_alt(p.tile_key_bits);
     hipLaunchKernelGGL(k_emit_pairs, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
                        wsp<uint32_t>(ws, p, WB_REC_IDX) + rec_lo, wsp<uint32_t>(ws, p, WB_PAIR_OFFSET),
-                       wsp<uint32_t>(ws, p, WB_PAIR_COUNT) + 2, wsp<uint2>(ws, p, WB_RECT),
+                       wsp<uint32_t>(ws, p, WB_PAIR_COUNT) + 2, wsp<uint2>(ws, p, WB_RECT_SORTED),
                        wsp<uint32_t>(ws, p, WB_REC_VIEW_BASE), (int)p.views.size(), wsp<ViewDev>(ws, p, WB_VIEWS),
                        n, (uint32_t)p.pair_cap, wsp<uint32_t>(ws, p, alt ? WB_PAIR_KEY_ALT : WB_PAIR_KEY),
                        wsp<uint32_t>(ws, p, alt ? WB_PAIR_VAL_ALT : WB_PAIR_VAL),

@@ -17,7 +17,7 @@ namespace swgs {
 constexpr int kMaxShDegree = 3;
 constexpr int kMaxRows = 11 + 3 * 16;      // F at SH degree 3
 constexpr int kGateChunk = 2048;           // slots per gating block
-constexpr int kSortBlocks = 1024;          // fixed grid of the radix-sort passes
+constexpr int kSortBlocks = 2048;          // fixed grid of the radix-sort passes
 constexpr int kSplatFloats = 12;           // floats per splat record
 constexpr int kXcds = 8;                   // accelerator complex dies (one L2 each)
 
@@ -85,7 +85,7 @@ enum WsBuf {
     WB_PAIR_OFFSET, WB_SORT_HIST, WB_SORT_TOTAL, WB_LAST, WB_LOSS_PART, WB_STATS, WB_STEP,
     WB_VIEWS, WB_GROUPS, WB_GROUP_VIEWS,
     WB_RELOC_W, WB_RELOC_FLAG, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_CNT, WB_RELOC_SCAN, WB_REG_PART, WB_COUNTERS, WB_CFLAGS,
-    WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE, WB_PAIR_BASE, WB_PAIR_GRAD,
+    WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE, WB_PAIR_BASE, WB_PAIR_GRAD, WB_RECT_SORTED,
     WB_COUNT
 };
 
@@ -157,14 +157,15 @@ void launch_tile_ranges(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t
 // (keys_alt, vals_alt) when radix_input_in_alt(bits) (an odd pass count),
 // else from (keys, vals); on return the sorted data is in (keys, vals) and
 // the other pair holds scratch.  32-bit keys take 4 passes (input in keys).
-// With gather_out, the last pass also writes gather_out[i] =
-// gather_src[vals[i]] for every sorted position i.
+// With gather_rect (tile rectangles packed as in the binning: x0 | y0 << 16,
+// x1 | y1 << 16), the last pass also writes, for every sorted position i,
+// rect_out[i] = gather_rect[vals[i]] and count_out[i] = its tile count.
 int radix_passes(int bits);
 bool radix_input_in_alt(int bits);
 void radix_sort_pairs(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *keys_alt,
                       uint32_t *vals_alt, const uint32_t *d_n, uint32_t n_fixed, uint32_t cap,
-                      int bits, uint32_t *hist, uint32_t *totals, const uint32_t *gather_src = nullptr,
-                      uint32_t *gather_out = nullptr);
+                      int bits, uint32_t *hist, uint32_t *totals, const uint2 *gather_rect = nullptr,
+                      uint2 *rect_out = nullptr, uint32_t *count_out = nullptr);
 // exclusive scan (in may equal out); *total_out = sum
 void exclusive_scan_u32(hipStream_t s, const uint32_t *in, uint32_t *out, uint32_t n,
                         uint32_t *total_out, uint32_t *scratch);
