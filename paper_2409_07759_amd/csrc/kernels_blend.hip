@@ -76,41 +76,51 @@ __device__ __forceinline__ void lane_pixel(int tid, int &px, int &py) {
     }
 }
 
-// Support box of a staged splat in pixel units: centre and half-extents of
-// {alpha >= 1/255} padded by one pixel (the same exact-support argument as
-// the tile ranges), from the FP32 record.
-__device__ __forceinline__ float4 cull_box(const float4 a, const float4 b) {
-    const float A = -2.0f * kLn2 * b.x, B = -kLn2 * b.y, C = -2.0f * kLn2 * b.z;
-    const float det = A * C - B * B;
-    const float kappa = fmaxf(0.0f, 2.0f * kLn2 * __log2f(255.0f * b.w));
-    // a nearly singular FP32 conic (very elongated splat) is never culled
-    if (!(det > 1e-3f * A * C)) return make_float4(0.0f, 0.0f, 3.0e38f, 3.0e38f);
-    const float rx = sqrtf(kappa * C / det) + 1.0f;
-    const float ry = sqrtf(kappa * A / det) + 1.0f;
-    return make_float4(a.x + 0.5f - a.z, a.y + 0.5f - a.w, rx, ry);
+// Bit w set if some pixel centre of wave w's 8x8 block of the tile at
+// (tx0, ty0) can take alpha >= 1/255 from the splat (a: position record,
+// b: pre-scaled conic and opacity).  With q(d) = -(A' dx^2 + B' dx dy +
+// C' dy^2) the exponent's positive quadratic form, alpha >= 1/255 iff
+// q <= log2(255 o).  The test takes the minimum of q over the rectangle of
+// the block's pixel centres grown by 1/64 px on every side: zero when the
+// splat centre lies inside, else attained on a face the centre sees (a
+// convex function's minimum over a box lies where the segment to its
+// unconstrained minimiser leaves the box), i.e. at the clamped 1D minimum
+// along at most one vertical and one horizontal face.  Threshold and
+// rectangle carry margins far above FP32 rounding, so no block holding a
+// blended pixel is culled; a nearly singular FP32 conic is never culled.
+template <int TW, int TH>
+__device__ __forceinline__ uint32_t support_wave_mask(const float4 a, const float4 b, int tx0, int ty0) {
+    constexpr int NWX = TW / 8, NW = (TW * TH) / 64;
+    constexpr float kEps = 1.0f / 64.0f;
+    const float qa = -b.x, qb = -b.y, qc = -b.z;
+    const float disc = 4.0f * qa * qc;
+    if (!(qa > 0.0f && qc > 0.0f && disc - qb * qb > 1e-3f * disc)) return (1u << NW) - 1u;
+    const float lam = __log2f(255.0f * b.w);
+    const float lim = lam + 1e-3f * (1.0f + fabsf(lam));
+    const float h2a = 0.5f / qa, h2c = 0.5f / qc;
+    uint32_t m = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        // offsets of the block's first pixel centre: (X0 - integer part) +
+        // (0.5 - fraction), the difference of integers exact
+        const float ex0 = (((float)(tx0 + (w % NWX) * 8) - a.x) + a.z) - kEps, ex1 = ex0 + (7.0f + 2.0f * kEps);
+        const float ey0 = (((float)(ty0 + (w / NWX) * 8) - a.y) + a.w) - kEps, ey1 = ey0 + (7.0f + 2.0f * kEps);
+        const bool inx = ex0 <= 0.0f && ex1 >= 0.0f, iny = ey0 <= 0.0f && ey1 >= 0.0f;
+        const float xe = ex0 > 0.0f ? ex0 : ex1;       // the vertical face the centre sees
+        const float ty = fminf(fmaxf(-qb * xe * h2c, ey0), ey1);
+        const float qv = inx ? 3.0e38f : (qa * xe + qb * ty) * xe + qc * ty * ty;
+        const float ye = ey0 > 0.0f ? ey0 : ey1;       // the horizontal face the centre sees
+        const float tx = fminf(fmaxf(-qb * ye * h2a, ex0), ex1);
+        const float qh = iny ? 3.0e38f : (qc * ye + qb * tx) * ye + qa * tx * tx;
+        const float qmin = (inx && iny) ? 0.0f : fminf(qv, qh);
+        m |= qmin <= lim ? (1u << w) : 0u;
+    }
+    return m;
 }
 
 // staged entry at a byte offset (16 x its index) of a float4 LDS array
 __device__ __forceinline__ float4 at16(const float4 *base, int off) {
     return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + off);
-}
-
-// true if the box can reach a pixel centre of the wave's 8x8 block
-__device__ __forceinline__ bool box_hits(const float4 bx, float wx0, float wy0) {
-    return (bx.x + bx.z >= wx0) & (bx.x - bx.z <= wx0 + 7.0f) & (bx.y + bx.w >= wy0) & (bx.y - bx.w <= wy0 + 7.0f);
-}
-
-// Bit w set if the box reaches wave w's 8x8 block of the tile at (tx0, ty0).
-template <int TW, int TH>
-__device__ __forceinline__ uint32_t box_wave_mask(const float4 bx, int tx0, int ty0) {
-    uint32_t m = 0;
-    constexpr int NWX = TW / 8, NW = (TW * TH) / 64;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-        const float wx0 = (float)(tx0 + (w % NWX) * 8) + 0.5f, wy0 = (float)(ty0 + (w / NWX) * 8) + 0.5f;
-        m |= box_hits(bx, wx0, wy0) ? (1u << w) : 0u;
-    }
-    return m;
 }
 
 // Each wave compacts, in ascending order, the batch entries whose mask has
@@ -185,7 +195,7 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
                 sa[k] = block_offset(a, tx * TW, ty * TH);
                 sb[k] = b;
                 sc[k] = splat[3 * (size_t)r + 2];
-                if (CULL) smask[k] = box_wave_mask<TW, TH>(cull_box(a, b), tx * TW, ty * TH);
+                if (CULL) smask[k] = support_wave_mask<TW, TH>(a, b, tx * TW, ty * TH);
             }
         }
         __syncthreads();
@@ -421,7 +431,7 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             sa[k] = block_offset(a, tx * TW, ty * TH);
             sb[k] = b;
             sc[k] = splat[3 * (size_t)r + 2];
-            smask[k] = CULL ? box_wave_mask<TW, TH>(cull_box(a, b), tx * TW, ty * TH) : 1u;
+            smask[k] = CULL ? support_wave_mask<TW, TH>(a, b, tx * TW, ty * TH) : 1u;
         }
         __syncthreads();
         const int wm = (int)min((uint32_t)m, wlast > b_start ? wlast - b_start : 0u);
