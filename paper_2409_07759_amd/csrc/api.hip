@@ -228,8 +228,10 @@ void seq_gate(hipStream_t s, swgs_plan &p, uint8_t *ws) {
 
 // forward of records [rec_lo, rec_hi) and tiles [tile_lo, tile_hi): one
 // view (plain) or all views (batched)
+// with ssim_follows the D-SSIM backward writes the whole of dL/dC (its L1
+// term included), so the forward only takes the loss
 void seq_forward(hipStream_t s, swgs_plan &p, uint8_t *ws, int view, float *images, const float *targets,
-                 float l1_weight = 1.0f) {
+                 float l1_weight = 1.0f, bool ssim_follows = false) {
     uint32_t rec_lo = 0, rec_hi = (uint32_t)p.R, tile_lo = 0, tile_hi = (uint32_t)p.T;
     if (view >= 0) {
         rec_lo = p.vdev[view].rec_base;
@@ -260,7 +262,8 @@ void seq_forward(hipStream_t s, swgs_plan &p, uint8_t *ws, int view, float *imag
     }
     {
         TimeScope t(p, s, TK_FWD);
-        launch_blend_forward(s, p, ws, images, targets, tile_lo, tile_hi, counters_of(p, ws), l1_weight);
+        launch_blend_forward(s, p, ws, images, targets, tile_lo, tile_hi, counters_of(p, ws), l1_weight,
+                             !ssim_follows);
     }
 }
 
@@ -681,13 +684,13 @@ static void seq_step_tail(hipStream_t s, swgs_plan &p, uint8_t *ws, const swgs_s
 static void seq_ssim(hipStream_t s, swgs_plan &p, uint8_t *ws, int v_lo, int v_hi, const float *images,
                      const float *targets, float lambda) {
     TimeScope t(p, s, TK_SSIM);
-    launch_ssim(s, p, ws, v_lo, v_hi, images, targets, lambda);
+    launch_ssim(s, p, ws, v_lo, v_hi, images, targets, lambda, 1.0f - lambda);
 }
 
 static void seq_window_batched(hipStream_t s, swgs_plan &p, uint8_t *ws, const swgs_step_cfg &cfg,
                                const float *targets, float *images) {
     seq_gate(s, p, ws);
-    seq_forward(s, p, ws, -1, images, targets, 1.0f - cfg.lambda_dssim);
+    seq_forward(s, p, ws, -1, images, targets, 1.0f - cfg.lambda_dssim, cfg.lambda_dssim > 0.0f);
     launch_loss_reduce(s, p, ws, &cfg, true);
     if (cfg.lambda_dssim > 0.0f) {
         seq_ssim(s, p, ws, 0, (int)p.views.size(), images, targets, cfg.lambda_dssim);
@@ -757,7 +760,7 @@ swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *p, void *workspace, s
         seq_gate(s, *p, ws);
         uint32_t *pc = wsp<uint32_t>(ws, *p, WB_PAIR_COUNT);
         for (int v = 0; v < (int)p->views.size(); ++v) {
-            seq_forward(s, *p, ws, v, images, targets, 1.0f - cfg->lambda_dssim);
+            seq_forward(s, *p, ws, v, images, targets, 1.0f - cfg->lambda_dssim, cfg->lambda_dssim > 0.0f);
             if (cfg->lambda_dssim > 0.0f) seq_ssim(s, *p, ws, v, v + 1, images, targets, cfg->lambda_dssim);
             uint32_t k = 0;
             HIP_TRY(ctx, hipMemcpyAsync(&k, pc, 4, hipMemcpyDeviceToHost, s));

@@ -247,9 +247,11 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         if (targets) {
             const float d0 = o0 - targets[o3], d1 = o1 - targets[o3 + HW], d2 = o2 - targets[o3 + 2 * HW];
             const float s = V.inv_norm * l1_weight;
-            dLdC[o3] = d0 > 0.0f ? s : (d0 < 0.0f ? -s : 0.0f);
-            dLdC[o3 + HW] = d1 > 0.0f ? s : (d1 < 0.0f ? -s : 0.0f);
-            dLdC[o3 + 2 * HW] = d2 > 0.0f ? s : (d2 < 0.0f ? -s : 0.0f);
+            if (dLdC) {   // (else the D-SSIM backward writes dL/dC, this L1 term included)
+                dLdC[o3] = d0 > 0.0f ? s : (d0 < 0.0f ? -s : 0.0f);
+                dLdC[o3 + HW] = d1 > 0.0f ? s : (d1 < 0.0f ? -s : 0.0f);
+                dLdC[o3 + 2 * HW] = d2 > 0.0f ? s : (d2 < 0.0f ? -s : 0.0f);
+            }
             l1 = (fabsf(d0) + fabsf(d1) + fabsf(d2)) * s;
             sq = d0 * d0 + d1 * d1 + d2 * d2;
         }
@@ -647,13 +649,14 @@ k_pair_grad_reduce(const uint32_t *__restrict__ order, const uint32_t *__restric
 
 template <int TW, int TH, int BATCH>
 void fwd_launch(hipStream_t s, const swgs_plan &p, uint8_t *ws, float *images, const float *targets,
-                uint32_t tile_lo, uint32_t tile_hi, unsigned long long *counters, float l1_weight) {
+                uint32_t tile_lo, uint32_t tile_hi, unsigned long long *counters, float l1_weight,
+                bool write_dldc) {
     auto kern = counters ? k_blend_fwd<TW, TH, BATCH, true> : k_blend_fwd<TW, TH, BATCH, false>;
     hipLaunchKernelGGL(kern, dim3(tile_hi - tile_lo), dim3(TW * TH), 0, s,
                        wsp<uint2>(ws, p, WB_TILE_RANGE), wsp<uint32_t>(ws, p, WB_PAIR_VAL),
                        wsp<float4>(ws, p, WB_SPLAT), wsp<ViewDev>(ws, p, WB_VIEWS),
                        (int)p.views.size(), tile_lo, images, wsp<float>(ws, p, WB_T_FINAL),
-                       wsp<uint32_t>(ws, p, WB_LAST), targets, wsp<float>(ws, p, WB_DLDC),
+                       wsp<uint32_t>(ws, p, WB_LAST), targets, write_dldc ? wsp<float>(ws, p, WB_DLDC) : nullptr,
                        wsp<double>(ws, p, WB_LOSS_PART) + 2 * (size_t)tile_lo, counters, l1_weight);
 }
 
@@ -685,9 +688,9 @@ void bwd_launch(hipStream_t s, const swgs_plan &p, uint8_t *ws, const float *dLd
 
 void launch_blend_forward(hipStream_t s, const swgs_plan &p, uint8_t *ws, float *images,
                           const float *targets, uint32_t tile_lo, uint32_t tile_hi,
-                          unsigned long long *counters, float l1_weight) {
+                          unsigned long long *counters, float l1_weight, bool write_dldc) {
     if (tile_hi <= tile_lo) return;
-    SWGS_DISPATCH_TILE(fwd_launch, s, p, ws, images, targets, tile_lo, tile_hi, counters, l1_weight);
+    SWGS_DISPATCH_TILE(fwd_launch, s, p, ws, images, targets, tile_lo, tile_hi, counters, l1_weight, write_dldc);
 }
 
 void launch_blend_backward(hipStream_t s, const swgs_plan &p, uint8_t *ws, const float *dLdC,

@@ -21,7 +21,9 @@
 // k_ssim_bwd: the window is symmetric, so the adjoint of a window sum is the
 // same window sum; it is applied to the three partial maps and
 //     dSSIM/dx(q) = (W*Sm)(q) + 2 x(q) (W*Sxx)(q) + y(q) (W*Sxy)(q)
-// (divided by the view's 3HW) is added, times -lambda / V, into dL/dC.
+// (divided by the view's 3HW), times -lambda / V, plus the L1 term
+// (1 - lambda) sign(x - y) / (V 3 H W), is written as dL/dC (the blend
+// forward leaves dL/dC to this kernel when the loss has a D-SSIM term).
 #include <cmath>
 
 #include "swgs_internal.h"
@@ -221,7 +223,7 @@ k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
 __global__ void __launch_bounds__(kThreads)
 k_ssim_bwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const float *__restrict__ img,
            const float *__restrict__ tgt, const float *__restrict__ part, float *__restrict__ dLdC,
-           float lambda, Taps taps) {
+           float lambda, float l1_weight, Taps taps) {
     __shared__ __align__(16) float4 lds[kLds];
     float(*sp)[kH][kPP] = reinterpret_cast<float(*)[kH][kPP]>(lds);   // the three map derivatives, planar
     float4(*hs)[kTP] = reinterpret_cast<float4(*)[kTP]>(lds);         // their row sums (w unused)
@@ -294,10 +296,10 @@ k_ssim_bwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
     __syncthreads();
     const int c = threadIdx.x % kT, r0 = kSeg * (threadIdx.x / kT);
     const int x = tl.x0 + c;
-    // this thread's pixels: their image, target and dL/dC loads go out
-    // before the column pass
+    // this thread's pixels: their image and target loads go out before the
+    // column pass
     size_t o[kSeg];
-    float xi[kSeg], ti[kSeg], gi[kSeg];
+    float xi[kSeg], ti[kSeg];
 #pragma unroll
     for (int j = 0; j < kSeg; ++j) {
         const int y = tl.y0 + r0 + j;
@@ -305,7 +307,6 @@ k_ssim_bwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
         o[j] = in ? 3 * (size_t)V.pix_base + (size_t)tl.ch * HW + (size_t)y * V.width + x : 0;
         xi[j] = in ? img[o[j]] : 0.0f;
         ti[j] = in ? tgt[o[j]] : 0.0f;
-        gi[j] = in ? dLdC[o[j]] : 0.0f;
     }
     float a[kSeg], b[kSeg], g[kSeg];
 #pragma unroll
@@ -324,13 +325,17 @@ k_ssim_bwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
         }
     }
     if (x >= V.width) return;
-    const float scale = lambda * V.inv_norm;
+    const float scale = lambda * V.inv_norm, s1 = V.inv_norm * l1_weight;
 #pragma unroll
     for (int j = 0; j < kSeg; ++j) {
         if (tl.y0 + r0 + j >= V.height) continue;
-        // d/dC of lambda (1 - SSIM_v) / V with SSIM_v = sum S / (3 H W):
-        // -lambda inv_norm (W*Sm + 2 x W*Sxx + y W*Sxy), inv_norm = 1 / (V 3 H W)
-        dLdC[o[j]] = gi[j] - scale * (a[j] + 2.0f * xi[j] * b[j] + ti[j] * g[j]);
+        // the L1 term as the blend forward forms it (the same FP32 values
+        // and operations), then d/dC of lambda (1 - SSIM_v) / V with
+        // SSIM_v = sum S / (3 H W): -lambda inv_norm (W*Sm + 2 x W*Sxx +
+        // y W*Sxy), inv_norm = 1 / (V 3 H W)
+        const float d = xi[j] - ti[j];
+        const float gl1 = d > 0.0f ? s1 : (d < 0.0f ? -s1 : 0.0f);
+        dLdC[o[j]] = gl1 - scale * (a[j] + 2.0f * xi[j] * b[j] + ti[j] * g[j]);
     }
 }
 
@@ -380,7 +385,7 @@ size_t ssim_tiles(int width, int height) {
 }
 
 void launch_ssim(hipStream_t s, const swgs_plan &p, uint8_t *ws, int view_lo, int view_hi, const float *images,
-                 const float *targets, float lambda) {
+                 const float *targets, float lambda, float l1_weight) {
     if (!images || !targets) return;   // callers always pass both (the window step renders into the workspace)
     const uint32_t t_lo = p.vdev[view_lo].ssim_tile_base;
     const uint32_t t_hi = view_hi < (int)p.views.size() ? p.vdev[view_hi].ssim_tile_base : (uint32_t)p.Tssim;
@@ -392,7 +397,7 @@ void launch_ssim(hipStream_t s, const swgs_plan &p, uint8_t *ws, int view_lo, in
                        window_taps());
     hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(kThreads), 0, s, wsp<ViewDev>(ws, p, WB_VIEWS), (int)p.views.size(),
                        t_lo, images, targets, wsp<float>(ws, p, WB_SSIM_PART), wsp<float>(ws, p, WB_DLDC), lambda,
-                       window_taps());
+                       l1_weight, window_taps());
 }
 
 void launch_ssim_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, float lambda) {

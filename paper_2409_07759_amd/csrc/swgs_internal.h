@@ -173,10 +173,11 @@ void exclusive_scan_u32(hipStream_t s, const uint32_t *in, uint32_t *out, uint32
 // Blend (kernels_blend.hip)
 // counters (nullable): [0] pixel x list entries evaluated by the forward,
 // [1] by the backward
-// l1_weight scales the fused L1 term and its gradient (1 - lambda_dssim)
+// l1_weight scales the fused L1 term and its gradient (1 - lambda_dssim);
+// without write_dldc only the loss is taken (the D-SSIM backward writes dL/dC)
 void launch_blend_forward(hipStream_t s, const swgs_plan &p, uint8_t *ws, float *images,
                           const float *targets, uint32_t tile_lo, uint32_t tile_hi,
-                          unsigned long long *counters, float l1_weight);
+                          unsigned long long *counters, float l1_weight, bool write_dldc = true);
 void launch_blend_backward(hipStream_t s, const swgs_plan &p, uint8_t *ws, const float *dLdC,
                            uint32_t tile_lo, uint32_t tile_hi, unsigned long long *counters);
 // Compact update record (kernels_codec.hip)
@@ -195,11 +196,12 @@ void launch_pair_grad_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, uin
 void launch_loss_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, const swgs_step_cfg *cfg,
                         bool with_reg);
 
-// D-SSIM term (kernels_ssim.hip): SSIM of views [view_lo, view_hi) with its
-// gradient added into dL/dC, then the weighted SSIM sums added to stats[0]
+// D-SSIM term (kernels_ssim.hip): SSIM of views [view_lo, view_hi); dL/dC of
+// those views is written whole: the L1 term (weight l1_weight) plus the
+// D-SSIM term; then the weighted SSIM sums are added to stats[0]
 size_t ssim_tiles(int width, int height);
 void launch_ssim(hipStream_t s, const swgs_plan &p, uint8_t *ws, int view_lo, int view_hi, const float *images,
-                 const float *targets, float lambda);
+                 const float *targets, float lambda, float l1_weight);
 void launch_ssim_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, float lambda);
 
 // Backward preprocess, step, relocation, mature (kernels_step.hip)
