@@ -42,7 +42,9 @@ constexpr int kRowItems = kH * (kT / kSeg);   // row pass: every staged row x 8 
 constexpr int kColItems = kT * (kT / kSeg);   // column pass: 32 columns x 8 segments (256)
 static_assert(kColItems == kThreads, "one column item per thread");
 constexpr int kItemRounds = (kRowItems + kThreads - 1) / kThreads;   // row items per thread (2)
-constexpr int kStage = (kH * kH + kThreads - 1) / kThreads;   // staged elements per thread (7)
+constexpr int kWaves = kThreads / 64;
+constexpr int kStageRows = (kH + kWaves - 1) / kWaves;         // staged rows per wave (11)
+static_assert(kH <= 64, "one lane per staged column");
 // LDS row pitches: in the row pass consecutive lanes take consecutive rows,
 // so a row's pitch in dwords is kept an odd multiple of 4 and the 16-byte
 // accesses of 8 consecutive lanes fall on disjoint banks
@@ -109,21 +111,25 @@ k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
     const float *X = img + 3 * (size_t)V.pix_base + (size_t)tl.ch * HW;
     const float *Y = tgt + 3 * (size_t)V.pix_base + (size_t)tl.ch * HW;
     {
-        // all of a thread's loads in flight before its LDS stores
-        float2 v[kStage];
+        // lane l stages column l, wave w rows w, w + 4, ... (row offsets and
+        // row bounds are wave-uniform); all of a thread's loads are in
+        // flight before its LDS stores
+        const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int xx = tl.x0 + lane - kR;
+        const bool col = lane < kH && xx >= 0 && xx < V.width;
+        const uint32_t cx = col ? (uint32_t)xx : 0u;
+        float2 v[kStageRows];
 #pragma unroll
-        for (int u = 0; u < kStage; ++u) {
-            const int i = threadIdx.x + u * kThreads;
-            const int r = i / kH, c = i - r * kH;
-            const int yy = tl.y0 + r - kR, xx = tl.x0 + c - kR;
-            const bool in = i < kH * kH && xx >= 0 && xx < V.width && yy >= 0 && yy < V.height;
-            const size_t o = in ? (size_t)yy * V.width + xx : 0;
-            v[u] = make_float2(in ? X[o] : 0.0f, in ? Y[o] : 0.0f);
+        for (int u = 0; u < kStageRows; ++u) {
+            const int r = wave + kWaves * u, yy = tl.y0 + r - kR;
+            const bool row = r < kH && yy >= 0 && yy < V.height;   // wave-uniform
+            const uint32_t o = (row ? (uint32_t)yy : 0u) * (uint32_t)V.width + cx;
+            v[u] = make_float2(col && row ? X[o] : 0.0f, col && row ? Y[o] : 0.0f);
         }
 #pragma unroll
-        for (int u = 0; u < kStage; ++u) {
-            const int i = threadIdx.x + u * kThreads;
-            if (i < kH * kH) sxy[i / kH][i % kH] = v[u];
+        for (int u = 0; u < kStageRows; ++u) {
+            const int r = wave + kWaves * u;
+            if (lane < kH && r < kH) sxy[r][lane] = v[u];
         }
     }
     __syncthreads();
@@ -168,7 +174,7 @@ k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
         for (int j = 0; j < kSeg; ++j) hq[r][c0 + j] = rs[u][j];
     }
     __syncthreads();
-    double s_val = 0.0;
+    float s_thr = 0.0f;   // this thread's (at most four) S values
     {
         const int c = threadIdx.x % kT, r0 = kSeg * (threadIdx.x / kT);
         float mx[kSeg], my[kSeg], ess[kSeg], exy[kSeg];
@@ -206,10 +212,11 @@ k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
             P[o] = 2.0f * my[j] * (B - A) * rCD - 2.0f * mx[j] * S * rC + 2.0f * mx[j] * S * rD;
             P[o + HW] = -S * rD;
             P[o + 2 * HW] = 2.0f * A * rCD;
-            s_val += (double)S;
+            s_thr += S;
         }
     }
     // tile sum of S, weighted lambda / (V 3 H W) = lambda * inv_norm
+    double s_val = (double)s_thr;
     for (int o = 32; o > 0; o >>= 1) s_val += __shfl_xor(s_val, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s_val;
     __syncthreads();
@@ -232,24 +239,26 @@ k_ssim_bwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
     const size_t HW = (size_t)V.width * V.height;
     const float *P = part + 9 * (size_t)V.pix_base + (size_t)tl.ch * 3 * HW;
     {
-        // all of a thread's loads in flight before its LDS stores
-        float v[3][kStage];
+        // staged as in the forward: lane l column l, wave w rows w, w + 4, ...
+        const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int xx = tl.x0 + lane - kR;
+        const bool col = lane < kH && xx >= 0 && xx < V.width;
+        const uint32_t cx = col ? (uint32_t)xx : 0u;
+        float v[3][kStageRows];
 #pragma unroll
-        for (int u = 0; u < kStage; ++u) {
-            const int i = threadIdx.x + u * kThreads;
-            const int r = i / kH, c = i - r * kH;
-            const int yy = tl.y0 + r - kR, xx = tl.x0 + c - kR;
-            const bool in = i < kH * kH && xx >= 0 && xx < V.width && yy >= 0 && yy < V.height;
-            const size_t o = in ? (size_t)yy * V.width + xx : 0;
+        for (int u = 0; u < kStageRows; ++u) {
+            const int r = wave + kWaves * u, yy = tl.y0 + r - kR;
+            const bool row = r < kH && yy >= 0 && yy < V.height;   // wave-uniform
+            const uint32_t o = (row ? (uint32_t)yy : 0u) * (uint32_t)V.width + cx;
 #pragma unroll
-            for (int m = 0; m < 3; ++m) v[m][u] = in ? P[o + m * HW] : 0.0f;
+            for (int m = 0; m < 3; ++m) v[m][u] = col && row ? P[(size_t)m * HW + o] : 0.0f;
         }
 #pragma unroll
-        for (int u = 0; u < kStage; ++u) {
-            const int i = threadIdx.x + u * kThreads;
-            if (i >= kH * kH) continue;
+        for (int u = 0; u < kStageRows; ++u) {
+            const int r = wave + kWaves * u;
+            if (lane >= kH || r >= kH) continue;
 #pragma unroll
-            for (int m = 0; m < 3; ++m) sp[m][i / kH][i % kH] = v[m][u];
+            for (int m = 0; m < 3; ++m) sp[m][r][lane] = v[m][u];
         }
     }
     __syncthreads();
