@@ -447,6 +447,9 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             const Px e = eval_splat(lxf, lyf, at16(sa, off), at16(sb, off));
             const float alpha = fminf(0.99f, e.og);
             const bool contrib = off < lim && alpha >= (1.0f / 255.0f);
+            // this lane's partial slot of the entry (off = 16 x entry index)
+            float *pdst = reinterpret_cast<float *>(reinterpret_cast<char *>(&part[0][wave][0]) +
+                                                    off * (NW * kTerm / 4)) + pslot;
             // T and W change only where the splat was blended: a wave with
             // no such pixel skips the gradient (branch-free inside) and
             // stores zero partials
@@ -474,7 +477,7 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
                 const float s8 = row_sum16(v8);
                 part_out = r16 < 2 ? y : s8;
             }
-            if (r16 < 3) reinterpret_cast<float *>(&part[0][wave][0])[(off >> 4) * (NW * kTerm) + pslot] = part_out;
+            if (r16 < 3) *pdst = part_out;
         }
         __syncthreads();
         // flush: one thread per (splat, term group) sums the group's row

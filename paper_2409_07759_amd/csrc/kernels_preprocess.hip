@@ -139,10 +139,13 @@ k_preprocess(const float *__restrict__ params, int n_slots, int deg, const Group
                 B = -cb * id;
                 C = ca * id;
                 const double hx = sqrt(kappa * ca), hy = sqrt(kappa * cc);
-                x0 = clip_tile(floor((u - hx - 1.0) / tile_w), V.tiles_x);
-                x1 = clip_tile(floor((u + hx + 1.0) / tile_w) + 1.0, V.tiles_x);
-                y0 = clip_tile(floor((v - hy - 1.0) / tile_h), V.tiles_y);
-                y1 = clip_tile(floor((v + hy + 1.0) / tile_h) + 1.0, V.tiles_y);
+                // tile sizes are powers of two: the product with the
+                // reciprocal is the quotient exactly
+                const double itw = 1.0 / (double)tile_w, ith = 1.0 / (double)tile_h;
+                x0 = clip_tile(floor((u - hx - 1.0) * itw), V.tiles_x);
+                x1 = clip_tile(floor((u + hx + 1.0) * itw) + 1.0, V.tiles_x);
+                y0 = clip_tile(floor((v - hy - 1.0) * ith), V.tiles_y);
+                y1 = clip_tile(floor((v + hy + 1.0) * ith) + 1.0, V.tiles_y);
                 vis = x0 < x1 && y0 < y1;
             }
         }
