@@ -3,7 +3,8 @@
 For a pool and a set of views it builds one plan per candidate, times the
 forward + backward of the whole view set (no parameter update, so every
 candidate sees the same scene) with device-side synchronisation, and returns
-the fastest.  Results are cached in a JSON file keyed by the workload shape
+the fastest (the default, first candidate unless another beats it by more
+than 1%).  Results are cached in a JSON file keyed by the workload shape
 (view resolutions, view count, live-slot count, SH degree).
 """
 from __future__ import annotations
@@ -17,6 +18,7 @@ import torch
 
 from . import swgs
 
+TIE_BAND = 0.01
 CANDIDATES = [((16, 16), 256), ((16, 16), 128), ((8, 8), 64), ((8, 8), 128), ((32, 8), 256), ((32, 8), 128)]
 CACHE = os.environ.get("SWGS_AUTOTUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "swgs_autotune.json"))
 
@@ -81,7 +83,12 @@ def tune(ctx: "swgs.Context", pool: "swgs.Pool", views, reps: int = 3, use_cache
                 f"blended {ev[2]:.3g}")
         plan.close()
         del dl
+    # the first candidate (the default shape) is kept unless another is
+    # faster by more than TIE_BAND: differences inside run-to-run noise do
+    # not flip the choice
     best = min(table, key=lambda r: r[2])
+    if best is not table[0] and best[2] > table[0][2] * (1.0 - TIE_BAND):
+        best = table[0]
     if use_cache:
         cache = _load()
         cache[key] = dict(tile=best[0], lds_batch=best[1], table=table)
