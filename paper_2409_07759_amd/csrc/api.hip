@@ -467,7 +467,8 @@ swgs_status swgs_plan_create(swgs_context *ctx, const swgs_pool *pool, const swg
         return fail(ctx, SWGS_ERR_INVALID_ARG, "pair_capacity must be in (0, 2^32 - 16)");
     for (int v = 0; v < n_views; ++v) {
         const swgs_view &w = views[v];
-        if (w.width <= 0 || w.height <= 0 || w.width > 16384 * 8 || w.height > 16384 * 8)
+        if (w.width <= 0 || w.height <= 0 || w.width > 16384 * 8 || w.height > 16384 * 8 ||
+            (int64_t)w.width * w.height > (int64_t)INT32_MAX)
             return fail(ctx, SWGS_ERR_INVALID_ARG, "view " + std::to_string(v) + ": bad size");
         if (!(w.fx > 0 && w.fy > 0)) return fail(ctx, SWGS_ERR_INVALID_ARG, "view " + std::to_string(v) + ": focal must be > 0");
     }

@@ -62,6 +62,80 @@ __device__ __forceinline__ float dpp_f(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, true));
 }
 
+// sum over the 16 lanes of each DPP row; every lane of a row holds its row sum
+__device__ __forceinline__ float row_sum16(float x) {
+    x += dpp_f<0xB1, 0xf>(x);   // quad_perm [1,0,3,2]
+    x += dpp_f<0x4E, 0xf>(x);   // quad_perm [2,3,0,1]
+    x += dpp_f<0x124, 0xf>(x);  // row_ror:4
+    x += dpp_f<0x128, 0xf>(x);  // row_ror:8
+    return x;
+}
+
+// One exchange step of a transposed reduction: lanes whose `bit` is clear
+// keep the partial sum of a, the others that of c, each adding the partner
+// lane's copy (the partner, selected by CTRL, has the opposite bit).
+template <int CTRL>
+__device__ __forceinline__ float xstep(float a, float c, bool bit) {
+    const float keep = bit ? c : a, send = bit ? a : c;
+    return keep + dpp_f<CTRL, 0xf>(send);
+}
+
+// One exchange step across the two 32-lane halves (x = 32) or across the
+// two rows of each row pair (x = 16) with gfx950's lane-swap instructions:
+// the result holds a's pair sum in the lower half / even rows and c's in
+// the upper half / odd rows (two instructions per step).
+__device__ __forceinline__ float xswap32(float a, float c) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(c), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float xswap16(float a, float c) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(c), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Wave sums of eight values at once (a transposed reduction): the half and
+// row-pair swaps leave row r of x0 / x1 holding values (0, 2, 1, 3)[r] /
+// (4, 6, 5, 7)[r], each summed over 4 lanes; an xor-1 exchange puts x0's
+// value on even lanes and x1's on odd ones, and xor-2, rotate-4 and
+// rotate-8 adds finish the sums.  Lane l then holds the wave sum of value
+// 4 (l & 1) + brev2(l >> 4), brev2 = (0, 2, 1, 3); 18 VALU operations.
+__device__ __forceinline__ float wave_sum_x8(float v0, float v1, float v2, float v3, float v4, float v5,
+                                             float v6, float v7, int lane) {
+    const float w0 = xswap32(v0, v1), w1 = xswap32(v2, v3), w2 = xswap32(v4, v5), w3 = xswap32(v6, v7);
+    const float x0 = xswap16(w0, w1), x1 = xswap16(w2, w3);
+    float y = xstep<0xB1>(x0, x1, lane & 1);
+    y += dpp_f<0x4E, 0xf>(y);    // quad_perm [2,3,0,1]
+    y += dpp_f<0x124, 0xf>(y);   // row_ror:4
+    y += dpp_f<0x128, 0xf>(y);   // row_ror:8
+    return y;
+}
+
+// max over the 16 lanes of each DPP row; every lane of a row holds it
+__device__ __forceinline__ uint32_t row_max16(uint32_t x) {
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xf, 0xf, true));   // quad_perm [1,0,3,2]
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xf, 0xf, true));   // quad_perm [2,3,0,1]
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x124, 0xf, 0xf, true));  // row_ror:4
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x128, 0xf, 0xf, true));  // row_ror:8
+    return x;
+}
+
+// Whole-wave max / sum, every lane holding it: row reductions, then the
+// half swap and the row-pair swap of each lane's value with itself (each
+// lane meets its partner in the other half, then in the other row of its
+// pair), 8 VALU operations.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+    x = row_max16(x);
+    const auto h = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    x = max(h[0], h[1]);
+    const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return max(r[0], r[1]);
+}
+__device__ __forceinline__ float wave_sum_f32(float x) {
+    x = row_sum16(x);
+    x = xswap32(x, x);
+    return xswap16(x, x);
+}
+
 // Pixel of a thread: each wave covers an 8x8 block of the tile (a 16x16
 // tile is 2x2 blocks, 32x8 is 4x1), lanes row-major inside the block.
 template <int TW, int TH>
@@ -270,10 +344,8 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         }
     }
     if (targets) {
-        for (int o = 32; o > 0; o >>= 1) {
-            l1 += __shfl_xor(l1, o, 64);
-            sq += __shfl_xor(sq, o, 64);
-        }
+        l1 = wave_sum_f32(l1);
+        sq = wave_sum_f32(sq);
         if ((threadIdx.x & 63) == 0) {
             red[0][threadIdx.x >> 6] = l1;
             red[1][threadIdx.x >> 6] = sq;
@@ -286,54 +358,6 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             loss_part[2 * (size_t)lt_idx + 1] = b;
         }
     }
-}
-
-// sum over the 16 lanes of each DPP row; every lane of a row holds its row sum
-__device__ __forceinline__ float row_sum16(float x) {
-    x += dpp_f<0xB1, 0xf>(x);   // quad_perm [1,0,3,2]
-    x += dpp_f<0x4E, 0xf>(x);   // quad_perm [2,3,0,1]
-    x += dpp_f<0x124, 0xf>(x);  // row_ror:4
-    x += dpp_f<0x128, 0xf>(x);  // row_ror:8
-    return x;
-}
-
-// One exchange step of a transposed reduction: lanes whose `bit` is clear
-// keep the partial sum of a, the others that of c, each adding the partner
-// lane's copy (the partner, selected by CTRL, has the opposite bit).
-template <int CTRL>
-__device__ __forceinline__ float xstep(float a, float c, bool bit) {
-    const float keep = bit ? c : a, send = bit ? a : c;
-    return keep + dpp_f<CTRL, 0xf>(send);
-}
-
-// One exchange step across the two 32-lane halves (x = 32) or across the
-// two rows of each row pair (x = 16) with gfx950's lane-swap instructions:
-// the result holds a's pair sum in the lower half / even rows and c's in
-// the upper half / odd rows (two instructions per step).
-__device__ __forceinline__ float xswap32(float a, float c) {
-    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(c), false, false);
-    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-__device__ __forceinline__ float xswap16(float a, float c) {
-    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(c), false, false);
-    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-
-// Wave sums of eight values at once (a transposed reduction): the half and
-// row-pair swaps leave row r of x0 / x1 holding values (0, 2, 1, 3)[r] /
-// (4, 6, 5, 7)[r], each summed over 4 lanes; an xor-1 exchange puts x0's
-// value on even lanes and x1's on odd ones, and xor-2, rotate-4 and
-// rotate-8 adds finish the sums.  Lane l then holds the wave sum of value
-// 4 (l & 1) + brev2(l >> 4), brev2 = (0, 2, 1, 3); 18 VALU operations.
-__device__ __forceinline__ float wave_sum_x8(float v0, float v1, float v2, float v3, float v4, float v5,
-                                             float v6, float v7, int lane) {
-    const float w0 = xswap32(v0, v1), w1 = xswap32(v2, v3), w2 = xswap32(v4, v5), w3 = xswap32(v6, v7);
-    const float x0 = xswap16(w0, w1), x1 = xswap16(w2, w3);
-    float y = xstep<0xB1>(x0, x1, lane & 1);
-    y += dpp_f<0x4E, 0xf>(y);    // quad_perm [2,3,0,1]
-    y += dpp_f<0x124, 0xf>(y);   // row_ror:4
-    y += dpp_f<0x128, 0xf>(y);   // row_ror:8
-    return y;
 }
 
 // Backward batches are BB splats; per splat each wave reduces eight of its
@@ -360,7 +384,6 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     __shared__ uint16_t slist[CULL ? NW : 1][CULL ? BB : 1];
     __shared__ uint32_t sslot[BB];        // emission slot of each batch pair
     __shared__ float4 part[BB][NW][kTerm / 4];
-    __shared__ uint32_t smax;
     __shared__ uint32_t swlast[NW];
     __shared__ unsigned long long cnt_evals;
     const uint32_t lt_idx = xcd_order(blockIdx.x, gridDim.x);   // neighbouring tiles share an XCD's L2
@@ -378,25 +401,30 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
     uint32_t lst = 0;
     if (inside) {
-        const size_t HW = (size_t)V.width * V.height;
-        const size_t pix = (size_t)V.pix_base + (size_t)y * V.width + x;
-        const size_t o3 = 3 * (size_t)V.pix_base + (size_t)y * V.width + x;
-        T = T_final[pix];
-        lst = last_in[pix];
-        g0 = dLdC[o3];
-        g1 = dLdC[o3 + HW];
-        g2 = dLdC[o3 + 2 * HW];
+        // per-view bases (64-bit, wave-uniform), in-view offsets in 32 bits
+        // (a view holds fewer than 2^31 pixels)
+        const uint32_t HW = (uint32_t)V.width * (uint32_t)V.height;
+        const uint32_t o = (uint32_t)y * (uint32_t)V.width + (uint32_t)x;
+        const float *dl = dLdC + 3 * V.pix_base;
+        T = (T_final + V.pix_base)[o];
+        lst = (last_in + V.pix_base)[o];
+        g0 = dl[o];
+        g1 = dl[o + HW];
+        g2 = dl[o + 2 * HW];
     }
-    // a wave never needs splats at or beyond its pixels' largest `last`
-    uint32_t wlast = lst;
-    for (int o = 32; o > 0; o >>= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, o, 64));
-    if (threadIdx.x == 0) { smax = 0; cnt_evals = 0; }
+    // a wave never needs splats at or beyond its pixels' largest `last`;
+    // the tile's largest is the largest of its waves'
+    const uint32_t wlast = wave_max_u32(lst);
+    if (threadIdx.x == 0) cnt_evals = 0;
     if ((threadIdx.x & 63) == 0) swlast[threadIdx.x >> 6] = wlast;
     __syncthreads();
-    atomicMax(&smax, lst);
-    if (counters) atomicAdd(&cnt_evals, (unsigned long long)lst);
-    __syncthreads();
-    const uint32_t nmax = smax;
+    if (counters) {
+        atomicAdd(&cnt_evals, (unsigned long long)lst);
+        __syncthreads();
+    }
+    uint32_t nmax = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) nmax = max(nmax, swlast[w]);
     if (counters && threadIdx.x == 0) atomicAdd(counters + 4 * (blockIdx.x % kCounterSlots) + 1, cnt_evals);
     // A pair's slot: the record's first emission slot plus this tile's
     // row-major index inside the record's tile rect.
