@@ -515,8 +515,7 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         // unscaled (A = -2 A' ln2, B = -B' ln2, C = -2 C' ln2): no atomics,
         // and a fixed summation order.  Groups: 0 colour 3 + opacity,
         // 1 conic terms 3 (+ offset x), 2 offset y (four rows) with offset x.
-        for (int t = threadIdx.x; t < 3 * m; t += NT) {
-            const int k = t % m, j = t / m;
+        auto flush = [&](int k, int j) {
             const uint32_t hit = smask[k];
             float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             float sx = 0.0f;
@@ -547,6 +546,13 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
                 row[0] = A * sx + B * sy;
                 row[1] = B * sx + C * sy;
             }
+        };
+        if constexpr (NT >= 3 * BB) {
+            // wave j takes term group j, lane k Gaussian k (the group's
+            // branch is wave-uniform)
+            if (threadIdx.x < 3 * BB && (int)(threadIdx.x & 63) < m) flush((int)(threadIdx.x & 63), (int)(threadIdx.x >> 6));
+        } else {
+            for (int t = threadIdx.x; t < 3 * m; t += NT) flush(t % m, t / m);
         }
         __syncthreads();
         b_end = b_start;
