@@ -87,6 +87,11 @@ k_preprocess(const float *__restrict__ params, int n_slots, int deg, const Group
     const bool faint = 255.0 * op <= 1.0;
     const double kappa = faint ? 0.0 : 2.0 * log(255.0 * op);
     const int nk = (deg + 1) * (deg + 1);
+    // the slot's SH coefficients, loaded once for all cameras (their loads
+    // overlap the covariance arithmetic)
+    float sh[48];
+#pragma unroll
+    for (int q = 0; q < 48; ++q) sh[q] = q < 3 * nk ? params[(11 + q) * S + slot] : 0.0f;
 
     for (int k = 0; k < G.n_views; ++k) {
         const int vi = group_views[G.view_first + k];
@@ -165,9 +170,12 @@ k_preprocess(const float *__restrict__ params, int n_slots, int deg, const Group
         double Y[16];
         sh_basis64(deg, dx, dy, dz, Y);
         double col[3];
+#pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             double acc = 0.0;
-            for (int kk = 0; kk < nk; ++kk) acc += Y[kk] * (double)params[(11 + 3 * kk + ch) * S + slot];
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk)
+                if (kk < nk) acc += Y[kk] * (double)sh[3 * kk + ch];
             acc += 0.5;
             col[ch] = acc > 0.0 ? acc : 0.0;
             flags |= acc > 0.0 ? 0u : (1u << ch);
