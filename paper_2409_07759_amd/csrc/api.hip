@@ -135,6 +135,7 @@ void swgs::compute_layout(const LayoutDims &d, Layout &lay, size_t &consts_bytes
     sz[WB_SSIM_SUM] = (3 * d.Tssim + 256) * 8;          // per (SSIM tile, channel), then 256 chunk sums
     sz[WB_IMAGE] = 3 * P * 4;                         // renders when the caller passes no image buffer
     sz[WB_PAIR_BASE] = R * 4;                         // first emission slot of each record
+    sz[WB_PAIR_MASK] = (cap + 3) / 4 * 4;             // each pair's support mask over the tile's waves (forward -> backward)
     sz[WB_PAIR_GRAD] = cap * 9 * 4 + 16;              // 9 gradient terms per (tile, record) pair, emission
                                                       // order (+16: the reduce reads whole 16-byte vectors)
     if (d.forward_only) {
@@ -142,7 +143,7 @@ void swgs::compute_layout(const LayoutDims &d, Layout &lay, size_t &consts_bytes
         // no loss, no step; pair buffers may live outside (ext)
         for (int b : {WB_ACTIVE_LIST, WB_GATE_BLK, WB_POS_OF, WB_DLDC, WB_REC_GRAD, WB_LOSS_PART, WB_RELOC_W,
                       WB_RELOC_FLAG, WB_RELOC_CNT, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_SCAN, WB_REG_PART,
-                      WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE, WB_PAIR_BASE, WB_PAIR_GRAD})
+                      WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE, WB_PAIR_BASE, WB_PAIR_GRAD, WB_PAIR_MASK})
             sz[b] = 0;
     }
     // order: constant block, then the rest

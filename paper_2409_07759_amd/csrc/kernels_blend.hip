@@ -231,7 +231,7 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             int n_views, uint32_t tile_lo, float *__restrict__ images,
             float *__restrict__ T_final, uint32_t *__restrict__ last_out,
             const float *__restrict__ targets, float *__restrict__ dLdC, double *__restrict__ loss_part,
-            unsigned long long *__restrict__ counters, float l1_weight) {
+            unsigned long long *__restrict__ counters, float l1_weight, uint8_t *__restrict__ pair_mask) {
     constexpr int NT = TW * TH;
     static_assert(64 % TW == 0 && 64 % TH == 0, "a tile lies inside one 64x64-aligned block");
     constexpr bool CULL = NT > 64;        // per-wave support-box lists
@@ -269,7 +269,11 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
                 sa[k] = block_offset(a, tx * TW, ty * TH);
                 sb[k] = b;
                 sc[k] = splat[3 * (size_t)r + 2];
-                if (CULL) smask[k] = support_wave_mask<TW, TH>(a, b, tx * TW, ty * TH);
+                if (CULL) {
+                    const uint32_t mk = support_wave_mask<TW, TH>(a, b, tx * TW, ty * TH);
+                    smask[k] = mk;
+                    if (pair_mask) pair_mask[rg.x + b0 + k] = (uint8_t)mk;   // for the backward
+                }
             }
         }
         __syncthreads();
@@ -373,7 +377,8 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             int n_views, uint32_t tile_lo, const float *__restrict__ T_final,
             const uint32_t *__restrict__ last_in, const float *__restrict__ dLdC,
             const uint2 *__restrict__ rect, const uint32_t *__restrict__ pair_base,
-            float *__restrict__ pair_grad, unsigned long long *__restrict__ counters) {
+            const uint8_t *__restrict__ pair_mask, float *__restrict__ pair_grad,
+            unsigned long long *__restrict__ counters) {
     constexpr int NT = TW * TH;
     static_assert(64 % TW == 0 && 64 % TH == 0, "a tile lies inside one 64x64-aligned block");
     constexpr int NW = NT / 64;           // waves
@@ -457,11 +462,12 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         for (int k = threadIdx.x; k < m; k += NT) {
             const uint32_t r = pair_val[rg.x + b_start + k];
             sslot[k] = slot_of(r);
-            const float4 a = splat[3 * (size_t)r], b = splat[3 * (size_t)r + 1];
-            sa[k] = block_offset(a, tx * TW, ty * TH);
-            sb[k] = b;
+            sa[k] = block_offset(splat[3 * (size_t)r], tx * TW, ty * TH);
+            sb[k] = splat[3 * (size_t)r + 1];
             sc[k] = splat[3 * (size_t)r + 2];
-            smask[k] = CULL ? support_wave_mask<TW, TH>(a, b, tx * TW, ty * TH) : 1u;
+            // the forward's support test of this pair (the forward staged
+            // every entry before the tile's largest last contributor)
+            smask[k] = CULL ? (uint32_t)pair_mask[rg.x + b_start + k] : 1u;
         }
         __syncthreads();
         const int wm = (int)min((uint32_t)m, wlast > b_start ? wlast - b_start : 0u);
@@ -694,7 +700,8 @@ void fwd_launch(hipStream_t s, const swgs_plan &p, uint8_t *ws, float *images, c
                        wsp<float4>(ws, p, WB_SPLAT), wsp<ViewDev>(ws, p, WB_VIEWS),
                        (int)p.views.size(), tile_lo, images, wsp<float>(ws, p, WB_T_FINAL),
                        wsp<uint32_t>(ws, p, WB_LAST), targets, write_dldc ? wsp<float>(ws, p, WB_DLDC) : nullptr,
-                       wsp<double>(ws, p, WB_LOSS_PART) + 2 * (size_t)tile_lo, counters, l1_weight);
+                       wsp<double>(ws, p, WB_LOSS_PART) + 2 * (size_t)tile_lo, counters, l1_weight,
+                       p.forward_only ? nullptr : wsp<uint8_t>(ws, p, WB_PAIR_MASK));
 }
 
 template <int TW, int TH, int BATCH>
@@ -705,7 +712,8 @@ void bwd_launch(hipStream_t s, const swgs_plan &p, uint8_t *ws, const float *dLd
                        wsp<float4>(ws, p, WB_SPLAT), wsp<ViewDev>(ws, p, WB_VIEWS),
                        (int)p.views.size(), tile_lo, wsp<float>(ws, p, WB_T_FINAL),
                        wsp<uint32_t>(ws, p, WB_LAST), dLdC, wsp<uint2>(ws, p, WB_RECT),
-                       wsp<uint32_t>(ws, p, WB_PAIR_BASE), wsp<float>(ws, p, WB_PAIR_GRAD), counters);
+                       wsp<uint32_t>(ws, p, WB_PAIR_BASE), wsp<uint8_t>(ws, p, WB_PAIR_MASK),
+                       wsp<float>(ws, p, WB_PAIR_GRAD), counters);
 }
 
 }  // namespace

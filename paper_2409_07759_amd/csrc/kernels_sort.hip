@@ -23,7 +23,7 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxDigitBits = 8;
 constexpr int kMaxBins = 1 << kMaxDigitBits;
-constexpr int kChunkRounds = 4;                   // rounds of kBlock elements per LDS chunk
+constexpr int kChunkRounds = 8;                   // rounds of kBlock elements per LDS chunk
 constexpr int kChunk = kBlock * kChunkRounds;
 
 // the scatter's count rows are cleared as 32-bit words and written as 16-bit
@@ -105,7 +105,7 @@ k_digit_scan(uint32_t *__restrict__ hist, int nblocks, uint32_t *__restrict__ to
 //   3. every element goes to run start + prefix + rank in an LDS copy of the
 //      chunk ordered by digit, which is then written out run by run, so
 //      consecutive threads write consecutive addresses of one digit's run.
-__global__ void __launch_bounds__(kBlock, 8)   // 8 blocks per CU: the whole grid resident at once
+__global__ void __launch_bounds__(kBlock, 4)   // 4 blocks per CU: the whole grid resident at once
 k_scatter(const uint32_t *__restrict__ keys, const uint32_t *__restrict__ vals, const uint32_t *d_n,
           uint32_t n_fixed, uint32_t cap, int shift, int dbits, const uint32_t *__restrict__ hist,
           const uint32_t *__restrict__ totals, uint32_t *__restrict__ keys_out,

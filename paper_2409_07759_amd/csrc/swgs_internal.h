@@ -17,7 +17,7 @@ namespace swgs {
 constexpr int kMaxShDegree = 3;
 constexpr int kMaxRows = 11 + 3 * 16;      // F at SH degree 3
 constexpr int kGateChunk = 2048;           // slots per gating block
-constexpr int kSortBlocks = 2048;          // fixed grid of the radix-sort passes
+constexpr int kSortBlocks = 1024;          // fixed grid of the radix-sort passes
 constexpr int kSplatFloats = 12;           // floats per splat record
 constexpr int kXcds = 8;                   // accelerator complex dies (one L2 each)
 
@@ -85,7 +85,7 @@ enum WsBuf {
     WB_PAIR_OFFSET, WB_SORT_HIST, WB_SORT_TOTAL, WB_LAST, WB_LOSS_PART, WB_STATS, WB_STEP,
     WB_VIEWS, WB_GROUPS, WB_GROUP_VIEWS,
     WB_RELOC_W, WB_RELOC_FLAG, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_CNT, WB_RELOC_SCAN, WB_REG_PART, WB_COUNTERS, WB_CFLAGS,
-    WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE, WB_PAIR_BASE, WB_PAIR_GRAD, WB_RECT_SORTED,
+    WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE, WB_PAIR_BASE, WB_PAIR_GRAD, WB_RECT_SORTED, WB_PAIR_MASK,
     WB_COUNT
 };
 
