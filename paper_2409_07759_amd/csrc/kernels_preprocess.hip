@@ -50,6 +50,10 @@ __device__ __forceinline__ int clip_tile(double f, int n) {
     return f < 0.0 ? 0 : (f > (double)n ? n : (int)f);
 }
 
+// HOIST_SH: load the slot's SH rows into registers once, before the camera
+// loop (frames seen by several cameras); else per camera, after the
+// basis (one camera per frame: fewer registers, higher occupancy).
+template <bool HOIST_SH>
 __global__ void __launch_bounds__(kBlock)
 k_preprocess(const float *__restrict__ params, int n_slots, int deg, const GroupDev *__restrict__ groups,
              const int32_t *__restrict__ group_views, const ViewDev *__restrict__ views,
@@ -89,9 +93,11 @@ k_preprocess(const float *__restrict__ params, int n_slots, int deg, const Group
     const int nk = (deg + 1) * (deg + 1);
     // the slot's SH coefficients, loaded once for all cameras (their loads
     // overlap the covariance arithmetic)
-    float sh[48];
+    float sh[HOIST_SH ? 48 : 1];
+    if constexpr (HOIST_SH) {
 #pragma unroll
-    for (int q = 0; q < 48; ++q) sh[q] = q < 3 * nk ? params[(11 + q) * S + slot] : 0.0f;
+        for (int q = 0; q < 48; ++q) sh[q] = q < 3 * nk ? params[(11 + q) * S + slot] : 0.0f;
+    }
 
     for (int k = 0; k < G.n_views; ++k) {
         const int vi = group_views[G.view_first + k];
@@ -173,9 +179,13 @@ k_preprocess(const float *__restrict__ params, int n_slots, int deg, const Group
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             double acc = 0.0;
+            if constexpr (HOIST_SH) {
 #pragma unroll
-            for (int kk = 0; kk < 16; ++kk)
-                if (kk < nk) acc += Y[kk] * (double)sh[3 * kk + ch];
+                for (int kk = 0; kk < 16; ++kk)
+                    if (kk < nk) acc += Y[kk] * (double)sh[3 * kk + ch];
+            } else {
+                for (int kk = 0; kk < nk; ++kk) acc += Y[kk] * (double)params[(11 + 3 * kk + ch) * S + slot];
+            }
             acc += 0.5;
             col[ch] = acc > 0.0 ? acc : 0.0;
             flags |= acc > 0.0 ? 0u : (1u << ch);
@@ -318,7 +328,11 @@ void launch_preprocess(hipStream_t s, const swgs_plan &p, uint8_t *ws, int view_
     (void)view_hi;
     if (maxn == 0) return;
     dim3 grid((maxn + kBlock - 1) / kBlock, g_n);
-    hipLaunchKernelGGL(k_preprocess, grid, dim3(kBlock), 0, s, p.pool.params, p.pool.n_slots, p.sh_degree,
+    // frames seen by two or more cameras on average: SH rows hoisted
+    size_t nv = 0;
+    for (int g = g_lo; g < g_lo + g_n; ++g) nv += (size_t)p.groups[g].n_views;
+    const bool hoist = only < 0 && nv >= 2 * (size_t)g_n;
+    hipLaunchKernelGGL(hoist ? k_preprocess<true> : k_preprocess<false>, grid, dim3(kBlock), 0, s, p.pool.params, p.pool.n_slots, p.sh_degree,
                        wsp<GroupDev>(ws, p, WB_GROUPS) , wsp<int32_t>(ws, p, WB_GROUP_VIEWS),
                        wsp<ViewDev>(ws, p, WB_VIEWS), wsp<uint32_t>(ws, p, WB_ACTIVE_LIST), g_lo, only,
                        p.tile_w, p.tile_h, wsp<float4>(ws, p, WB_SPLAT), wsp<uint32_t>(ws, p, WB_DEPTH_KEY),
