@@ -94,7 +94,7 @@ typedef struct {
  * it (culling, tile ranges, depth keys) are taken in FP64. */
 typedef struct {
     int32_t frame;             /* frame index for the lifespan gate */
-    int32_t width, height;     /* pixels, >= 1 */
+    int32_t width, height;     /* pixels, 1..131072 each, width * height < 2^31 */
     int32_t reserved;
     double R[9];
     double t[3];
