@@ -410,7 +410,7 @@ swgs_status progress_once(swgs_server *s) {
 
 bool view_ok(const swgs_server *s, const swgs_view &w) {
     return w.frame >= 0 && w.frame < s->o.n_frames && w.width > 0 && w.height > 0 && w.width <= 16384 * 8 &&
-           w.height <= 16384 * 8 && w.fx > 0 && w.fy > 0;
+           w.height <= 16384 * 8 && (int64_t)w.width * w.height <= (int64_t)INT32_MAX && w.fx > 0 && w.fy > 0;
 }
 
 void enqueue(swgs_server *s, swgs_request *r) {
