@@ -140,7 +140,7 @@ void swgs::compute_layout(const LayoutDims &d, Layout &lay, size_t &consts_bytes
                                                       // order (+16: the reduce reads whole 16-byte vectors)
     if (d.forward_only) {
         // serving: no gating (the live lists are resident), no gradients,
-        // no loss, no step; pair buffers may live outside (ext)
+        // no loss, no step
         for (int b : {WB_ACTIVE_LIST, WB_GATE_BLK, WB_POS_OF, WB_DLDC, WB_REC_GRAD, WB_LOSS_PART, WB_RELOC_W,
                       WB_RELOC_FLAG, WB_RELOC_CNT, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_SCAN, WB_REG_PART,
                       WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE, WB_PAIR_BASE, WB_PAIR_GRAD, WB_PAIR_MASK})
