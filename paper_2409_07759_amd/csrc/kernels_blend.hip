@@ -370,7 +370,7 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
 // opacity, conic 3, offset x), 8-11 the row sums of the offset-y term.
 constexpr int kTerm = 12;                 // 9 terms padded to 3 x float4
 
-template <int TW, int TH, int BATCH>
+template <int TW, int TH, int BATCH, bool COUNT>
 __global__ void __launch_bounds__(TW *TH)
 k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_val,
             const float4 *__restrict__ splat, const ViewDev *__restrict__ views,
@@ -423,14 +423,14 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     if (threadIdx.x == 0) cnt_evals = 0;
     if ((threadIdx.x & 63) == 0) swlast[threadIdx.x >> 6] = wlast;
     __syncthreads();
-    if (counters) {
+    if (COUNT) {   // counted build only (timing flag SWGS_TIMING_COUNT)
         atomicAdd(&cnt_evals, (unsigned long long)lst);
         __syncthreads();
     }
     uint32_t nmax = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) nmax = max(nmax, swlast[w]);
-    if (counters && threadIdx.x == 0) atomicAdd(counters + 4 * (blockIdx.x % kCounterSlots) + 1, cnt_evals);
+    if (COUNT && threadIdx.x == 0) atomicAdd(counters + 4 * (blockIdx.x % kCounterSlots) + 1, cnt_evals);
     // A pair's slot: the record's first emission slot plus this tile's
     // row-major index inside the record's tile rect.
     auto slot_of = [&](uint32_t r) {
@@ -707,7 +707,8 @@ void fwd_launch(hipStream_t s, const swgs_plan &p, uint8_t *ws, float *images, c
 template <int TW, int TH, int BATCH>
 void bwd_launch(hipStream_t s, const swgs_plan &p, uint8_t *ws, const float *dLdC, uint32_t tile_lo,
                 uint32_t tile_hi, unsigned long long *counters) {
-    hipLaunchKernelGGL((k_blend_bwd<TW, TH, BATCH>), dim3(tile_hi - tile_lo), dim3(TW * TH), 0, s,
+    auto kern = counters ? k_blend_bwd<TW, TH, BATCH, true> : k_blend_bwd<TW, TH, BATCH, false>;
+    hipLaunchKernelGGL(kern, dim3(tile_hi - tile_lo), dim3(TW * TH), 0, s,
                        wsp<uint2>(ws, p, WB_TILE_RANGE), wsp<uint32_t>(ws, p, WB_PAIR_VAL),
                        wsp<float4>(ws, p, WB_SPLAT), wsp<ViewDev>(ws, p, WB_VIEWS),
                        (int)p.views.size(), tile_lo, wsp<float>(ws, p, WB_T_FINAL),
