@@ -653,6 +653,14 @@ def test_invalid_arguments_are_rejected(sw, ctx):
     with pytest.raises(sw.SwgsError) as e:
         pl.set_timing(4)
     assert e.value.status == sw.SWGS_ERR_INVALID_ARG
+    # a view of 2^31 pixels or more (in-view pixel offsets are 32-bit) is
+    # rejected before anything is allocated
+    import copy
+    big = copy.copy(views[0])
+    big.width, big.height = 65536, 32768
+    with pytest.raises(sw.SwgsError) as e:
+        sw.Plan(ctx, dp, [big])
+    assert e.value.status == sw.SWGS_ERR_INVALID_ARG
 
 
 def test_counted_forward_matches_uncounted(sw, ctx):
@@ -682,7 +690,7 @@ def test_counted_forward_matches_uncounted(sw, ctx):
 
 
 def test_extreme_shapes_tile_invariant_and_match_oracle(sw, ctx):
-    """Needle-like, huge and sub-pixel splats: the per-wave support-box cull
+    """Needle-like, huge and sub-pixel splats: the per-wave support test
     and the tile ranges must never drop a contribution."""
     say("extreme shapes")
     rng = np.random.default_rng(21)
