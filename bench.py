@@ -1,19 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the sliding-window Gaussian-splatting hot path on one MI355X.
 
-Workload (default): the paper-scale window step -- 200k optimisable
-Gaussians plus their 200k-slot frozen store, SH degree 3, a window of 10
-frames x 4 cameras at 1352x1014, every frame with exactly 200k live slots
-(10% retire and 10% are born per frame).  One step = forward of all 40
-views with the fused L1 gradient, backward, Adam + SGLD, relocation.
+Workload of `value` (config 2): the paper-scale window step -- 200k
+optimisable Gaussians plus their 200k-slot frozen store, SH degree 3, a
+window of 10 frames x 4 cameras at 1352x1014, every frame with exactly 200k
+live slots (10% retire and 10% are born per frame), 2% of the Gaussians
+near-transparent at the start (so relocation has work from the first step).
+One step = forward of all 40 views, the image term 0.8 L1 + 0.2 D-SSIM and
+its gradient, backward, Adam + SGLD, relocation.
 
-The step runs in three launch structures on the same inputs and the same
-number of steps from the same initial state: GRAPH (chosen form: the batched
-sequence captured once in a hipGraph), BATCHED (one launch per kernel over
-all views; its timed region also yields the per-kernel HIP-event breakdown)
-and PLAIN (one launch sequence per view with a host read-back of each
-view's pair count, the per-frame baseline).  `value` is GRAPH window
-steps/s.  The PSNR of each form after the run shows they train equally.
+The step runs in three launch structures on the same inputs, from the same
+initial state with the same seeds: GRAPH (chosen form: the batched sequence
+captured once in a hipGraph), BATCHED (one launch per kernel over all views;
+its timed runs also yield the per-kernel HIP-event breakdown) and PLAIN (one
+launch sequence per view with a host read-back of each view's pair count,
+the per-frame baseline).  Each form does `--warmup` untimed steps, then
+`--reps` timed runs of `--steps` steps (device synchronised around each
+run); ms/step is the median run.  `value` is GRAPH window steps/s.  After
+`--psnr-steps` steps in total the PSNR of each form shows they train
+equally.  The other configurations -- the tiny window (1), the uneven
+180-view window (3) and the 1M-Gaussian long video (5) -- are timed the same
+way under `configs`; serving (4) under `serving`.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -30,16 +37,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
-PEAK_FP32_NONPACKED = 78.6     # TFLOP/s: 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, no packed FP32
-# Algorithmic FP32 work of the blend kernels, counted from the math (FMA = 2):
-#  every evaluated (pixel, splat) pair: offsets 4, quadratic form 7, exp 1,
-#    o*g 1, min 1, alpha test 1                                        = 15
-#  forward, per blended pair: 1-alpha 1, T(1-alpha) 1, stop test 1,
-#    w = alpha T 1, colour 3 FMA 6                                     = 10
-#  backward, per blended pair: T recovery (rcp, mul) 2, dC/dalpha 3 x 5,
-#    colour grads 4, U update 3 x 3, prod 1, dQ 2, opacity 1, conic and
-#    offset terms 5                                                    = 40
-FLOPS_EVAL, FLOPS_FWD_BLEND, FLOPS_BWD_BLEND = 15.0, 10.0, 40.0
 
 
 def log(*a):
@@ -72,6 +69,16 @@ def parse():
     ap.add_argument("--stream-frames", type=int, default=10, help="frames of the update-stream run; 0: skip it")
     ap.add_argument("--literal-iters", type=int, default=200,
                     help="timed iterations of the paper's one-view-per-iteration loop; 0: skip it")
+    ap.add_argument("--reps", type=int, default=5, help="timed runs of --steps steps per form (median reported)")
+    ap.add_argument("--psnr-steps", type=int, default=200, help="steps (in total) before the PSNR comparison")
+    ap.add_argument("--dead-fraction", type=float, default=0.02,
+                    help="fraction of the student's Gaussians made near-transparent at the start (seeded)")
+    ap.add_argument("--c1", type=int, default=1, help="time the tiny window (config 1)")
+    ap.add_argument("--c1-steps", type=int, default=100)
+    ap.add_argument("--c3", type=int, default=1, help="time the uneven 180-view window (config 3)")
+    ap.add_argument("--c3-steps", type=int, default=10)
+    ap.add_argument("--c5-advances", type=int, default=300, help="window advances of the 1M long video; 0: skip")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="threads of the oracle's all-core leg (0: the host's)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run 3 device-to-device copies of this many MiB (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -130,61 +137,11 @@ def main():
         log(f"autotuned: {tw}x{th}, lds batch {args.lds_batch}")
     else:
         tw, th = (int(x) for x in args.tile.split("x"))
+    S.add_faint_gaussians(student, args.dead_fraction, seed=5)
     cfg_base = dict(window_start=st0, relocate_period=1)
-    results = {}
-    pool_for = {}
-
-    def run_mode(mode_name):
-        mode = {"graph": swgs.SWGS_MODE_GRAPH, "batched": swgs.SWGS_MODE_BATCHED, "plain": swgs.SWGS_MODE_PLAIN}[mode_name]
-        dp = swgs.Pool.from_synth(student)
-        plan = swgs.Plan(ctx, dp, views, tile=(tw, th), lds_batch=args.lds_batch, headroom=1.5)
-        cfg = swgs.step_cfg(mode=mode, **cfg_base)
-        stats = torch.zeros(8, dtype=torch.float64, device=dev)
-        step = 0
-        counts = None
-        for w in range(args.warmup):
-            # the batched form's last warm-up step counts the blend pairs (in
-            # the forward's counting build); the timed steps run uncounted
-            count = mode_name == "batched" and w == args.warmup - 1
-            if count:
-                plan.set_timing(swgs.SWGS_TIMING_COUNT)
-            plan.window_step(cfg, targets, step + 1, step, 2, stats=stats)
-            if count:
-                counts = plan.timing()[1]
-                plan.set_timing(0)
-            step += 1
-        torch.cuda.synchronize()
-        timing = None
-        if mode_name == "batched":
-            plan.set_timing(swgs.SWGS_TIMING_EVENTS)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(args.steps):
-            plan.window_step(cfg, targets, step + 1, step, 2, stats=stats)
-            step += 1
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t
-        if mode_name == "batched":
-            timing = (plan.timing()[0], counts)
-            plan.set_timing(0)
-        st = stats.cpu().numpy()
-        if st[6] != 0:
-            raise RuntimeError(f"{mode_name}: pair capacity overflow")
-        # PSNR of the trained state over all window views
-        img = plan.forward()
-        torch.cuda.synchronize()
-        mse = torch.mean((img - targets) ** 2).item()
-        psnr = 10 * math.log10(1.0 / mse)
-        results[mode_name] = dict(ms=1e3 * el / args.steps, steps_per_s=args.steps / el, psnr=psnr,
-                                  loss=float(st[3]), pairs=int(st[4]), relocated=int(st[5]), timing=timing,
-                                  records=plan.n_records, pixels=plan.n_pixels, ws_gb=plan.ws_bytes / 1e9)
-        log(f"{mode_name}: {1e3 * el / args.steps:.2f} ms/step, {args.steps / el:.2f} steps/s, PSNR {psnr:.3f} dB, "
-            f"pairs {int(st[4])}, relocated {int(st[5])}")
-        plan.close()
-        del dp
-
-    for m in args.modes.split(","):
-        run_mode(m.strip())
+    results = run_forms(ctx, student, views, targets, (tw, th), args.lds_batch, cfg_base,
+                        [m.strip() for m in args.modes.split(",")], args.steps, args.warmup, args.reps,
+                        args.psnr_steps, breakdown=True, label="c2")
 
     chosen = "graph" if "graph" in results else list(results)[0]
     out = {
@@ -203,41 +160,32 @@ def main():
         "config": {
             "workload": f"paper-scale window step: {args.num_gs} optimisable + {args.num_gs} frozen Gaussians, "
                         f"SH degree {args.sh_degree}, W={args.swin} frames x {args.cams} cameras at "
-                        f"{args.width}x{args.height}, Adam+SGLD+relocation every step",
+                        f"{args.width}x{args.height}, image term 0.8 L1 + 0.2 D-SSIM, Adam+SGLD+relocation "
+                        f"every step, {args.dead_fraction:g} of the Gaussians near-transparent at the start",
             "views": len(views), "tile": f"{tw}x{th}", "lds_batch": args.lds_batch, "form": chosen,
+            "repetitions": args.reps, "statistic": f"median of {args.reps} timed runs of {args.steps} steps",
         },
-        "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items() if kk != "timing"}
+        "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()
+                      if kk not in ("timing", "counts", "timed_steps")}
                   for k, v in results.items()},
     }
     if "plain" in results:
         out["speedup_vs_plain"] = round(results[chosen]["steps_per_s"] / results["plain"]["steps_per_s"], 3)
         out["psnr_delta_vs_plain_db"] = round(results[chosen]["psnr"] - results["plain"]["psnr"], 4)
+        out["psnr_steps"] = results[chosen]["psnr_steps"]
     if tune_table:
         out["autotune_ms_fwd_bwd"] = {f"{t[0]}x{t[1]}/lds{l}": ms for t, l, ms in tune_table}
     if "batched" in results and results["batched"]["timing"]:
-        tm, counts = results["batched"]["timing"]
-        per_step = {k: round(v[0] / max(1, args.steps), 4) for k, v in tm.items()}
-        out["kernel_ms_per_step"] = per_step
-        dom = max(tm, key=lambda k: tm[k][0])
-        n_launch = max(1, tm[dom][1])
-        avg_s = tm[dom][0] / n_launch / 1e3
-        blend_work = {}
-        if counts is not None:
-            # pairs of one step; launches per step from the timed run
-            ev_f, ev_b, n_bl = counts
-            per = lambda k: max(1, tm[k][1]) / max(1, args.steps)
-            blend_work = {"blend_fwd": (ev_f * FLOPS_EVAL + n_bl * FLOPS_FWD_BLEND) / per("blend_fwd"),
-                          "blend_bwd": (ev_b * FLOPS_EVAL + n_bl * FLOPS_BWD_BLEND) / per("blend_bwd")}
-            out["blend_pairs_per_step"] = {"fwd_evaluated": ev_f, "bwd_evaluated": ev_b, "blended": n_bl}
-        if dom in blend_work:
-            ach = blend_work[dom] / avg_s / 1e12
-            out["roofline"] = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": PEAK_FP32_NONPACKED,
-                               "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_NONPACKED, 4),
-                               "traffic": measured_traffic(dom, tw, th, args.lds_batch),
-                               "flops_per_launch": int(blend_work[dom]), "avg_launch_ms": round(avg_s * 1e3, 4)}
-        else:
-            out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                               "frac": None, "traffic": None, "avg_launch_ms": round(avg_s * 1e3, 4)}
+        out.update(roofline_report(results["batched"], (tw, th), args.lds_batch))
+    configs = {}
+    if args.c1:
+        configs["c1"] = run_c1(args, ctx)
+    if args.c3:
+        configs["c3"] = run_c3(args, ctx)
+    if args.c5_advances > 0:
+        configs["c5"] = run_c5(args, ctx)
+    if configs:
+        out["configs"] = configs
     if args.literal_iters > 0:
         out["literal_loop"] = run_literal(args, ctx, student, views, targets, (tw, th), results)
     if args.stream_frames > 0:
@@ -252,6 +200,308 @@ def main():
         out["cpu_baseline"] = cpu_baseline(S.steady_window_pool(args.num_gs, args.swin, args.sh_degree, st0, seed=0),
                                            views, args)
     print(json.dumps(out), flush=True)
+
+
+MODES = {"graph": 2, "batched": 1, "plain": 0}
+
+
+def run_forms(ctx, synth_pool, views, targets, tile, lds, cfg_base, forms, steps, warmup, reps, psnr_steps,
+              breakdown=False, label="", headroom=1.5, inspect=False):
+    """Train `synth_pool` on `views` in each launch structure of `forms` from
+    the same initial state with the same seeds: `warmup` untimed steps, then
+    `reps` timed runs of `steps` steps each (device synchronised around each
+    run; the median run gives ms/step), then untimed steps up to `psnr_steps`
+    in total, and the PSNR of the result over all views.  Every step writes
+    its own stats row (relocated count, pairs, loss).  With `breakdown` the
+    batched form also records per-kernel-class HIP-event times over its
+    timed runs and counts the blend pairs in its last warm-up step."""
+    import numpy as np
+    import torch
+
+    from paper_2409_07759_amd import swgs
+    results = {}
+    for name in forms:
+        dp = swgs.Pool.from_synth(synth_pool)
+        plan = swgs.Plan(ctx, dp, views, tile=tile, lds_batch=lds, headroom=headroom)
+        cfg = swgs.step_cfg(mode=MODES[name], **cfg_base)
+        n_rows = max(warmup + reps * steps, psnr_steps)
+        st_all = torch.zeros((n_rows, 8), dtype=torch.float64, device="cuda")
+        step = 0
+        counts = None
+        for w in range(warmup):
+            count = breakdown and name == "batched" and w == warmup - 1
+            if count:
+                plan.set_timing(swgs.SWGS_TIMING_COUNT)
+            plan.window_step(cfg, targets, step + 1, step, 2, stats=st_all[step])
+            if count:
+                counts = plan.timing()[1]
+                plan.set_timing(0)
+            step += 1
+        torch.cuda.synchronize()
+        if breakdown and name == "batched":
+            plan.set_timing(swgs.SWGS_TIMING_EVENTS)
+        rep_ms = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(steps):
+                plan.window_step(cfg, targets, step + 1, step, 2, stats=st_all[step])
+                step += 1
+            torch.cuda.synchronize()
+            rep_ms.append(1e3 * (time.perf_counter() - t) / steps)
+        timing = None
+        if breakdown and name == "batched":
+            timing = plan.timing()[0]
+            plan.set_timing(0)
+        timed = slice(warmup, step)
+        while step < psnr_steps:
+            plan.window_step(cfg, targets, step + 1, step, 2, stats=st_all[step])
+            step += 1
+        st = st_all[:step].cpu().numpy()
+        if (st[:, 6] != 0).any():
+            raise RuntimeError(f"{label} {name}: pair capacity overflow or stale plan (flags {st[:, 6].max()})")
+        img = plan.forward()
+        torch.cuda.synchronize()
+        mse = torch.mean((img - targets) ** 2).item()
+        psnr = 10 * math.log10(1.0 / mse)
+        ms = float(np.median(rep_ms))
+        rel = st[timed, 5]
+        r = dict(ms=ms, steps_per_s=1e3 / ms, rep_ms=[round(x, 4) for x in rep_ms], psnr=psnr, psnr_steps=step,
+                 loss=float(st[-1, 3]), pairs=int(st[-1, 4]), relocated_per_step=float(rel.mean()),
+                 relocated_steps_nonzero=int((rel > 0).sum()), relocated_first_step=int(st[0, 5]),
+                 records=plan.n_records, pixels=plan.n_pixels, ws_gb=plan.ws_bytes / 1e9, timing=timing,
+                 counts=counts, timed_steps=reps * steps)
+        if inspect and not results:
+            cnt = plan.buffer(swgs.SWGS_BUF_ACTIVE_COUNT).cpu().numpy()
+            rng = plan.buffer(swgs.SWGS_BUF_TILE_RANGE).cpu().numpy().reshape(-1, 2).astype(np.int64)
+            ln = rng[:, 1] - rng[:, 0]
+            r["inspect"] = {"live_per_frame": [int(x) for x in cnt[:plan.n_groups]], "window_set": int(cnt[plan.n_groups]),
+                            "tile_list_len": {"mean": round(float(ln.mean()), 1),
+                                              "p99": int(np.percentile(ln, 99)), "max": int(ln.max())}}
+        results[name] = r
+        log(f"{label} {name}: {ms:.3f} ms/step (median of {reps} x {steps}), PSNR {psnr:.3f} dB after {step} "
+            f"steps, pairs {r['pairs']}, relocated {r['relocated_per_step']:.1f}/step")
+        plan.close()
+        del dp, plan
+        torch.cuda.empty_cache()
+    return results
+
+
+# Algorithmic work of the blend kernels per contributing (pixel, Gaussian)
+# pair -- alpha >= 1/255 before the pixel stops -- in VALU lane operations
+# (an FMA, a compare, a select, v_exp_f32, v_rcp_f32 each count one):
+#  forward: offsets 2, quadratic form 4, exp 1, o*g 1, clamp 1, skip test 1,
+#    1 - alpha 1, T (1 - alpha) 1, stop test 1, weight alpha T 1, colour 3 = 17
+#  backward: the forward's first 10 (alpha recomputed), 1 - alpha and its
+#    reciprocal 2, T recovery 1, g.c - g.W 4, dL/dalpha 1, weight 1, colour
+#    terms 3, clamp select 1, opacity term 1, dL/dQ 1, offset products 2,
+#    conic products 3, g.W update 1, T update 1, and one add per gradient
+#    term into the Gaussian's sums 9 = 41
+LANE_OPS_FWD, LANE_OPS_BWD = 17.0, 41.0
+PEAK_LANE_OPS = 256 * 64 * 2.4e9 / 1e12   # T lane-ops/s: 256 CUs x 4 SIMD x 16 lanes, one op per lane per clock
+
+
+def roofline_report(res, tile, lds):
+    """Per-kernel-class ms per step, blend pair counts, and the roofline of
+    the dominant kernel: contributing pairs x lane-ops per pair per launch
+    over its average launch time, against the FP32 vector rate."""
+    tm, counts = res["timing"], res["counts"]
+    n_steps = max(1, res["timed_steps"])
+    out = {"kernel_ms_per_step": {k: round(v[0] / n_steps, 4) for k, v in tm.items()}}
+    dom = max(tm, key=lambda k: tm[k][0])
+    avg_s = tm[dom][0] / max(1, tm[dom][1]) / 1e3
+    if counts is None:
+        return out
+    ev_f, ev_b, n_bl = counts
+    out["blend_pairs_per_step"] = {"fwd_evaluated": ev_f, "bwd_evaluated": ev_b, "contributing": n_bl}
+    work = {"blend_fwd": n_bl * LANE_OPS_FWD, "blend_bwd": n_bl * LANE_OPS_BWD}
+    per_kernel = {}
+    for k, w in work.items():
+        a = w / (tm[k][0] / max(1, tm[k][1]) / 1e3) / 1e12
+        per_kernel[k] = {"achieved": round(a, 3), "frac": round(a / PEAK_LANE_OPS, 4),
+                         "avg_launch_ms": round(tm[k][0] / max(1, tm[k][1]), 4)}
+    out["blend_roofline"] = per_kernel
+    if dom in work:
+        ach = work[dom] / avg_s / 1e12
+        ev = ev_b if dom == "blend_bwd" else ev_f
+        out["roofline"] = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": round(PEAK_LANE_OPS, 2),
+                           "unit": "T lane-ops/s", "frac": round(ach / PEAK_LANE_OPS, 4),
+                           "traffic": measured_traffic(dom, tile[0], tile[1], lds),
+                           "work_per_launch": int(work[dom]),
+                           "work": f"contributing pairs x {int(LANE_OPS_BWD if dom == 'blend_bwd' else LANE_OPS_FWD)} "
+                                   f"lane-ops (FMA = 1; peak 256 CU x 64 lanes x 2.4 GHz, packed FP32 off)",
+                           "avg_launch_ms": round(avg_s * 1e3, 4),
+                           "tiling_overhead": {"evaluated_per_contributing": round(ev / max(1, n_bl), 3),
+                                               "evaluated_pairs": int(ev)}}
+    else:
+        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                           "frac": None, "traffic": None, "avg_launch_ms": round(avg_s * 1e3, 4)}
+    return out
+
+
+def summarize_forms(res, chosen, base="plain"):
+    d = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()
+             if kk not in ("timing", "counts", "timed_steps")} for k, v in res.items()}
+    if chosen in res and base in res:
+        d["speedup_vs_plain"] = round(res[chosen]["steps_per_s"] / res[base]["steps_per_s"], 3)
+        d["psnr_delta_vs_plain_db"] = round(res[chosen]["psnr"] - res[base]["psnr"], 4)
+    return d
+
+
+def run_c1(args, ctx):
+    """The tiny plain-method window: 2,000 Gaussians, SH degree 0, W = 3
+    frames x 3 cameras at 128x96; targets rendered from a second seeded set.
+    Captured graph against one launch sequence per view."""
+    import torch
+
+    from paper_2409_07759_amd import swgs
+    from paper_2409_07759_amd import synth as S
+    n = 2000
+    birth, start, expire = S.lifespans_tiny(n, 0)
+    student = S.Pool(n, 3, 0, S.make_gaussians(n, 0, 0), birth, start, expire)
+    teacher = S.Pool(n, 3, 0, S.make_gaussians(n, 0, 1), birth, start, expire)
+    views = S.ring_views([0, 1, 2], 3, 128, 96)
+    tp = swgs.Pool.from_synth(teacher, train=False)
+    tpl = swgs.Plan(ctx, tp, views)
+    targets = tpl.forward()
+    torch.cuda.synchronize()
+    tpl.close()
+    res = run_forms(ctx, student, views, targets, (16, 16), 0, dict(window_start=0, relocate_period=1),
+                    ["graph", "plain"], args.c1_steps, 5, args.reps, 5 + args.reps * args.c1_steps, label="c1")
+    out = summarize_forms(res, "graph")
+    out["workload"] = "2000 Gaussians, SH degree 0, W=3 frames x 3 cameras at 128x96, relocation every step"
+    return out
+
+
+def run_c3(args, ctx):
+    """The uneven window: a 500k-slot pool over 30 frames (40k Gaussians live
+    in every frame, 460k start at U{0..29} and live U{1..27} frames), SH
+    degree 3, 6 cameras per frame (960x720 and 1352x1014 alternating): 180
+    views per step, tile shape and LDS batch autotuned over {8x8, 16x16,
+    32x8} x {128, 256}; captured graph against one launch sequence per view,
+    PSNR after the same 50-odd steps."""
+    import torch
+
+    from paper_2409_07759_amd import autotune, swgs
+    from paper_2409_07759_amd import synth as S
+    sizes = [(960, 720), (1352, 1014)] * 3
+    student = S.uneven_window_pool(500_000, 40_000, 30, 3, 5)
+    teacher = S.uneven_window_pool(500_000, 40_000, 30, 3, 6)
+    views = S.ring_views(list(range(30)), 6, 0, 0, sizes=sizes)
+    tp = swgs.Pool.from_synth(teacher, train=False)
+    tpl = swgs.Plan(ctx, tp, views)
+    targets = tpl.forward()
+    torch.cuda.synchronize()
+    tpl.close()
+    del tp
+    dp = swgs.Pool.from_synth(student)
+    cands = [((8, 8), 128), ((8, 8), 256), ((16, 16), 128), ((16, 16), 256), ((32, 8), 128), ((32, 8), 256)]
+    tile, lds, table = autotune.tune(ctx, dp, views, reps=1, use_cache=False, candidates=cands, log=log)
+    del dp
+    torch.cuda.empty_cache()
+    res = run_forms(ctx, student, views, targets, tile, lds, dict(window_start=0, relocate_period=1),
+                    ["graph", "plain"], args.c3_steps, 3, args.reps, 3 + args.reps * args.c3_steps, label="c3",
+                    inspect=True)
+    out = summarize_forms(res, "graph")
+    live = res["graph"].get("inspect", {}).get("live_per_frame", [])
+    out["workload"] = ("500k-slot pool, 30 frames x 6 cameras (960x720 / 1352x1014), uneven live sets, SH degree 3, "
+                       "relocation every step")
+    out["tile"], out["lds_batch"] = f"{tile[0]}x{tile[1]}", lds
+    out["autotune_ms_fwd_bwd"] = {f"{t[0]}x{t[1]}/lds{l}": ms for t, l, ms in table}
+    if live:
+        out["live_min_max"] = [min(live), max(live)]
+    return out
+
+
+def run_c5(args, ctx):
+    """The long video: a constant pool of 1M optimisable Gaussians (plus the
+    1M-slot frozen store), SH degree 3, window W = 10 x 4 cameras at
+    1352x1014.  Each advance runs one window step (I = 1), then mature(st+1)
+    emits the packed per-frame update of the slice born at st and the next
+    window's plan is made.  Device memory is sampled after every advance.
+    The batched form (one launch per kernel over the window; a graph would
+    be captured for a single replay per window) against one launch sequence
+    per view.  The teacher is static (every Gaussian live in every frame),
+    so its renders of the 4 cameras are every frame's targets, resident as
+    one W x C buffer."""
+    import numpy as np
+    import torch
+
+    from paper_2409_07759_amd import swgs
+    from paper_2409_07759_amd import synth as S
+    num_gs, swin, deg, cams, W, H, st0 = 1_000_000, 10, 3, 4, 1352, 1014, 10
+    n_adv = args.c5_advances
+    base = S.steady_window_pool(num_gs, swin, deg, st0, seed=21)
+    S.add_faint_gaussians(base, args.dead_fraction, seed=22)
+    tpar = S.make_gaussians(num_gs, deg, 23)
+    big = np.int32(1 << 30)
+    tp = swgs.Pool(tpar, np.zeros(num_gs, np.int32), np.zeros(num_gs, np.int32), np.full(num_gs, big, np.int32),
+                   0, swin, deg, "cuda", train=False)
+    cam_views = S.ring_views([st0], cams, W, H, phase_deg=10.0)
+    tpl = swgs.Plan(ctx, tp, cam_views)
+    t4 = tpl.forward()
+    torch.cuda.synchronize()
+    tpl.close()
+    del tp, tpar
+    targets = t4.repeat(swin)
+    del t4
+    res = {}
+    for name in ("batched", "plain"):
+        dp = swgs.Pool.from_synth(base)
+        cfg = swgs.step_cfg(mode=MODES[name], relocate_period=1)
+        stats = torch.zeros((n_adv, 8), dtype=torch.float64, device="cuda")
+        views0 = S.ring_views(list(range(st0, st0 + swin)), cams, W, H, phase_deg=10.0)
+        probe = swgs.Plan(ctx, dp, views0)
+        cap = int(probe.measure() * 1.5) + 65536
+        probe.close()
+        del probe
+        torch.cuda.empty_cache()
+        used, t_step, t_adv, rec_bytes = [], [], [], []
+        torch.cuda.synchronize()
+        t_all = time.perf_counter()
+        for k in range(n_adv):
+            t0 = time.perf_counter()
+            st = st0 + k
+            views = S.ring_views(list(range(st, st + swin)), cams, W, H, phase_deg=10.0)
+            plan = swgs.Plan(ctx, dp, views, pair_capacity=cap)
+            cfg.window_start = st
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            plan.window_step(cfg, targets, k + 1, k, 5, stats=stats[k])
+            torch.cuda.synchronize()
+            t_step.append(time.perf_counter() - t1)
+            if k == n_adv - 1:
+                img = plan.forward()
+                mse = torch.mean((img - targets) ** 2).item()
+            plan.close()
+            del plan
+            rec, cnt = swgs.mature(ctx, dp, st + 1)
+            rec_bytes.append(rec.numel())
+            del rec
+            torch.cuda.synchronize()
+            t_adv.append(time.perf_counter() - t0)
+            used.append(torch.cuda.mem_get_info()[1] - torch.cuda.mem_get_info()[0])
+            if k % 50 == 0:
+                log(f"c5 {name}: advance {k}, step {1e3 * t_step[-1]:.1f} ms, advance {1e3 * t_adv[-1]:.1f} ms")
+        wall = time.perf_counter() - t_all
+        s = stats.cpu().numpy()
+        if (s[:, 6] != 0).any():
+            raise RuntimeError(f"c5 {name}: pair capacity overflow or stale plan")
+        u = np.array(used[1:], np.float64)
+        res[name] = {"ms": float(np.median(t_step)) * 1e3, "steps_per_s": 1.0 / float(np.median(t_step)),
+                     "advance_ms": float(np.median(t_adv)) * 1e3, "sustained_advances_per_s": n_adv / wall,
+                     "psnr": 10 * math.log10(1.0 / mse), "psnr_steps": n_adv,
+                     "record_bytes": int(np.median(rec_bytes)), "relocated_per_step": float(s[:, 5].mean()),
+                     "device_bytes_min_max": [int(u.min()), int(u.max())],
+                     "device_bytes_spread": float((u.max() - u.min()) / u.max())}
+        log(f"c5 {name}: {res[name]}")
+        del dp
+        torch.cuda.empty_cache()
+    out = summarize_forms(res, "batched")
+    out["workload"] = (f"1M optimisable + 1M frozen Gaussians, SH degree 3, W=10 x 4 cameras at 1352x1014; "
+                       f"{n_adv} advances measured (each: plan, window step, mature/emit), a 3,000-frame run is "
+                       f"3000/{n_adv} times longer at the same per-advance cost")
+    return out
 
 
 def measured_traffic(kernel, tw, th, lds):
@@ -535,19 +785,37 @@ def run_serving(args, ctx, tile, lds):
     return res
 
 
-def cpu_baseline(student, views, args):
-    """The FP64 oracle, single-threaded, on a bounded sample of the same step:
-    one view's preprocess of every slot, forward and adjoint of `cpu_pixels`
-    random pixels, the adjoint preprocess of every visible slot; scaled to a
-    full window step (all views, all pixels) plus the numpy Adam step."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads(args):
+    if args.cpu_threads > 0:
+        return args.cpu_threads
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_c2_sample(O, student, views, pixels, seed):
+    """One view of the paper-scale window in the FP64 oracle: preprocess of
+    every slot, forward and adjoint of `pixels` random pixels (brute force
+    over every visible Gaussian in depth order), adjoint preprocess of every
+    visible optimisable slot; returns seconds per part."""
     import numpy as np
-
-    import oracle as O
-
     v = views[0]
-    rng = np.random.default_rng(0)
+    rng = np.random.default_rng(seed)
     P = v.width * v.height
-    pix = rng.choice(P, size=min(args.cpu_pixels, P), replace=False)
+    pix = rng.choice(P, size=min(pixels, P), replace=False)
     t = time.perf_counter()
     vis, rec, _ = O.preprocess(student.params, student.sh_degree, student.start, student.expire, v)
     t_pre = time.perf_counter() - t
@@ -557,28 +825,89 @@ def cpu_baseline(student, views, args):
     t = time.perf_counter()
     drec = O.blend_backward_pixels(vis, rec, v, pix, rng.uniform(-1, 1, size=(3, len(pix))))
     t_bwd = time.perf_counter() - t
-    slots = np.nonzero(vis[:student.num_gs])[0]
-    sub = slots[: min(len(slots), 20000)]
     t = time.perf_counter()
-    O.preprocess_backward(student.params, student.sh_degree, v, drec, sub)
-    t_pb = (time.perf_counter() - t) * (len(slots) / max(1, len(sub)))
+    O.preprocess_backward_visible(student.params, student.sh_degree, v, drec, vis, student.num_gs)
+    t_pb = time.perf_counter() - t
+    return dict(pre=t_pre, fwd=t_fwd, bwd=t_bwd, pb=t_pb, pixels=len(pix), P=P)
+
+
+def cpu_c1_full(O):
+    """The tiny window in full in the FP64 oracle: 9 views of 128x96 from
+    2,000 Gaussians -- render, L1 + D-SSIM loss and gradient, adjoint, the
+    adjoint preprocess, Adam + SGLD and relocation; seconds."""
+    import numpy as np
+
+    from paper_2409_07759_amd import synth as S
+    n = 2000
+    params = S.make_gaussians(n, 0, 0)
+    birth, start, expire = S.lifespans_tiny(n, 0)
+    views = S.ring_views([0, 1, 2], 3, 128, 96)
+    tgt = S.random_images(views, 1)
+    t = time.perf_counter()
+    img, _ = O.window_render(params, 0, start, expire, views)
+    A = O.window_set(start, expire, n, [0, 1, 2])
+    L, _, g, dreg = O.loss_and_grad(img, tgt, views, params, A, lam_dssim=0.2)
+    grads = dreg.copy()
+    o = 0
+    for v in views:
+        m = 3 * v.width * v.height
+        vis, rec, _ = O.preprocess(params, 0, start, expire, v)
+        drec = O.blend_backward(vis, rec, v, g[o:o + m].reshape(3, -1))
+        grads += O.preprocess_backward_visible(params, 0, v, drec, vis, n)
+        o += m
+    Z = np.zeros_like(grads)
+    P2, M2, V2 = O.adam_sgld_step(params, grads, Z, Z, A, 1, 0, seed=2, step=0)
+    O.relocate(P2, M2, V2, A, 2, 0)
+    return time.perf_counter() - t
+
+
+def cpu_baseline(student, views, args):
+    """The FP64 oracle on the host cores: the paper-scale step from a
+    bounded sample (one view's preprocess of every slot, forward and adjoint
+    of random pixels, adjoint preprocess of the visible slots; scaled to all
+    40 views x 1.37M pixels, plus the numpy Adam step), single-threaded and
+    with every host core (OpenMP over slots and pixels); and the tiny window
+    (config 1) timed in full both ways."""
+    import numpy as np
+
+    import oracle as O
+    nt = host_threads(args)
     F = student.params.shape[0]
+    rng = np.random.default_rng(0)
     g = rng.normal(size=(F, student.num_gs)) * 1e-3
     A = np.ones(student.num_gs, bool)
     t = time.perf_counter()
     O.adam_sgld_step(student.params[:, :student.num_gs], g, np.zeros_like(g), np.zeros_like(g), A, 1,
                      student.sh_degree, 0, 0, noise_lr=0.0)
     t_adam = time.perf_counter() - t
-    per_view = t_pre + (P / len(pix)) * (t_fwd + t_bwd) + t_pb
-    step_s = len(views) * per_view + t_adam
-    sample_s = t_pre + t_fwd + t_bwd + t_pb * len(sub) / max(1, len(slots)) + t_adam
-    log(f"cpu oracle: preprocess {t_pre:.2f}s, fwd {t_fwd:.2f}s + bwd {t_bwd:.2f}s for {len(pix)} px, "
-        f"adjoint preprocess {t_pb:.2f}s (extrapolated), adam {t_adam:.2f}s -> {step_s:.0f} s/step")
-    return {"value": 1.0 / step_s, "unit": "window steps/s", "cores": 1, "kind": "oracle",
+    legs = {}
+    for threads, px in ((1, args.cpu_pixels), (nt, args.cpu_pixels * max(1, nt // 2))):
+        O.set_threads(threads)
+        try:
+            smp = cpu_c2_sample(O, student, views, px, 0)
+            c1 = cpu_c1_full(O)
+        finally:
+            O.set_threads(1)
+        per_view = smp["pre"] + (smp["P"] / smp["pixels"]) * (smp["fwd"] + smp["bwd"]) + smp["pb"]
+        step_s = len(views) * per_view + t_adam
+        legs[threads] = dict(step_s=step_s, sample_s=smp["pre"] + smp["fwd"] + smp["bwd"] + smp["pb"],
+                             pixels=smp["pixels"], c1_s=c1)
+        log(f"cpu oracle, {threads} thread(s): c2 sample {legs[threads]['sample_s']:.1f}s "
+            f"({smp['pixels']} px) -> {step_s:.0f} s/step; c1 window step in full {c1:.2f}s")
+        if nt == 1:
+            break
+    best = legs[nt]
+    return {"value": 1.0 / best["step_s"], "unit": "window steps/s", "cores": nt, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"1 of {len(views)} views: preprocess of all {student.slots} slots, forward+adjoint of "
-                      f"{len(pix)} random pixels of {P}, adjoint preprocess of {len(sub)} of {len(slots)} visible "
-                      f"slots, dense Adam step; scaled to {len(views)} views x {P} pixels",
-            "sample_seconds": round(sample_s, 2)}
+                      f"{best['pixels']} random pixels of {views[0].width * views[0].height} (brute force over "
+                      f"every visible Gaussian), adjoint preprocess of the visible slots, dense numpy Adam step; "
+                      f"scaled to {len(views)} views x all pixels",
+            "sample_seconds": round(best["sample_s"] + t_adam, 2),
+            "single_thread": {"value": 1.0 / legs[1]["step_s"], "sample_seconds": round(legs[1]["sample_s"], 2),
+                              "pixels": legs[1]["pixels"]},
+            "c1_full_step_s": {"1": round(legs[1]["c1_s"], 3), str(nt): round(best["c1_s"], 3)},
+            "c1_steps_per_s": {"1": round(1.0 / legs[1]["c1_s"], 4), str(nt): round(1.0 / best["c1_s"], 4)}}
 
 
 if __name__ == "__main__":

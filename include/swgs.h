@@ -166,7 +166,8 @@ swgs_status swgs_plan_info(const swgs_plan *plan, int64_t *n_groups, int64_t *n_
  * gradient dL/dimage = sign(C - GT) / (V * 3 * H_v * W_v) into the workspace
  * (SWGS_BUF_DLDC), and, when `stats` (device double[8]) is not NULL, writes
  * stats[0] = sum_v mean|C - GT| / V, stats[1] = mean (C - GT)^2 over all
- * pixels and channels, stats[4] = pairs, stats[6] = overflow flag. */
+ * pixels and channels, stats[4] = pairs, stats[6] = flags as for
+ * swgs_window_step (1: pair overflow, 2: stale plan). */
 swgs_status swgs_render_forward(swgs_context *ctx, swgs_plan *plan, void *workspace,
                                 size_t ws_bytes, float *images, const float *targets,
                                 double *stats);
@@ -231,13 +232,17 @@ swgs_status swgs_relocate(swgs_context *ctx, swgs_plan *plan, void *workspace, s
  * step % relocate_period == 0.  cfg->mode selects the launch structure:
  * PLAIN = one launch sequence per view (the per-frame baseline), BATCHED =
  * one launch per kernel over all views, GRAPH = the batched sequence
- * captured once into a hipGraph and replayed (step numbers advance on the
- * device; the first call with a plan captures).  `images` may be NULL (the
+ * captured once into a hipGraph and replayed (the first call with a plan,
+ * or with a different workspace, targets, images or cfg, captures; adam_t,
+ * step and seed are taken from every call's arguments).  `images` may be NULL (the
  * renders then stay in the workspace).
  * stats (device double[8]): [0] image term
  * (1/V) sum_v [(1 - l) mean|C - GT| + l (1 - SSIM_v)], [1] MSE, [2] regulariser,
- * [3] total loss, [4] pairs, [5] dead slots relocated, [6] overflow flag,
- * [7] |A|. */
+ * [3] total loss, [4] pairs, [5] dead slots relocated, [6] flags: bit 0
+ * (value 1) the pair capacity overflowed, bit 1 (value 2) a frame's live
+ * count differs from the count at plan creation (the lifespans changed, e.g.
+ * by mature() or apply_update(): the plan's lists are stale and the step's
+ * results are not valid; make a new plan), [7] |A|. */
 swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *plan, void *workspace, size_t ws_bytes,
                              const swgs_step_cfg *cfg, const float *targets, float *images,
                              int64_t adam_t, uint64_t step, uint64_t seed, double *stats);

@@ -29,7 +29,7 @@ _lib = None
 def build(force: bool = False) -> str:
     """Compile swgs_oracle.c with gcc into oracle/liborc.so."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"])
     return _LIB
 
 
@@ -52,6 +52,10 @@ def lib():
         L.orc_reloc_SN.restype = ctypes.c_double
         L.orc_relocate.argtypes = [i64, i64, i32, P, P, P, P, u64, u64, i32, P, P, P]
         L.orc_relocate.restype = i64
+        L.orc_set_threads.argtypes = [i32]
+        L.orc_get_threads.restype = i32
+        L.orc_preprocess_backward_many.argtypes = [P, i64, i32, P, i32, i32, P, i64, P, P]
+        L.orc_set_threads(1)
         _lib = L
     return _lib
 
@@ -193,6 +197,22 @@ def preprocess_backward(params, sh_degree, view, drec, slots):
     for i in slots:
         lib().orc_preprocess_backward_one(_p(P), S, int(i), int(sh_degree), _p(cam),
                                           view.width, view.height, _p(np.ascontiguousarray(dr[i])), _p(out))
+    return out
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's per-slot and per-pixel loops (1 by default;
+    the CPU-baseline timing uses all host cores)."""
+    lib().orc_set_threads(int(n))
+
+
+def preprocess_backward_visible(params, sh_degree, view, drec, visible, n_opt):
+    """preprocess_backward over every visible slot below n_opt, in C."""
+    P = _f64(params)
+    S = P.shape[1]
+    out = np.zeros_like(P)
+    lib().orc_preprocess_backward_many(_p(P), S, int(sh_degree), _p(_f64(view.cam16())), view.width, view.height,
+                                       _p(_i32(visible)), int(min(n_opt, S)), _p(_f64(drec)), _p(out))
     return out
 
 

@@ -20,9 +20,20 @@
  * closed forms, brute force, finite differences or library routines.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads for the per-slot and per-pixel loops (OpenMP).  The library
+ * starts single-threaded; the CPU-baseline timing raises it.  Loops over
+ * slots and pixels write disjoint outputs, so the thread count changes no
+ * result, except the order in which the adjoint sums pixel contributions
+ * into a slot's record gradient (with more than one thread: per-thread
+ * partial sums, added in thread order). */
+static int g_threads = 1;
+void orc_set_threads(int n) { g_threads = n > 0 ? n : 1; }
+int orc_get_threads(void) { return g_threads; }
 
 /* Per-slot record of one view, as doubles. */
 enum {
@@ -309,6 +320,7 @@ void orc_preprocess(const double *params, int64_t S, int deg,
                     const double cam[16], int W, int H, int tw, int th,
                     int32_t *visible, double *rec, int32_t *rect)
 {
+#pragma omp parallel for schedule(dynamic, 256) num_threads(g_threads)
     for (int64_t i = 0; i < S; ++i) {
         if (!orc_active(start[i], expire[i], frame)) {
             visible[i] = 0;
@@ -394,6 +406,7 @@ void orc_render(int64_t S, const int32_t *visible, const double *rec,
     int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(S > 0 ? S : 1));
     int64_t n = orc_depth_order(S, visible, rec, order);
     int64_t np = pix ? npix : (int64_t)W * H;
+#pragma omp parallel for schedule(dynamic, 64) num_threads(g_threads)
     for (int64_t j = 0; j < np; ++j) {
         int64_t id = pix ? pix[j] : j;
         double px = (double)(id % W) + 0.5, py = (double)(id / W) + 0.5;
@@ -425,66 +438,94 @@ void orc_blend_backward(int64_t S, const int32_t *visible, const double *rec,
     orc_blend_backward_pixels(S, visible, rec, W, H, bg, dLdC, -1, NULL, drec);
 }
 
+/* Adjoint of one pixel: the forward walk stores its contributors (who, al,
+ * Tk: scratch of n entries), the backward walk accumulates into drec. */
+static void adjoint_pixel(int64_t n, const int64_t *order, const double *rec, double px, double py,
+                          const double bg[3], const double g[3], int64_t *who, double *al, double *Tk,
+                          double *drec)
+{
+    /* forward walk, storing contributors */
+    double T = 1.0;
+    int64_t m = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        const double *r = rec + order[k] * REC;
+        double dx = px - r[R_U], dy = py - r[R_V];
+        double Q = r[R_A] * dx * dx + 2.0 * r[R_B] * dx * dy + r[R_C] * dy * dy;
+        double og = r[R_OPA] * exp(-0.5 * Q);
+        double alpha = og < 0.99 ? og : 0.99;
+        if (alpha < 1.0 / 255.0) continue;
+        double Tn = T * (1.0 - alpha);
+        if (Tn < 1e-4) break;
+        who[m] = order[k]; al[m] = alpha; Tk[m] = T; ++m;
+        T = Tn;
+    }
+    /* backward walk */
+    double U[3] = {0, 0, 0}, Rr = 1.0;
+    for (int64_t j = m - 1; j >= 0; --j) {
+        int64_t i = who[j];
+        const double *r = rec + i * REC;
+        double a = al[j], Tj = Tk[j];
+        double dalpha = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            dalpha += g[c] * Tj * (r[R_RED + c] - U[c] - Rr * bg[c]);
+            drec[i * 9 + 6 + c] += g[c] * a * Tj;
+        }
+        for (int c = 0; c < 3; ++c) U[c] = r[R_RED + c] * a + (1.0 - a) * U[c];
+        Rr *= (1.0 - a);
+        double dx = px - r[R_U], dy = py - r[R_V];
+        double Q = r[R_A] * dx * dx + 2.0 * r[R_B] * dx * dy + r[R_C] * dy * dy;
+        double G = exp(-0.5 * Q);
+        if (r[R_OPA] * G >= 0.99) continue;   /* clamped: alpha is constant */
+        /* alpha = o G, G = exp(-Q/2) */
+        drec[i * 9 + 5] += dalpha * G;
+        double dQ = -0.5 * r[R_OPA] * G * dalpha;
+        drec[i * 9 + 2] += dQ * dx * dx;
+        drec[i * 9 + 3] += dQ * 2.0 * dx * dy;
+        drec[i * 9 + 4] += dQ * dy * dy;
+        /* dQ/ddx = 2(A dx + B dy); ddx/du = -1 */
+        drec[i * 9 + 0] += -dQ * 2.0 * (r[R_A] * dx + r[R_B] * dy);
+        drec[i * 9 + 1] += -dQ * 2.0 * (r[R_B] * dx + r[R_C] * dy);
+    }
+}
+
 /* Same over a list of pixels (pix[j] = y*W + x, dLdC[3][npix]) or, when pix
- * is NULL, over the whole image (dLdC[3][W*H]). */
+ * is NULL, over the whole image (dLdC[3][W*H]).  Pixels are summed in
+ * ascending order into drec (one thread), or into per-thread partials that
+ * are then added in thread order. */
 void orc_blend_backward_pixels(int64_t S, const int32_t *visible, const double *rec,
                                int W, int H, const double bg[3], const double *dLdC,
                                int64_t npix, const int64_t *pix, double *drec)
 {
     int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(S > 0 ? S : 1));
     int64_t n = orc_depth_order(S, visible, rec, order);
-    int64_t *who = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
-    double *al = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    double *Tk = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    const size_t nn = (size_t)(n > 0 ? n : 1);
     int64_t P = pix ? npix : (int64_t)W * H;
-    for (int64_t j = 0; j < P; ++j) {
-        int64_t pid = pix ? pix[j] : j;
-        double px = (double)(pid % W) + 0.5, py = (double)(pid / W) + 0.5;
-        double g[3] = {dLdC[j], dLdC[P + j], dLdC[2 * P + j]};
-        /* forward walk, storing contributors */
-        double T = 1.0;
-        int64_t m = 0;
-        for (int64_t k = 0; k < n; ++k) {
-            const double *r = rec + order[k] * REC;
-            double dx = px - r[R_U], dy = py - r[R_V];
-            double Q = r[R_A] * dx * dx + 2.0 * r[R_B] * dx * dy + r[R_C] * dy * dy;
-            double og = r[R_OPA] * exp(-0.5 * Q);
-            double alpha = og < 0.99 ? og : 0.99;
-            if (alpha < 1.0 / 255.0) continue;
-            double Tn = T * (1.0 - alpha);
-            if (Tn < 1e-4) break;
-            who[m] = order[k]; al[m] = alpha; Tk[m] = T; ++m;
-            T = Tn;
+    const int nt = g_threads;
+    double *part = nt > 1 ? (double *)calloc((size_t)nt * (size_t)S * 9, sizeof(double)) : NULL;
+#pragma omp parallel num_threads(nt)
+    {
+        const int tid = omp_get_thread_num();
+        int64_t *who = (int64_t *)malloc(sizeof(int64_t) * nn);
+        double *al = (double *)malloc(sizeof(double) * nn);
+        double *Tk = (double *)malloc(sizeof(double) * nn);
+        double *acc = part ? part + (size_t)tid * (size_t)S * 9 : drec;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t j = 0; j < P; ++j) {
+            int64_t pid = pix ? pix[j] : j;
+            double px = (double)(pid % W) + 0.5, py = (double)(pid / W) + 0.5;
+            double g[3] = {dLdC[j], dLdC[P + j], dLdC[2 * P + j]};
+            adjoint_pixel(n, order, rec, px, py, bg, g, who, al, Tk, acc);
         }
-        /* backward walk */
-        double U[3] = {0, 0, 0}, Rr = 1.0;
-        for (int64_t j = m - 1; j >= 0; --j) {
-            int64_t i = who[j];
-            const double *r = rec + i * REC;
-            double a = al[j], Tj = Tk[j];
-            double dalpha = 0.0;
-            for (int c = 0; c < 3; ++c) {
-                dalpha += g[c] * Tj * (r[R_RED + c] - U[c] - Rr * bg[c]);
-                drec[i * 9 + 6 + c] += g[c] * a * Tj;
-            }
-            for (int c = 0; c < 3; ++c) U[c] = r[R_RED + c] * a + (1.0 - a) * U[c];
-            Rr *= (1.0 - a);
-            double dx = px - r[R_U], dy = py - r[R_V];
-            double Q = r[R_A] * dx * dx + 2.0 * r[R_B] * dx * dy + r[R_C] * dy * dy;
-            double G = exp(-0.5 * Q);
-            if (r[R_OPA] * G >= 0.99) continue;   /* clamped: alpha is constant */
-            /* alpha = o G, G = exp(-Q/2) */
-            drec[i * 9 + 5] += dalpha * G;
-            double dQ = -0.5 * r[R_OPA] * G * dalpha;
-            drec[i * 9 + 2] += dQ * dx * dx;
-            drec[i * 9 + 3] += dQ * 2.0 * dx * dy;
-            drec[i * 9 + 4] += dQ * dy * dy;
-            /* dQ/ddx = 2(A dx + B dy); ddx/du = -1 */
-            drec[i * 9 + 0] += -dQ * 2.0 * (r[R_A] * dx + r[R_B] * dy);
-            drec[i * 9 + 1] += -dQ * 2.0 * (r[R_B] * dx + r[R_C] * dy);
-        }
+        free(who); free(al); free(Tk);
     }
-    free(order); free(who); free(al); free(Tk);
+    if (part) {
+        for (int t = 0; t < nt; ++t) {
+            const double *pt = part + (size_t)t * (size_t)S * 9;
+            for (size_t k = 0; k < (size_t)S * 9; ++k) drec[k] += pt[k];
+        }
+        free(part);
+    }
+    free(order);
 }
 
 /* ------------------------------------------------------------------------
@@ -641,6 +682,16 @@ void orc_preprocess_backward_one(const double *params, int64_t S, int64_t i, int
     for (int k = 0; k < 4; ++k) dparams[(6 + k) * S + i] += (dq[k] - q[k] * qd) / qn;
 }
 
+/* The adjoint preprocess of every visible slot i < n (each writes its own
+ * parameter column). */
+void orc_preprocess_backward_many(const double *params, int64_t S, int deg, const double cam[16], int W, int H,
+                                  const int32_t *visible, int64_t n, const double *drec, double *dparams)
+{
+#pragma omp parallel for schedule(dynamic, 256) num_threads(g_threads)
+    for (int64_t i = 0; i < n; ++i)
+        if (visible[i]) orc_preprocess_backward_one(params, S, i, deg, cam, W, H, drec + 9 * i, dparams);
+}
+
 /* Whole-view adjoint: dparams += d/dparams of sum(dLdC * image), for the
  * slots visible in this view that are not frozen (slot < n_opt). */
 void orc_view_backward(const double *params, int64_t S, int deg,
@@ -655,8 +706,7 @@ void orc_view_backward(const double *params, int64_t S, int deg,
     if (!drec_out) memset(drec, 0, sizeof(double) * (size_t)S * 9);
     orc_preprocess(params, S, deg, start, expire, frame, cam, W, H, 16, 16, vis, rec, rect);
     orc_blend_backward(S, vis, rec, W, H, bg, dLdC, drec);
-    for (int64_t i = 0; i < S && i < n_opt; ++i)
-        if (vis[i]) orc_preprocess_backward_one(params, S, i, deg, cam, W, H, drec + 9 * i, dparams);
+    orc_preprocess_backward_many(params, S, deg, cam, W, H, vis, n_opt < S ? n_opt : S, drec, dparams);
     free(vis); free(rec); free(rect);
     if (!drec_out) free(drec);
 }

@@ -21,8 +21,6 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    # hardware float atomics on coarse-grained device memory
-    "-munsafe-fp-atomics",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
 

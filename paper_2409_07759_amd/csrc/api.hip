@@ -728,14 +728,12 @@ swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *p, void *workspace, s
         if (!same) {
             if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
             if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
-            launch_set_step(s, reinterpret_cast<uint8_t *>(wsp<StepDev>(ws, *p, WB_STEP)), adam_t, step, seed);
             const bool was_timing = p->timing, was_counting = p->counting;
             p->timing = p->counting = false;   // no event records or counters inside a graph
             hipError_t ce = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
             if (ce != hipSuccess) { p->timing = was_timing; p->counting = was_counting; return fail(ctx, SWGS_ERR_HIP, std::string("begin capture: ") + hipGetErrorString(ce)); }
             launch_fill_f64(s, sdev, 0.0, 8);
             seq_window_batched(s, *p, ws, *cfg, targets, images);
-            launch_advance_step(s, reinterpret_cast<uint8_t *>(wsp<StepDev>(ws, *p, WB_STEP)));
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(s, &g);
             p->timing = was_timing;
@@ -748,6 +746,10 @@ swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *p, void *workspace, s
             p->graph_images = images;
             p->graph_cfg = *cfg;
         }
+        // the graph reads Adam's t, the step and the seed from the device:
+        // set them from this call's arguments outside the graph, so every
+        // replay takes exactly the numbers it is given
+        launch_set_step(s, reinterpret_cast<uint8_t *>(wsp<StepDev>(ws, *p, WB_STEP)), adam_t, step, seed);
         HIP_TRY(ctx, hipGraphLaunch(p->graph_exec, s));
     } else if (cfg->mode == SWGS_MODE_BATCHED) {
         launch_set_step(s, reinterpret_cast<uint8_t *>(wsp<StepDev>(ws, *p, WB_STEP)), adam_t, step, seed);

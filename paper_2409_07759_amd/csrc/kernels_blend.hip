@@ -14,15 +14,20 @@
 // shape lies inside one such block, so the rounding, and with it every
 // image bit, does not depend on the tile shape.
 //
+// The forward also stores, per pair, a byte of per-wave support bits (which
+// 8x8 pixel blocks of the tile the splat can reach with alpha >= 1/255).
 // The backward walks the same list back to front from each pixel's last
-// contributor, recovering the transmittance in front of each splat by
-// T <- T / (1 - alpha) (nothing per pair is stored), and keeping W, the
-// colour behind the splat including the background seen through it
-// (W <- c alpha + (1 - alpha) W from W = bg), so that
+// contributor, reading those bits instead of repeating the test and
+// recovering the transmittance in front of each splat by
+// T <- T / (1 - alpha) (only the final transmittance is stored per pixel),
+// and keeping W, the colour behind the splat including the background seen
+// through it (W <- c alpha + (1 - alpha) W from W = bg), so that
 //     dC/dalpha_k = T_k (c_k - W_k).
-// Per-splat gradient terms are summed over each 16-lane row with DPP
-// exchanges, the row sums of all waves are combined per batch through LDS,
-// and flushed with one global float atomic per term per (tile, splat).
+// Per-splat gradient terms are summed over each wave with lane swaps and
+// DPP steps, the wave partials are combined per batch through LDS in wave
+// order, and each pair's nine terms are stored as one row at the pair's
+// emission slot; an ordered per-record reduce then sums a record's rows in
+// slot order.  No float atomics: gradients are bit-reproducible.
 #include "swgs_internal.h"
 
 namespace swgs {
@@ -406,16 +411,19 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     float T = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
     uint32_t lst = 0;
     if (inside) {
-        // per-view bases (64-bit, wave-uniform), in-view offsets in 32 bits
-        // (a view holds fewer than 2^31 pixels)
-        const uint32_t HW = (uint32_t)V.width * (uint32_t)V.height;
+        // per-view and per-channel bases (64-bit, wave-uniform), in-view
+        // offsets in 32 bits (a view holds fewer than 2^31 pixels; the
+        // channel planes are reached through their own bases, so 3 HW may
+        // exceed 2^32)
+        const size_t HW = (size_t)V.width * (size_t)V.height;
         const uint32_t o = (uint32_t)y * (uint32_t)V.width + (uint32_t)x;
-        const float *dl = dLdC + 3 * V.pix_base;
+        const float *dl0 = dLdC + 3 * V.pix_base;
+        const float *dl1 = dl0 + HW, *dl2 = dl1 + HW;
         T = (T_final + V.pix_base)[o];
         lst = (last_in + V.pix_base)[o];
-        g0 = dl[o];
-        g1 = dl[o + HW];
-        g2 = dl[o + 2 * HW];
+        g0 = dl0[o];
+        g1 = dl1[o];
+        g2 = dl2[o];
     }
     // a wave never needs splats at or beyond its pixels' largest `last`;
     // the tile's largest is the largest of its waves'

@@ -35,10 +35,11 @@ __device__ __forceinline__ bool gate_pred(const int32_t *__restrict__ start,
 __global__ void __launch_bounds__(kBlock)
 k_gate_count(const int32_t *__restrict__ start, const int32_t *__restrict__ expire,
              const GroupDev *__restrict__ groups, int n_groups, int num_gs, int n_slots,
-             int nblk, uint32_t *__restrict__ blk_count) {
+             int nblk, uint32_t *__restrict__ blk_count, uint32_t *__restrict__ stale) {
     const int g = blockIdx.y;
     const int base = blockIdx.x * kGateChunk;
     __shared__ uint32_t wsum[kWaves];
+    if (stale && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *stale = 0u;   // set by k_gate_scan
     uint32_t c = 0;
     for (int k = 0; k < kPerThread; ++k) {
         int slot = base + k * kBlock + threadIdx.x;
@@ -57,7 +58,8 @@ k_gate_count(const int32_t *__restrict__ start, const int32_t *__restrict__ expi
 
 // one block per group: exclusive scan of the chunk counts in place
 __global__ void __launch_bounds__(kBlock)
-k_gate_scan(uint32_t *__restrict__ blk_count, int nblk, uint32_t *__restrict__ totals) {
+k_gate_scan(uint32_t *__restrict__ blk_count, int nblk, uint32_t *__restrict__ totals,
+            const GroupDev *__restrict__ groups, int n_groups, uint32_t nA_cap, uint32_t *__restrict__ stale) {
     const int g = blockIdx.x;
     uint32_t *c = blk_count + (size_t)g * nblk;
     __shared__ uint32_t wsum[kWaves];
@@ -83,7 +85,12 @@ k_gate_scan(uint32_t *__restrict__ blk_count, int nblk, uint32_t *__restrict__ t
         if (threadIdx.x == kBlock - 1) carry = before + x;
         __syncthreads();
     }
-    if (threadIdx.x == 0) totals[g] = carry;
+    if (threadIdx.x == 0) {
+        totals[g] = carry;
+        // a live count that differs from the plan's means the lifespans
+        // changed after the plan was made: its lists are stale
+        if (stale && carry != (g < n_groups ? groups[g].n_live : nA_cap)) atomicOr(stale, 1u);
+    }
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -158,10 +165,12 @@ void launch_gate(hipStream_t s, const swgs_plan &p, uint8_t *ws) {
     auto *blk = wsp<uint32_t>(ws, p, WB_GATE_BLK);
     auto *groups = wsp<GroupDev>(ws, p, WB_GROUPS);
     dim3 grid(nblk, G + 1);
+    // word 3 of the pair-count block: set when a live count differs from the plan's
+    uint32_t *stale = wsp<uint32_t>(ws, p, WB_PAIR_COUNT) + 3;
     hipLaunchKernelGGL(k_gate_count, grid, dim3(kBlock), 0, s, p.pool.start, p.pool.expire, groups, G,
-                       p.pool.num_gs, S, nblk, blk);
+                       p.pool.num_gs, S, nblk, blk, stale);
     hipLaunchKernelGGL(k_gate_scan, dim3(G + 1), dim3(kBlock), 0, s, blk, nblk,
-                       wsp<uint32_t>(ws, p, WB_ACTIVE_COUNT));
+                       wsp<uint32_t>(ws, p, WB_ACTIVE_COUNT), groups, G, p.n_A, stale);
     hipLaunchKernelGGL(k_gate_write, grid, dim3(kBlock), 0, s, p.pool.start, p.pool.expire, groups, G,
                        p.pool.num_gs, S, nblk, blk, p.list_A_base, p.n_A, wsp<uint32_t>(ws, p, WB_ACTIVE_LIST),
                        wsp<int32_t>(ws, p, WB_POS_OF));
@@ -174,8 +183,9 @@ void launch_frame_lists(hipStream_t s, const int32_t *start, const int32_t *expi
     const int nblk = (n_slots + kGateChunk - 1) / kGateChunk;
     dim3 grid(nblk, n_groups + 1);
     hipLaunchKernelGGL(k_gate_count, grid, dim3(kBlock), 0, s, start, expire, groups, n_groups, 0, n_slots, nblk,
-                       blk);
-    hipLaunchKernelGGL(k_gate_scan, dim3(n_groups + 1), dim3(kBlock), 0, s, blk, nblk, totals);
+                       blk, nullptr);
+    hipLaunchKernelGGL(k_gate_scan, dim3(n_groups + 1), dim3(kBlock), 0, s, blk, nblk, totals, groups, n_groups,
+                       0u, nullptr);
     hipLaunchKernelGGL(k_gate_write, grid, dim3(kBlock), 0, s, start, expire, groups, n_groups, 0, n_slots, nblk,
                        blk, 0u, 0u, lists, nullptr);
 }

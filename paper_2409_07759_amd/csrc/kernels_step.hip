@@ -428,10 +428,6 @@ __global__ void k_set_step(StepDev *sd, int64_t adam_t, uint64_t step, uint64_t 
     sd->step = step;
     sd->seed = seed;
 }
-__global__ void k_advance_step(StepDev *sd) {
-    sd->adam_t += 1;
-    sd->step += 1;
-}
 
 // ------------------------------------------------------------------ relocation
 __device__ __forceinline__ double softplus(double x) { return x > 0 ? x + log1p(exp(-x)) : log1p(exp(x)); }
@@ -587,7 +583,9 @@ __global__ void k_reloc_finish(const uint32_t *nD, const uint64_t *Wtot, int32_t
 __global__ void k_stats_out(const double *in, const uint32_t *pc, const uint32_t *nA, double *out) {
     for (int i = 0; i < 8; ++i) out[i] = in[i];
     out[4] = (double)pc[0];
-    out[6] = (double)pc[1];
+    // bit 0: pair capacity overflow; bit 1: live counts differ from the
+    // plan's (lifespans changed after plan creation; the lists are stale)
+    out[6] = (double)(pc[1] | (pc[3] ? 2u : 0u));
     if (nA) out[7] = (double)nA[0];
 }
 
@@ -747,10 +745,6 @@ void launch_relocate(hipStream_t s, const swgs_plan &p, uint8_t *ws, const swgs_
 
 void launch_set_step(hipStream_t s, uint8_t *ws_step, int64_t adam_t, uint64_t step, uint64_t seed) {
     hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, reinterpret_cast<StepDev *>(ws_step), adam_t, step, seed);
-}
-
-void launch_advance_step(hipStream_t s, uint8_t *ws_step) {
-    hipLaunchKernelGGL(k_advance_step, dim3(1), dim3(1), 0, s, reinterpret_cast<StepDev *>(ws_step));
 }
 
 void launch_stats_out(hipStream_t s, const double *stats, const uint32_t *pair_count, const uint32_t *nA,

@@ -120,7 +120,6 @@ struct swgs_plan {
     void *graph_ws = nullptr;
     const void *graph_targets = nullptr;
     void *graph_images = nullptr;
-    double *graph_stats = nullptr;
     swgs_step_cfg graph_cfg{};
     void *consts_host = nullptr;                  // pinned copy of the constant block
     size_t consts_bytes = 0;
@@ -212,7 +211,6 @@ void launch_adam_sgld(hipStream_t s, const swgs_plan &p, uint8_t *ws, const swgs
 void launch_relocate(hipStream_t s, const swgs_plan &p, uint8_t *ws, const swgs_step_cfg &cfg,
                      int32_t *dst_out, int32_t *src_out, int32_t *count_out);
 void launch_set_step(hipStream_t s, uint8_t *ws_step, int64_t adam_t, uint64_t step, uint64_t seed);
-void launch_advance_step(hipStream_t s, uint8_t *ws_step);
 void launch_fill_u32(hipStream_t s, uint32_t *p, uint32_t v, size_t n);
 void launch_fill_f32(hipStream_t s, float *p, float v, size_t n);
 void launch_fill_f64(hipStream_t s, double *p, double v, size_t n);
@@ -225,8 +223,8 @@ void launch_stats_out(hipStream_t s, const double *stats, const uint32_t *pair_c
 void launch_mature(hipStream_t s, const swgs_pool &pool, int F, int st, uint8_t *record,
                    uint32_t *scratch, uint32_t *d_count);
 
-// Device step parameters (kept in the workspace so a captured graph can
-// advance them on the device).
+// Device step parameters (kept in the workspace so a captured graph reads
+// them; each call sets them from its arguments before the replay).
 struct StepDev {
     int64_t adam_t;
     uint64_t step;

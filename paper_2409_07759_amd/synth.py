@@ -183,6 +183,20 @@ def steady_window_pool(num_gs: int, swin: int, sh_degree: int, st: int, seed: in
     return Pool(num_gs, swin, sh_degree, params, birth, start, expire)
 
 
+def add_faint_gaussians(pool: Pool, fraction: float, seed: int, lo: float = -7.0, hi: float = -3.5) -> int:
+    """Give a seeded `fraction` of the optimisable slots [0, num_gs)
+    near-transparent opacity logits, uniform in [lo, hi] (opacity 0.0009 ..
+    0.029): the low-opacity tail that a trained model carries and that
+    relocation works on.  With the default range about half of them start
+    below opacity 0.005; the rest lie just above it.  Changes pool.params in
+    place and returns the number of slots changed."""
+    rng = np.random.default_rng(seed)
+    k = int(round(fraction * pool.num_gs))
+    idx = rng.choice(pool.num_gs, size=k, replace=False)
+    pool.params[ROW_LOGIT, idx] = rng.uniform(lo, hi, size=k).astype(np.float32)
+    return k
+
+
 def uneven_window_pool(n_total: int, n_base: int, W: int, sh_degree: int, seed: int,
                        max_len: int = 27) -> Pool:
     """Pool for a W-frame window with uneven per-frame active sets: n_base

@@ -131,3 +131,35 @@ def test_active_gate_half_open():
     assert O.active(start, expire, 3).tolist() == [False, False, True, False]
     assert O.active(start, expire, 4).tolist() == [False, False, False, False]
     assert O.active(start, expire, 5).tolist() == [False, False, False, True]
+
+
+def test_threaded_oracle_loops_agree_with_one_thread():
+    """The OpenMP loops used by the CPU-baseline timing change nothing but
+    the order of the adjoint's sums over pixels: preprocess and render are
+    bit-identical, the record and parameter gradients agree to rounding."""
+    import oracle as O
+    from paper_2409_07759_amd import synth as S
+    params = S.make_gaussians(1500, 1, 4)
+    birth, start, expire = S.lifespans_tiny(1500, 4)
+    v = S.ring_views([1], 2, 80, 60)[1]
+    rng = np.random.default_rng(3)
+    out = []
+    for nt in (1, 4):
+        O.set_threads(nt)
+        try:
+            vis, rec, rect = O.preprocess(params, 1, start, expire, v)
+            rgb = O.render_records(vis, rec, v)[0]
+            dl = rng.uniform(-1, 1, size=(3, v.width * v.height)) if nt == 1 else dl
+            drec = O.blend_backward(vis, rec, v, dl)
+            gp = O.preprocess_backward_visible(params, 1, v, drec, vis, 1500)
+        finally:
+            O.set_threads(1)
+        out.append((vis, rec, rect, rgb, drec, gp))
+    a, b = out
+    for k in range(4):
+        assert np.array_equal(a[k], b[k])
+    assert np.allclose(a[4], b[4], rtol=1e-12, atol=1e-18) and np.abs(a[4]).max() > 0
+    assert np.allclose(a[5], b[5], rtol=1e-11, atol=1e-16)
+    # the C loop over visible slots equals the per-slot Python loop
+    ref = O.preprocess_backward(params, 1, v, a[4], np.nonzero(vis)[0])
+    assert np.array_equal(a[5], ref)

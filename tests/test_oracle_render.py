@@ -253,3 +253,53 @@ def test_tile_pairs_are_sorted_by_tile_depth_slot():
     counts = ((rect[:, 2] - rect[:, 0]) * (rect[:, 3] - rect[:, 1]))[vis == 1]
     assert len(tiles) == counts.sum()
     assert ranges[-1, 1] == len(tiles) and np.all(ranges[:, 0] <= ranges[:, 1])
+
+
+@pytest.mark.parametrize("tw,th", [(16, 16), (8, 8), (32, 8)])
+def test_tile_rect_of_hand_placed_gaussians_closed_form(tw, th):
+    """The support rectangle, pinned from both sides.  An isotropic Gaussian
+    of scale s and opacity o at camera-space (x, 0, z) projects to
+    u = f x / z + c_x with projected variances a = (f s / z)^2 (1 + (x/z)^2)
+    + 0.3 along the image x axis and c = (f s / z)^2 + 0.3 along y.  Its
+    support {alpha >= 1/255} has half-extents h_x = sqrt(2 ln(255 o) a),
+    h_y = sqrt(2 ln(255 o) c); the rect covers tiles
+    floor((u - h_x - 1) / T_w) .. floor((u + h_x + 1) / T_w) (one pixel of
+    padding), clipped to the grid.  Two on-axis Gaussians (opacity 0.9 and
+    0.01) are scaled to h = 15.5 px, so the padded edge crosses a tile
+    boundary that the unpadded edge does not, and a 3-sigma extent (first)
+    or an extent without the opacity term (second) lands in another tile;
+    the third Gaussian's rect is clipped at the grid's left edge."""
+    W, H = 256, 192
+    v = one_view(W, H)
+    z = 4.0                                   # the camera sits at world z = 4
+    f = v.fx
+    h = 15.5
+    gs = []
+    for (o, u_want) in ((0.9, v.cx), (0.01, v.cx), (0.9, 10.0)):
+        kappa = 2.0 * math.log(255.0 * o)
+        var = h * h / kappa                   # projected variance on the axis
+        gs.append(dict(o=o, kappa=kappa, var=var, s=z * math.sqrt(var - 0.3) / f, x=(u_want - v.cx) * z / f))
+    p = scene([dict(mean=(g["x"], 0, 0), logscale=[math.log(g["s"])] * 3, logit=logit(g["o"]), rgb=(0.5,) * 3)
+               for g in gs])
+    st, ex = always(len(gs))
+    vis, rec, rect = O.preprocess(p, 0, st, ex, v, tw, th)
+    assert (vis == 1).all()
+    tx, ty = -(-W // tw), -(-H // th)
+    for i, g in enumerate(gs):
+        s, x = g["s"], g["x"]
+        u = f * x / z + v.cx
+        a = (f * s / z) ** 2 * (1.0 + (x / z) ** 2) + 0.3
+        c = (f * s / z) ** 2 + 0.3
+        hx, hy = math.sqrt(g["kappa"] * a), math.sqrt(g["kappa"] * c)
+        want = (max(0, math.floor((u - hx - 1.0) / tw)), max(0, math.floor((v.cy - hy - 1.0) / th)),
+                min(tx, math.floor((u + hx + 1.0) / tw) + 1), min(ty, math.floor((v.cy + hy + 1.0) / th) + 1))
+        assert tuple(int(k) for k in rect[i]) == want, (i, rect[i], want)
+        assert rec[i, O.R_U] == pytest.approx(u, abs=1e-9)
+    assert rect[2, 0] == 0                    # clipped at the grid's left edge
+    # the rect tells the exact extent from the plausible wrong ones
+    if (tw, th) == (16, 16):
+        right = lambda e: math.floor((v.cx + e) / tw) + 1
+        assert int(rect[0, 2]) == int(rect[1, 2]) == right(h + 1.0) == 10 and int(rect[0, 0]) == 6
+        assert right(h) != right(h + 1.0)                                         # no padding
+        assert right(3.0 * math.sqrt(gs[0]["var"]) + 1.0) != right(h + 1.0)      # 3 sigma
+        assert right(math.sqrt(2.0 * math.log(255.0) * gs[1]["var"]) + 1.0) != right(h + 1.0)  # no opacity term
