@@ -763,6 +763,7 @@ swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *p, void *workspace, s
         launch_fill_f64(s, sdev, 0.0, 8);
         seq_gate(s, *p, ws);
         uint32_t *pc = wsp<uint32_t>(ws, *p, WB_PAIR_COUNT);
+        uint64_t k_total = 0;
         for (int v = 0; v < (int)p->views.size(); ++v) {
             seq_forward(s, *p, ws, v, images, targets, 1.0f - cfg->lambda_dssim, cfg->lambda_dssim > 0.0f);
             if (cfg->lambda_dssim > 0.0f) seq_ssim(s, *p, ws, v, v + 1, images, targets, cfg->lambda_dssim);
@@ -770,8 +771,12 @@ swgs_status swgs_window_step(swgs_context *ctx, swgs_plan *p, void *workspace, s
             HIP_TRY(ctx, hipMemcpyAsync(&k, pc, 4, hipMemcpyDeviceToHost, s));
             HIP_TRY(ctx, hipStreamSynchronize(s));
             if (k > (uint64_t)p->pair_cap) return fail(ctx, SWGS_ERR_CAPACITY, "pair capacity exceeded in view " + std::to_string(v));
+            k_total += k;
             seq_backward_blend(s, *p, ws, v, wsp<float>(ws, *p, WB_DLDC));
         }
+        // the step's pair count: the sum over the views (each view's count
+        // replaced the previous one on the device)
+        launch_fill_u32(s, pc, (uint32_t)std::min<uint64_t>(k_total, 0xFFFFFFFFull), 1);
         launch_loss_reduce(s, *p, ws, cfg, true);
         if (cfg->lambda_dssim > 0.0f) launch_ssim_reduce(s, *p, ws, cfg->lambda_dssim);
         seq_step_tail(s, *p, ws, *cfg);
