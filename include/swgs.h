@@ -284,6 +284,22 @@ swgs_status swgs_plan_timing(swgs_context *ctx, swgs_plan *plan, void *workspace
 swgs_status swgs_mature(swgs_context *ctx, const swgs_pool *pool, int32_t st,
                         void *record, size_t capacity, int64_t *count_out, size_t *bytes_out);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): swgs_mature without
+ * any allocation.  Arguments, record layout, pool changes and errors are
+ * those of swgs_mature, and so are the results, bit for bit.  Its scratch
+ * (flags, positions, scan sums, count: about 8 bytes per optimisable slot)
+ * is a 16 MiB array that the library holds on each device it runs on until
+ * the process ends, so num_gs must not exceed swgs_mature_noalloc_max_gs()
+ * (2,096,891); a larger pool fails with SWGS_ERR_CAPACITY before anything is
+ * launched.  All calls on one device share that array: calls that overlap
+ * on one device (two host threads, or two contexts on different streams)
+ * race.  Synchronises (once to read the count, once at the end). */
+swgs_status swgs_mature_noalloc(swgs_context *ctx, const swgs_pool *pool, int32_t st,
+                                void *record, size_t capacity, int64_t *count_out, size_t *bytes_out);
+/* Largest num_gs swgs_mature_noalloc accepts. */
+int64_t swgs_mature_noalloc_max_gs(void);
+
 /* Bytes of a mature record for `count` Gaussians of SH degree d. */
 size_t swgs_record_bytes(int64_t count, int32_t sh_degree);
 

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 
 #include "swgs_internal.h"
@@ -50,6 +51,32 @@ hipError_t ctx_scratch(swgs_context *ctx, size_t bytes, void **out) {
     *out = s.ptr;
     return hipSuccess;
 }
+
+// Scratch of swgs_mature_noalloc: a file-scope device array (each device
+// that runs the library holds its own copy until the process ends).  Host
+// code never uses the array's name as an address: its device address is
+// looked up once per device, with that device current, when a context is
+// created on it, and kept in g_noalloc_ptr.
+constexpr size_t kNoAllocWords = size_t(4) << 20;               // 16 MiB
+static __device__ __align__(256) uint32_t scratch[kNoAllocWords];
+constexpr int kMaxDevices = 64;
+void *g_noalloc_ptr[kMaxDevices] = {};
+std::mutex g_noalloc_mu;
+
+hipError_t noalloc_lookup(int device) {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    if (g_noalloc_ptr[device]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_noalloc_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+// words of mature's scratch for num_gs slots: flags, positions, the scan's
+// per-chunk sums, the count
+size_t mature_scratch_words(size_t n) { return 2 * (n + 1) + n / 4096 + 8; }
 
 bool pool_ok(const swgs_pool *p, bool need_train, std::string &why) {
     if (!p) { why = "pool is NULL"; return false; }
@@ -423,6 +450,8 @@ swgs_status swgs_context_create(int device, void *hip_stream, swgs_context **out
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SWGS_ERR_INVALID_ARG;
     if (hipSetDevice(device) != hipSuccess) return SWGS_ERR_HIP;
+    // the allocation-free entry points' scratch address on this device
+    if (noalloc_lookup(device) != hipSuccess) return SWGS_ERR_HIP;
     auto *c = new (std::nothrow) swgs_context;
     if (!c) return SWGS_ERR_HIP;
     c->device = device;
@@ -847,7 +876,7 @@ swgs_status swgs_mature(swgs_context *ctx, const swgs_pool *pool, int32_t st, vo
     if (!record) return fail(ctx, SWGS_ERR_INVALID_ARG, "record is NULL");
     const int n = pool->num_gs;
     void *scr = nullptr;
-    const size_t words = 2 * ((size_t)n + 1) + (size_t)n / 4096 + 8;
+    const size_t words = mature_scratch_words((size_t)n);
     HIP_TRY(ctx, ctx_scratch(ctx, words * 4, &scr));
     uint32_t *sc = static_cast<uint32_t *>(scr);
     uint32_t *d_count = sc + words - 2;
@@ -871,6 +900,54 @@ swgs_status swgs_mature(swgs_context *ctx, const swgs_pool *pool, int32_t st, vo
     if (count_out) *count_out = cnt;
     if (bytes_out) *bytes_out = need;
     return SWGS_OK;
+}
+
+swgs_status swgs_mature_noalloc(swgs_context *ctx, const swgs_pool *pool, int32_t st, void *record,
+                                size_t capacity, int64_t *count_out, size_t *bytes_out) {
+    if (!ctx) return SWGS_ERR_INVALID_ARG;
+    std::string why;
+    if (!pool_ok(pool, false, why)) return fail(ctx, SWGS_ERR_INVALID_ARG, why);
+    if (pool->n_slots < 2 * pool->num_gs) return fail(ctx, SWGS_ERR_INVALID_ARG, "mature needs n_slots >= 2 num_gs");
+    if (!record) return fail(ctx, SWGS_ERR_INVALID_ARG, "record is NULL");
+    const int n = pool->num_gs;
+    const size_t words = mature_scratch_words((size_t)n);
+    if (words > kNoAllocWords)
+        return fail(ctx, SWGS_ERR_CAPACITY, "num_gs " + std::to_string(n) + " needs " + std::to_string(4 * words) +
+                                                " bytes of scratch; the allocation-free call holds " +
+                                                std::to_string(4 * kNoAllocWords) + " (num_gs <= " +
+                                                std::to_string(swgs_mature_noalloc_max_gs()) + ")");
+    uint32_t *sc = static_cast<uint32_t *>(ctx->device >= 0 && ctx->device < kMaxDevices ? g_noalloc_ptr[ctx->device] : nullptr);
+    if (!sc) return fail(ctx, SWGS_ERR_HIP, "no scratch address for this device");
+    uint32_t *flag = sc;
+    uint32_t *pos = sc + n + 1;
+    uint32_t *d_count = sc + words - 2;
+    hipStream_t s = ctx->stream;
+    const int F = rows_for(pool->sh_degree);
+    // the count first, on the device (flags and their scan; every word these
+    // kernels read is written earlier in the same call): the record must be
+    // known to fit before anything is written
+    launch_mature_count(s, *pool, st, flag, pos, d_count);
+    uint32_t cnt = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&cnt, d_count, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    const size_t need = swgs_record_bytes(cnt, pool->sh_degree);
+    if (capacity < need) return fail(ctx, SWGS_ERR_INVALID_ARG, "record capacity " + std::to_string(capacity) + " < " + std::to_string(need));
+    launch_mature_pack(s, *pool, F, st, static_cast<uint8_t *>(record), flag, pos, d_count);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (count_out) *count_out = cnt;
+    if (bytes_out) *bytes_out = need;
+    return SWGS_OK;
+}
+
+int64_t swgs_mature_noalloc_max_gs(void) {
+    // largest n with 2 (n + 1) + n / 4096 + 8 <= kNoAllocWords
+    int64_t lo = 0, hi = (int64_t)kNoAllocWords;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (mature_scratch_words((size_t)mid) <= kNoAllocWords) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
 
 // version-2 (compact) records: header int32[16], see swgs_encode_update

@@ -752,11 +752,12 @@ void launch_stats_out(hipStream_t s, const double *stats, const uint32_t *pair_c
     hipLaunchKernelGGL(k_stats_out, dim3(1), dim3(1), 0, s, stats, pair_count, nA, out);
 }
 
-void launch_mature(hipStream_t s, const swgs_pool &pool, int F, int st, uint8_t *record, uint32_t *scratch,
-                   uint32_t *d_count) {
+// mature in two halves: the flags of the slots to mature and their
+// exclusive scan (positions, count), then the packing.  Scratch: flag [n+1],
+// pos [n+1], then the scan's per-chunk sums.
+void launch_mature_count(hipStream_t s, const swgs_pool &pool, int st, uint32_t *flag, uint32_t *pos,
+                         uint32_t *d_count) {
     const int n = pool.num_gs;
-    uint32_t *flag = scratch;
-    uint32_t *pos = scratch + n + 1;
     uint32_t *scan_scratch = pos + n + 1;
     const int nb = (n + kBlock - 1) / kBlock;
     if (nb == 0) {
@@ -765,8 +766,24 @@ void launch_mature(hipStream_t s, const swgs_pool &pool, int F, int st, uint8_t 
     }
     hipLaunchKernelGGL(k_mature_flags, dim3(nb), dim3(kBlock), 0, s, pool.start, n, st, flag);
     exclusive_scan_u32(s, flag, pos, (uint32_t)n, d_count, scan_scratch);
+}
+
+void launch_mature_pack(hipStream_t s, const swgs_pool &pool, int F, int st, uint8_t *record, const uint32_t *flag,
+                        const uint32_t *pos, const uint32_t *d_count) {
+    const int n = pool.num_gs;
+    const int nb = (n + kBlock - 1) / kBlock;
+    if (nb == 0) return;
     hipLaunchKernelGGL(k_mature_pack, dim3(nb), dim3(kBlock), 0, s, pool.params, pool.n_slots, n, F, pool.swin,
                        pool.sh_degree, st, pool.birth, pool.start, pool.expire, flag, pos, d_count, record);
+}
+
+void launch_mature(hipStream_t s, const swgs_pool &pool, int F, int st, uint8_t *record, uint32_t *scratch,
+                   uint32_t *d_count) {
+    const int n = pool.num_gs;
+    uint32_t *flag = scratch;
+    uint32_t *pos = scratch + n + 1;
+    launch_mature_count(s, pool, st, flag, pos, d_count);
+    launch_mature_pack(s, pool, F, st, record, flag, pos, d_count);
 }
 
 }  // namespace swgs

@@ -222,6 +222,10 @@ void launch_stats_out(hipStream_t s, const double *stats, const uint32_t *pair_c
 // Mature (kernels_step.hip)
 void launch_mature(hipStream_t s, const swgs_pool &pool, int F, int st, uint8_t *record,
                    uint32_t *scratch, uint32_t *d_count);
+void launch_mature_count(hipStream_t s, const swgs_pool &pool, int st, uint32_t *flag, uint32_t *pos,
+                         uint32_t *d_count);
+void launch_mature_pack(hipStream_t s, const swgs_pool &pool, int F, int st, uint8_t *record, const uint32_t *flag,
+                        const uint32_t *pos, const uint32_t *d_count);
 
 // Device step parameters (kept in the workspace so a captured graph reads
 // them; each call sets them from its arguments before the replay).

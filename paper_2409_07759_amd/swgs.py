@@ -100,6 +100,8 @@ _sigs = {
     "swgs_relocate": ([P, P, P, SZ, P, U64, U64, P, P, P], ctypes.c_int),
     "swgs_window_step": ([P, P, P, SZ, P, P, P, I64, U64, U64, P], ctypes.c_int),
     "swgs_mature": ([P, P, I32, P, SZ, P, P], ctypes.c_int),
+    "swgs_mature_noalloc": ([P, P, I32, P, SZ, P, P], ctypes.c_int),
+    "swgs_mature_noalloc_max_gs": ([], I64),
     "swgs_record_bytes": ([I64, I32], SZ),
     "swgs_plan_set_timing": ([P, P, P, SZ, I32], ctypes.c_int),
     "swgs_plan_timing": ([P, P, P, SZ, P, P, P], ctypes.c_int),
@@ -367,6 +369,18 @@ def mature(ctx: Context, pool: Pool, st: int):
     with ctx:
         ctx.check(swgs_mature(ctx.h, ctypes.byref(cp), int(st), ptr(rec), cap, ctypes.byref(cnt), ctypes.byref(nb)))
     return rec[:nb.value], cnt.value
+
+
+def mature_noalloc(ctx: Context, pool: Pool, st: int, record):
+    """swgs_mature_noalloc into the caller's `record` (uint8 device tensor of
+    at least swgs_record_bytes(num_gs, sh_degree) bytes); returns the used
+    part of the record and the number of Gaussians it holds."""
+    cnt, nb = ctypes.c_int64(), ctypes.c_size_t()
+    cp = pool.c()
+    with ctx:
+        ctx.check(swgs_mature_noalloc(ctx.h, ctypes.byref(cp), int(st), ptr(record), record.numel(),
+                                      ctypes.byref(cnt), ctypes.byref(nb)))
+    return record[:nb.value], cnt.value
 
 
 def encode_update(ctx: Context, record, enc: int = SWGS_ENC_Q, keep: int = -1):
