@@ -113,6 +113,18 @@ typedef struct {
     int64_t pair_capacity;     /* (view, tile, Gaussian) pairs held by the workspace (> 0) */
 } swgs_plan_opts;
 
+/* Bind a pool once (Algorithm 1's global gs and matured, Sec. 4.2): the
+ * descriptor is checked (struct_size, counts, SH degree) and every non-NULL
+ * pointer must be device memory of the context's device
+ * (SWGS_ERR_INVALID_ARG names the first that is not).  The handle keeps a
+ * copy of the descriptor -- the library never frees the caller's buffers --
+ * and swgs_pool_desc returns it (valid until release) for every call that
+ * takes a const swgs_pool *. */
+typedef struct swgs_pool_handle swgs_pool_handle;
+swgs_status swgs_pool_bind(swgs_context *ctx, const swgs_pool *desc, swgs_pool_handle **out);
+const swgs_pool *swgs_pool_desc(const swgs_pool_handle *h);
+swgs_status swgs_pool_release(swgs_pool_handle *h);
+
 /* Create a plan for rendering/training `views` (host array, copied) on
  * `pool` (copied).  Synchronises: counts the live slots of every distinct
  * frame on the device (lifespans must not change while the plan is in use;
@@ -469,6 +481,24 @@ typedef struct {
     size_t budget_bytes;       /* memory budget for batches (arena minus resident lists) */
     size_t resident_bytes;     /* per-frame live lists kept for the server's lifetime */
 } swgs_serve_stats;
+
+/* Algorithm 2's render (Sec. 4.3) of one batch of requests of mixed frames
+ * and resolutions on `pool`, without a server: the slots live at each
+ * request's frame (optimisable and frozen alike) are rendered forward in one
+ * launch sequence (gating, preprocess, depth sort, binning, tile sort,
+ * blend) into each request's `image` (device [3][height][width]; NULL:
+ * rendered, then dropped), each image bit-identical to the same request in
+ * any other batch.  opts as for swgs_plan_create (pair_capacity is the
+ * batch's pair capacity).  swgs_query_workspace_batch returns the workspace
+ * bytes the batch needs (device memory, 256-byte aligned, caller-owned;
+ * it counts the live slots of each frame on the device and synchronises).
+ * swgs_render_batch synchronises, sets each request's status (SWGS_OK, or
+ * SWGS_ERR_CAPACITY when the pairs exceeded the capacity: the call then
+ * fails with the needed count in its message), batch 0 and ready 0. */
+swgs_status swgs_query_workspace_batch(swgs_context *ctx, const swgs_pool *pool, const swgs_request *reqs,
+                                       int32_t n, const swgs_plan_opts *opts, size_t *ws_bytes);
+swgs_status swgs_render_batch(swgs_context *ctx, const swgs_pool *pool, swgs_request *reqs, int32_t n,
+                              const swgs_plan_opts *opts, void *workspace, size_t ws_bytes);
 
 /* Create a server on `pool` (copied; only params, start, expire are used).
  * `arena` (device, 256-byte aligned, arena_bytes, caller-owned) is carved

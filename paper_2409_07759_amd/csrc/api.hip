@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 
@@ -172,6 +173,12 @@ void swgs::compute_layout(const LayoutDims &d, Layout &lay, size_t &consts_bytes
                       WB_RELOC_FLAG, WB_RELOC_CNT, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_SCAN, WB_REG_PART,
                       WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE, WB_PAIR_BASE, WB_PAIR_GRAD, WB_PAIR_MASK})
             sz[b] = 0;
+        if (d.own_lists) {
+            // a standalone batch render gates into its workspace (no
+            // optimisable slots: no window set, no pos_of)
+            sz[WB_ACTIVE_LIST] = (n_list + 1) * 4;
+            sz[WB_GATE_BLK] = (G + 1) * nblk * 4;
+        }
     }
     // order: constant block, then the rest
     const int order_first[] = {WB_VIEWS, WB_GROUPS, WB_GROUP_VIEWS, WB_REC_VIEW_BASE};
@@ -209,6 +216,7 @@ void build_layout(swgs_plan &p) {
     for (auto &g : p.groups) d.n_list += g.n_live;
     d.Tssim = (size_t)p.Tssim;
     d.forward_only = p.forward_only;
+    d.own_lists = p.own_lists;
     compute_layout(d, p.lay, p.consts_bytes);
 }
 
@@ -480,10 +488,34 @@ swgs_status swgs_context_destroy(swgs_context *ctx) {
 
 const char *swgs_last_error(const swgs_context *ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
 
+// A plan object for `views` on `pool` (checks, live counts per frame on the
+// device -- synchronising --, geometry and layout).  forward_only plans
+// with own_lists gate into their own workspace and keep no training
+// buffers; their constant block lives in `host_consts` (pageable) instead of
+// pinned memory.
+static swgs_status make_plan(swgs_context *ctx, const swgs_pool *pool, const swgs_view *views, int32_t n_views,
+                             const swgs_plan_opts *opts, bool forward_only, swgs_plan **out);
+
 swgs_status swgs_plan_create(swgs_context *ctx, const swgs_pool *pool, const swgs_view *views, int32_t n_views,
                              const swgs_plan_opts *opts, swgs_plan **out, size_t *ws_bytes) {
     if (!ctx) return SWGS_ERR_INVALID_ARG;
     if (!out || !ws_bytes) return fail(ctx, SWGS_ERR_INVALID_ARG, "out/ws_bytes must not be NULL");
+    *out = nullptr;
+    swgs_plan *p = nullptr;
+    const swgs_status st = make_plan(ctx, pool, views, n_views, opts, false, &p);
+    if (st != SWGS_OK) return st;
+    if (hipHostMalloc(&p->consts_host, p->consts_bytes) != hipSuccess) {
+        delete p;
+        return fail(ctx, SWGS_ERR_HIP, "pinned constant block alloc failed");
+    }
+    fill_consts(*p);
+    *out = p;
+    *ws_bytes = p->lay.total;
+    return SWGS_OK;
+}
+
+static swgs_status make_plan(swgs_context *ctx, const swgs_pool *pool, const swgs_view *views, int32_t n_views,
+                             const swgs_plan_opts *opts, bool forward_only, swgs_plan **out) {
     *out = nullptr;
     std::string why;
     if (!pool_ok(pool, false, why)) return fail(ctx, SWGS_ERR_INVALID_ARG, why);
@@ -505,6 +537,12 @@ swgs_status swgs_plan_create(swgs_context *ctx, const swgs_pool *pool, const swg
     auto *p = new (std::nothrow) swgs_plan;
     if (!p) return fail(ctx, SWGS_ERR_HIP, "out of host memory");
     p->pool = *pool;
+    if (forward_only) {
+        // every live slot is drawn; none is optimised
+        p->pool.num_gs = 0;
+        p->forward_only = true;
+        p->own_lists = true;
+    }
     p->sh_degree = pool->sh_degree;
     p->F = rows_for(pool->sh_degree);
     p->tile_w = tw;
@@ -531,7 +569,7 @@ swgs_status swgs_plan_create(swgs_context *ctx, const swgs_pool *pool, const swg
         delete p;
         return fail(ctx, SWGS_ERR_HIP, "count upload failed");
     }
-    launch_count_live(ctx->stream, pool->start, pool->expire, pool->n_slots, pool->num_gs, d_frames, G, d_counts);
+    launch_count_live(ctx->stream, pool->start, pool->expire, pool->n_slots, p->pool.num_gs, d_frames, G, d_counts);
     if (hipMemcpyAsync(counts.data(), d_counts, 4 * (G + 1), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess) {
         delete p;
@@ -543,13 +581,127 @@ swgs_status swgs_plan_create(swgs_context *ctx, const swgs_pool *pool, const swg
         delete p;
         return fail(ctx, SWGS_ERR_UNSUPPORTED, gerr);
     }
-    if (hipHostMalloc(&p->consts_host, p->consts_bytes) != hipSuccess) {
-        delete p;
-        return fail(ctx, SWGS_ERR_HIP, "pinned constant block alloc failed");
-    }
-    fill_consts(*p);
     *out = p;
-    *ws_bytes = p->lay.total;
+    return SWGS_OK;
+}
+
+// ------------------------------------------------------------ pool handles
+struct swgs_pool_handle {
+    swgs_pool desc{};
+    int device = 0;
+};
+
+static bool device_ptr_on(const void *ptr, int device) {
+    hipPointerAttribute_t a;
+    std::memset(&a, 0, sizeof a);
+    if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
+        (void)hipGetLastError();   // an unknown host pointer is an answer, not a sticky error
+        return false;
+    }
+    return (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) && a.device == device;
+}
+
+swgs_status swgs_pool_bind(swgs_context *ctx, const swgs_pool *desc, swgs_pool_handle **out) {
+    if (!ctx) return SWGS_ERR_INVALID_ARG;
+    if (!out) return fail(ctx, SWGS_ERR_INVALID_ARG, "out must not be NULL");
+    *out = nullptr;
+    std::string why;
+    if (!pool_ok(desc, false, why)) return fail(ctx, SWGS_ERR_INVALID_ARG, why);
+    const struct { const void *p; const char *name; } ptrs[] = {
+        {desc->params, "params"}, {desc->grads, "grads"}, {desc->adam_m, "adam_m"}, {desc->adam_v, "adam_v"},
+        {desc->birth, "birth"}, {desc->start, "start"}, {desc->expire, "expire"}};
+    for (const auto &q : ptrs)
+        if (q.p && !device_ptr_on(q.p, ctx->device))
+            return fail(ctx, SWGS_ERR_INVALID_ARG, std::string("pool.") + q.name + " is not device memory of device " +
+                                                       std::to_string(ctx->device));
+    auto *h = new (std::nothrow) swgs_pool_handle;
+    if (!h) return fail(ctx, SWGS_ERR_HIP, "out of host memory");
+    h->desc = *desc;
+    h->device = ctx->device;
+    *out = h;
+    return SWGS_OK;
+}
+
+const swgs_pool *swgs_pool_desc(const swgs_pool_handle *h) { return h ? &h->desc : nullptr; }
+
+swgs_status swgs_pool_release(swgs_pool_handle *h) {
+    if (!h) return SWGS_ERR_INVALID_ARG;
+    delete h;
+    return SWGS_OK;
+}
+
+// ------------------------------------------------------------ batch render
+static swgs_status batch_views(swgs_context *ctx, const swgs_request *reqs, int32_t n, std::vector<swgs_view> &views) {
+    if (!reqs || n <= 0) return fail(ctx, SWGS_ERR_INVALID_ARG, "need at least one request");
+    views.resize(n);
+    for (int i = 0; i < n; ++i) views[i] = reqs[i].view;
+    return SWGS_OK;
+}
+
+static size_t batch_ws_bytes(const swgs_plan &p) { return align_up(p.lay.total, 256) + align_up(12 * (size_t)p.P, 256); }
+
+swgs_status swgs_query_workspace_batch(swgs_context *ctx, const swgs_pool *pool, const swgs_request *reqs, int32_t n,
+                                       const swgs_plan_opts *opts, size_t *ws_bytes) {
+    if (!ctx) return SWGS_ERR_INVALID_ARG;
+    if (!ws_bytes) return fail(ctx, SWGS_ERR_INVALID_ARG, "ws_bytes must not be NULL");
+    std::vector<swgs_view> views;
+    swgs_status st = batch_views(ctx, reqs, n, views);
+    if (st) return st;
+    swgs_plan *p = nullptr;
+    if ((st = make_plan(ctx, pool, views.data(), n, opts, true, &p))) return st;
+    *ws_bytes = batch_ws_bytes(*p);
+    delete p;
+    return SWGS_OK;
+}
+
+swgs_status swgs_render_batch(swgs_context *ctx, const swgs_pool *pool, swgs_request *reqs, int32_t n,
+                              const swgs_plan_opts *opts, void *workspace, size_t ws_bytes) {
+    if (!ctx) return SWGS_ERR_INVALID_ARG;
+    std::vector<swgs_view> views;
+    swgs_status st = batch_views(ctx, reqs, n, views);
+    if (st) return st;
+    swgs_plan *p = nullptr;
+    if ((st = make_plan(ctx, pool, views.data(), n, opts, true, &p))) return st;
+    std::unique_ptr<swgs_plan> hold(p);
+    if (!workspace) return fail(ctx, SWGS_ERR_INVALID_ARG, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(ctx, SWGS_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    const size_t need = batch_ws_bytes(*p);
+    if (ws_bytes < need)
+        return fail(ctx, SWGS_ERR_WORKSPACE_TOO_SMALL,
+                    "workspace has " + std::to_string(ws_bytes) + " bytes, needs " + std::to_string(need));
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    float *images = reinterpret_cast<float *>(ws + align_up(p->lay.total, 256));
+    hipStream_t s = ctx->stream;
+    // constant block from pageable memory: this call synchronises before it
+    // returns, so the buffer outlives the transfer
+    std::vector<uint8_t> consts(p->consts_bytes);
+    p->consts_host = consts.data();
+    fill_consts(*p);
+    const hipError_t ce = hipMemcpyAsync(ws + p->lay.off[WB_VIEWS], consts.data(), p->consts_bytes,
+                                         hipMemcpyHostToDevice, s);
+    p->consts_host = nullptr;
+    if (ce != hipSuccess) return fail(ctx, SWGS_ERR_HIP, std::string("constant upload: ") + hipGetErrorString(ce));
+    launch_gate(s, *p, ws);
+    seq_forward_all(s, *p, ws, images, nullptr);
+    for (int v = 0; v < n; ++v) {
+        if (!reqs[v].image) continue;
+        const size_t m = 3 * (size_t)views[v].width * (size_t)views[v].height;
+        HIP_TRY(ctx, hipMemcpyAsync(reqs[v].image, images + 3 * (size_t)p->vdev[v].pix_base, m * 4,
+                                    hipMemcpyDeviceToDevice, s));
+    }
+    uint32_t pc[2] = {0, 0};
+    HIP_TRY(ctx, hipMemcpyAsync(pc, wsp<uint32_t>(ws, *p, WB_PAIR_COUNT), 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    const bool over = pc[1] != 0;
+    for (int v = 0; v < n; ++v) {
+        reqs[v].status = over ? SWGS_ERR_CAPACITY : SWGS_OK;
+        reqs[v].batch = 0;
+        reqs[v].ready = 0.0;
+    }
+    if (over)
+        return fail(ctx, SWGS_ERR_CAPACITY, "batch needs " + std::to_string(pc[0]) + " pairs, capacity " +
+                                                std::to_string(p->pair_cap));
     return SWGS_OK;
 }
 

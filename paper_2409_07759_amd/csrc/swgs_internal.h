@@ -74,6 +74,7 @@ struct Layout {
 struct LayoutDims {
     size_t V = 0, G = 0, R = 0, T = 0, P = 0, cap = 0, S = 0, NG = 0, nA = 0, n_list = 0, Tssim = 0;
     bool forward_only = false;
+    bool own_lists = false;    // forward only, but gating into the workspace
 };
 
 enum WsBuf {
@@ -125,6 +126,9 @@ struct swgs_plan {
     size_t consts_bytes = 0;
     // forward-only plans (serving) carry no training buffers
     bool forward_only = false;
+    // a forward-only plan that gates into its own workspace (a standalone
+    // batch render) instead of reading resident lists
+    bool own_lists = false;
     // buffers that live outside the workspace (absolute device pointers; a
     // null entry means "at lay.off[] in the workspace")
     uint8_t *ext[swgs::WB_COUNT] = {};

@@ -89,6 +89,11 @@ _sigs = {
     "swgs_context_destroy": ([P], ctypes.c_int),
     "swgs_last_error": ([P], ctypes.c_char_p),
     "swgs_plan_create": ([P, P, P, I32, P, P, P], ctypes.c_int),
+    "swgs_pool_bind": ([P, P, P], ctypes.c_int),
+    "swgs_pool_desc": ([P], P),
+    "swgs_pool_release": ([P], ctypes.c_int),
+    "swgs_query_workspace_batch": ([P, P, P, I32, P, P], ctypes.c_int),
+    "swgs_render_batch": ([P, P, P, I32, P, P, SZ], ctypes.c_int),
     "swgs_plan_destroy": ([P], ctypes.c_int),
     "swgs_plan_measure": ([P, P, P, SZ, P, P], ctypes.c_int),
     "swgs_plan_buffer": ([P, I32, P, P], ctypes.c_int),
@@ -559,6 +564,52 @@ def c_requests(views, images=None, arrivals=None):
         arr[i].status = -1
         arr[i].batch = -1
     return arr
+
+
+class BoundPool:
+    """A pool bound with swgs_pool_bind (descriptor checked once, device
+    pointers verified); .desc() is the descriptor every call takes."""
+
+    def __init__(self, ctx: Context, pool: Pool):
+        self.ctx, self.pool = ctx, pool
+        self._cpool = pool.c()
+        h = ctypes.c_void_p()
+        with ctx:
+            ctx.check(swgs_pool_bind(ctx.h, ctypes.byref(self._cpool), ctypes.byref(h)))
+        self.h = h
+
+    def desc(self):
+        return swgs_pool_desc(self.h)
+
+    def close(self):
+        if self.h:
+            swgs_pool_release(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def render_batch(ctx: Context, pool: Pool, views, images=None, tile=(16, 16), lds_batch=0, pair_capacity=1 << 22):
+    """swgs_render_batch of one batch of (frame, camera, resolution)
+    requests into `images` (list of device [3, H, W] tensors or None);
+    returns the per-request statuses and the workspace bytes used."""
+    reqs = c_requests(views, images)
+    cp = pool.c()
+    opts = SwgsPlanOpts(ctypes.sizeof(SwgsPlanOpts), int(tile[0]), int(tile[1]), int(lds_batch), 0, int(pair_capacity))
+    nb = ctypes.c_size_t()
+    with ctx:
+        ctx.check(swgs_query_workspace_batch(ctx.h, ctypes.byref(cp), reqs, len(views), ctypes.byref(opts),
+                                             ctypes.byref(nb)))
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=ctx.device)
+        st = swgs_render_batch(ctx.h, ctypes.byref(cp), reqs, len(views), ctypes.byref(opts), ptr(ws), nb.value)
+    status = np.array([reqs[i].status for i in range(len(views))])
+    if st != SWGS_OK:
+        raise SwgsError(st, (swgs_last_error(ctx.h) or b"").decode())
+    return status, nb.value
 
 
 class Server:

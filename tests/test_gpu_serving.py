@@ -311,3 +311,63 @@ def test_server_submit_and_progress(sw, ctx, serving):
     assert all(r.ready >= r.arrival for r in list(reqs) + list(reqs2))
     srv.close()
     check_against_oracle(pool, views[:4], imgs[:4])
+
+
+# ---------------------------------------------------- standalone batch render
+def test_render_batch_matches_server_and_oracle(sw, ctx, serving):
+    """swgs_render_batch (no server: gating in its own workspace) renders a
+    batch of mixed frames and resolutions bit-identical to the server's
+    images of the same requests, and within 1e-5 of the oracle."""
+    pool, dp = serving
+    views = requests(10, 6, 41)
+    say("render_batch", len(views))
+    got = out_images(views)
+    status, ws_bytes = sw.render_batch(ctx, dp, views, images=got)
+    assert (status == sw.SWGS_OK).all() and ws_bytes > 0
+    ref = out_images(views)
+    srv = sw.Server(ctx, dp, 6, 256 << 20, lanes=2, max_batch=4)
+    (_, _, st2, _), _ = srv.run(views, images=ref)
+    srv.close()
+    assert (st2 == sw.SWGS_OK).all()
+    for a, b in zip(got, ref):
+        assert np.array_equal(host(a).view(np.uint32), host(b).view(np.uint32))
+    check_against_oracle(pool, views, got)
+
+
+def test_render_batch_reports_capacity_and_bad_workspace(sw, ctx, serving):
+    pool, dp = serving
+    views = requests(4, 6, 42)
+    say("render_batch capacity")
+    with pytest.raises(sw.SwgsError) as e:
+        sw.render_batch(ctx, dp, views, images=out_images(views), pair_capacity=64)
+    assert e.value.status == sw.SWGS_ERR_CAPACITY and "needs" in str(e.value)
+    import ctypes
+    reqs = sw.c_requests(views)
+    cp = dp.c()
+    opts = sw.SwgsPlanOpts(ctypes.sizeof(sw.SwgsPlanOpts), 16, 16, 0, 0, 1 << 20)
+    nb = ctypes.c_size_t()
+    ctx.check(sw.swgs_query_workspace_batch(ctx.h, ctypes.byref(cp), reqs, len(views), ctypes.byref(opts),
+                                            ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    assert sw.swgs_render_batch(ctx.h, ctypes.byref(cp), reqs, len(views), ctypes.byref(opts), sw.ptr(ws),
+                                nb.value - 256) == sw.SWGS_ERR_WORKSPACE_TOO_SMALL
+
+
+def test_pool_bind_checks_device_pointers(sw, ctx, serving):
+    """swgs_pool_bind keeps the checked descriptor; a host pointer in it is
+    refused; a plan made from the bound descriptor renders."""
+    import ctypes
+    pool, dp = serving
+    b = sw.BoundPool(ctx, dp)
+    d = ctypes.cast(b.desc(), ctypes.POINTER(sw.SwgsPool)).contents
+    assert d.params == dp.params.data_ptr() and d.n_slots == dp.params.shape[1]
+    pl = sw.Plan(ctx, dp, requests(2, 6, 43))
+    assert np.isfinite(host(pl.forward())).all()
+    pl.close()
+    b.close()
+    host_params = np.zeros(16, np.float32)
+    bad = dp.c()
+    bad.params = host_params.ctypes.data
+    h = ctypes.c_void_p()
+    assert sw.swgs_pool_bind(ctx.h, ctypes.byref(bad), ctypes.byref(h)) == sw.SWGS_ERR_INVALID_ARG
+    assert b"params" in sw.swgs_last_error(ctx.h)
