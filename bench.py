@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--c1-steps", type=int, default=100)
     ap.add_argument("--c3", type=int, default=1, help="time the uneven 180-view window (config 3)")
     ap.add_argument("--c3-steps", type=int, default=10)
+    ap.add_argument("--c3-tile", default="auto", help="auto (autotuner) or WxH/LDS, e.g. 16x16/256")
+    ap.add_argument("--c3-forms", default="graph,plain")
     ap.add_argument("--c5-advances", type=int, default=300, help="window advances of the 1M long video; 0: skip")
     ap.add_argument("--cpu-threads", type=int, default=0, help="threads of the oracle's all-core leg (0: the host's)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -395,14 +397,18 @@ def run_c3(args, ctx):
     torch.cuda.synchronize()
     tpl.close()
     del tp
-    dp = swgs.Pool.from_synth(student)
-    cands = [((8, 8), 128), ((8, 8), 256), ((16, 16), 128), ((16, 16), 256), ((32, 8), 128), ((32, 8), 256)]
-    tile, lds, table = autotune.tune(ctx, dp, views, reps=1, use_cache=False, candidates=cands, log=log)
-    del dp
-    torch.cuda.empty_cache()
+    if args.c3_tile == "auto":
+        dp = swgs.Pool.from_synth(student)
+        cands = [((8, 8), 128), ((8, 8), 256), ((16, 16), 128), ((16, 16), 256), ((32, 8), 128), ((32, 8), 256)]
+        tile, lds, table = autotune.tune(ctx, dp, views, reps=1, use_cache=False, candidates=cands, log=log)
+        del dp
+        torch.cuda.empty_cache()
+    else:
+        ts, ls = args.c3_tile.split("/")
+        tile, lds, table = tuple(int(x) for x in ts.split("x")), int(ls), []
     res = run_forms(ctx, student, views, targets, tile, lds, dict(window_start=0, relocate_period=1),
-                    ["graph", "plain"], args.c3_steps, 3, args.reps, 3 + args.reps * args.c3_steps, label="c3",
-                    inspect=True)
+                    [f.strip() for f in args.c3_forms.split(",")], args.c3_steps, 3, args.reps,
+                    3 + args.reps * args.c3_steps, label="c3", inspect=True)
     out = summarize_forms(res, "graph")
     live = res["graph"].get("inspect", {}).get("live_per_frame", [])
     out["workload"] = ("500k-slot pool, 30 frames x 6 cameras (960x720 / 1352x1014), uneven live sets, SH degree 3, "

@@ -382,6 +382,15 @@ std::string swgs::plan_geometry(swgs_plan &p, const swgs_view *views, int n_view
         pix += (int64_t)w.width * w.height;
     }
     if (rec >= 0xFFFFFFF0ull || tiles >= 0xFFFFFFF0ull) return "more than 2^32 records or tiles in one plan";
+    // the work per tile follows the live Gaussians per pixel of a view: a
+    // window whose views differ there is launched spread over the XCDs
+    double dmin = 1e300, dmax = 0.0;
+    for (int v = 0; v < n_views; ++v) {
+        const double d = (double)live[vgroup[v]] / ((double)views[v].width * (double)views[v].height);
+        dmin = std::min(dmin, d);
+        dmax = std::max(dmax, d);
+    }
+    p.uneven = n_views > 1 && dmax > 1.25 * dmin;
     p.R = (int64_t)rec;
     p.T = (int64_t)tiles;
     p.Tssim = (int64_t)tssim;

@@ -236,7 +236,8 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             int n_views, uint32_t tile_lo, float *__restrict__ images,
             float *__restrict__ T_final, uint32_t *__restrict__ last_out,
             const float *__restrict__ targets, float *__restrict__ dLdC, double *__restrict__ loss_part,
-            unsigned long long *__restrict__ counters, float l1_weight, uint8_t *__restrict__ pair_mask) {
+            unsigned long long *__restrict__ counters, float l1_weight, uint8_t *__restrict__ pair_mask,
+            uint32_t spread) {
     constexpr int NT = TW * TH;
     static_assert(64 % TW == 0 && 64 % TH == 0, "a tile lies inside one 64x64-aligned block");
     constexpr bool CULL = NT > 64;        // per-wave support-box lists
@@ -246,7 +247,9 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     __shared__ uint16_t slist[CULL ? NW : 1][CULL ? BATCH : 1];
     __shared__ float red[2][NT / 64];
     __shared__ unsigned long long cnt_evals, cnt_blend;
-    const uint32_t lt_idx = xcd_order(blockIdx.x, gridDim.x);   // neighbouring tiles share an XCD's L2
+    // neighbouring tiles share an XCD's L2; a window of uneven views is
+    // spread over the XCDs in chunks of tiles
+    const uint32_t lt_idx = xcd_spread(xcd_order(blockIdx.x, gridDim.x), gridDim.x, spread);
     const uint32_t tile = tile_lo + lt_idx;
     const ViewDev &V = views[view_of_tile(views, n_views, tile)];
     const uint32_t lt = tile - V.tile_base;
@@ -383,7 +386,7 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             const uint32_t *__restrict__ last_in, const float *__restrict__ dLdC,
             const uint2 *__restrict__ rect, const uint32_t *__restrict__ pair_base,
             const uint8_t *__restrict__ pair_mask, float *__restrict__ pair_grad,
-            unsigned long long *__restrict__ counters) {
+            unsigned long long *__restrict__ counters, uint32_t spread) {
     constexpr int NT = TW * TH;
     static_assert(64 % TW == 0 && 64 % TH == 0, "a tile lies inside one 64x64-aligned block");
     constexpr int NW = NT / 64;           // waves
@@ -396,7 +399,9 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     __shared__ float4 part[BB][NW][kTerm / 4];
     __shared__ uint32_t swlast[NW];
     __shared__ unsigned long long cnt_evals;
-    const uint32_t lt_idx = xcd_order(blockIdx.x, gridDim.x);   // neighbouring tiles share an XCD's L2
+    // neighbouring tiles share an XCD's L2; a window of uneven views is
+    // spread over the XCDs in chunks of tiles
+    const uint32_t lt_idx = xcd_spread(xcd_order(blockIdx.x, gridDim.x), gridDim.x, spread);
     const uint32_t tile = tile_lo + lt_idx;
     const ViewDev &V = views[view_of_tile(views, n_views, tile)];
     const uint32_t lt = tile - V.tile_base;
@@ -709,7 +714,8 @@ void fwd_launch(hipStream_t s, const swgs_plan &p, uint8_t *ws, float *images, c
                        (int)p.views.size(), tile_lo, images, wsp<float>(ws, p, WB_T_FINAL),
                        wsp<uint32_t>(ws, p, WB_LAST), targets, write_dldc ? wsp<float>(ws, p, WB_DLDC) : nullptr,
                        wsp<double>(ws, p, WB_LOSS_PART) + 2 * (size_t)tile_lo, counters, l1_weight,
-                       p.forward_only ? nullptr : wsp<uint8_t>(ws, p, WB_PAIR_MASK));
+                       p.forward_only ? nullptr : wsp<uint8_t>(ws, p, WB_PAIR_MASK),
+                       p.uneven && tile_hi - tile_lo == (uint32_t)p.T ? spread_multiplier(tile_hi - tile_lo) : 0u);
 }
 
 template <int TW, int TH, int BATCH>
@@ -722,7 +728,8 @@ void bwd_launch(hipStream_t s, const swgs_plan &p, uint8_t *ws, const float *dLd
                        (int)p.views.size(), tile_lo, wsp<float>(ws, p, WB_T_FINAL),
                        wsp<uint32_t>(ws, p, WB_LAST), dLdC, wsp<uint2>(ws, p, WB_RECT),
                        wsp<uint32_t>(ws, p, WB_PAIR_BASE), wsp<uint8_t>(ws, p, WB_PAIR_MASK),
-                       wsp<float>(ws, p, WB_PAIR_GRAD), counters);
+                       wsp<float>(ws, p, WB_PAIR_GRAD), counters,
+                       p.uneven && tile_hi - tile_lo == (uint32_t)p.T ? spread_multiplier(tile_hi - tile_lo) : 0u);
 }
 
 }  // namespace

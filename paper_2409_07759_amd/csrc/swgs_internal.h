@@ -33,6 +33,32 @@ __host__ __device__ inline uint32_t xcd_order(uint32_t b, uint32_t n) {
     return x * q + (x < r ? x : r) + i;
 }
 
+// A launch over many views whose work per tile differs between views (an
+// uneven window: frames with few and with many live Gaussians) would leave
+// the XCDs holding the densest views' eighths busy after the others are
+// done.  xcd_spread maps a position p of xcd_order's order to a work item
+// so that the full chunks of kSpreadChunk consecutive items are visited in
+// the order k -> (k s) mod m (m full chunks, s coprime to m, about m / 8):
+// each XCD's contiguous positions then cover chunks spread over the whole
+// range, and neighbouring items stay together inside a chunk.  s = 0: p
+// itself.
+constexpr uint32_t kSpreadChunk = 1024;
+__host__ __device__ inline uint32_t xcd_spread(uint32_t p, uint32_t n, uint32_t s) {
+    const uint32_t m = n / kSpreadChunk, k = p / kSpreadChunk;
+    if (s == 0 || k >= m) return p;
+    return (uint32_t)(((uint64_t)k * s) % m) * kSpreadChunk + p % kSpreadChunk;
+}
+// the multiplier xcd_spread uses for n items (0 when there are fewer than
+// two full chunks per XCD)
+inline uint32_t spread_multiplier(uint32_t n) {
+    const uint32_t m = n / kSpreadChunk;
+    if (m < 2 * kXcds) return 0;
+    auto gcd = [](uint32_t a, uint32_t b) { while (b) { const uint32_t t = a % b; a = b; b = t; } return a; };
+    uint32_t s = m / kXcds + 1;
+    while (gcd(s, m) != 1) ++s;
+    return s;
+}
+
 // A view as the kernels see it: camera in FP64 plus its place in the plan.
 struct ViewDev {
     double R[9];
@@ -109,6 +135,7 @@ struct swgs_plan {
     std::vector<swgs::ViewDev> vdev;              // caller order
     std::vector<swgs::GroupDev> groups;           // distinct frames
     std::vector<int32_t> group_views;             // view indices ordered by group
+    bool uneven = false;                          // views' live Gaussians per pixel differ by more than 25%
     uint32_t n_A = 0;                             // |A|
     uint32_t list_A_base = 0;
     int64_t R = 0, P = 0, T = 0, Tssim = 0;   // records, pixels, tiles, SSIM tiles
