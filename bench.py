@@ -408,9 +408,13 @@ def run_c3(args, ctx):
         tile, lds, table = tuple(int(x) for x in ts.split("x")), int(ls), []
     res = run_forms(ctx, student, views, targets, tile, lds, dict(window_start=0, relocate_period=1),
                     [f.strip() for f in args.c3_forms.split(",")], args.c3_steps, 3, args.reps,
-                    3 + args.reps * args.c3_steps, label="c3", inspect=True)
+                    3 + args.reps * args.c3_steps, label="c3", inspect=True, breakdown=True)
     out = summarize_forms(res, "graph")
-    live = res["graph"].get("inspect", {}).get("live_per_frame", [])
+    if "batched" in res and res["batched"]["timing"]:
+        out["kernel_ms_per_step_batched"] = {k: round(v[0] / max(1, res["batched"]["timed_steps"]), 4)
+                                             for k, v in res["batched"]["timing"].items()}
+    first = res[list(res)[0]]
+    live = first.get("inspect", {}).get("live_per_frame", [])
     out["workload"] = ("500k-slot pool, 30 frames x 6 cameras (960x720 / 1352x1014), uneven live sets, SH degree 3, "
                        "relocation every step")
     out["tile"], out["lds_batch"] = f"{tile[0]}x{tile[1]}", lds
