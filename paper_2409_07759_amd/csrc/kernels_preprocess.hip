@@ -46,6 +46,39 @@ __device__ __forceinline__ void sh_basis64(int deg, double x, double y, double z
     Y[15] = -0.5900435899266435 * x * (xx - 3.0 * yy);
 }
 
+// The same basis, each term added into the three channel sums as soon as it
+// is formed (acc[c] += Y_k sh[3 k + c], k ascending: the sums of the loop
+// over sh_basis64's terms, without holding all sixteen terms at once).
+__device__ __forceinline__ void sh_accumulate64(int deg, double x, double y, double z, const float *sh,
+                                                double *acc) {
+    auto add = [&](int k, double yk) {
+        acc[0] += yk * (double)sh[3 * k];
+        acc[1] += yk * (double)sh[3 * k + 1];
+        acc[2] += yk * (double)sh[3 * k + 2];
+    };
+    add(0, 0.28209479177387814);
+    if (deg < 1) return;
+    const double c1 = 0.4886025119029199;
+    add(1, -c1 * y);
+    add(2, c1 * z);
+    add(3, -c1 * x);
+    if (deg < 2) return;
+    const double xx = x * x, yy = y * y, zz = z * z;
+    add(4, 1.0925484305920792 * x * y);
+    add(5, -1.0925484305920792 * y * z);
+    add(6, 0.31539156525252005 * (2.0 * zz - xx - yy));
+    add(7, -1.0925484305920792 * x * z);
+    add(8, 0.5462742152960396 * (xx - yy));
+    if (deg < 3) return;
+    add(9, -0.5900435899266435 * y * (3.0 * xx - yy));
+    add(10, 2.890611442640554 * x * y * z);
+    add(11, -0.4570457994644658 * y * (4.0 * zz - xx - yy));
+    add(12, 0.3731763325901154 * z * (2.0 * zz - 3.0 * xx - 3.0 * yy));
+    add(13, -0.4570457994644658 * x * (4.0 * zz - xx - yy));
+    add(14, 1.445305721320277 * z * (xx - yy));
+    add(15, -0.5900435899266435 * x * (xx - 3.0 * yy));
+}
+
 __device__ __forceinline__ int clip_tile(double f, int n) {
     return f < 0.0 ? 0 : (f > (double)n ? n : (int)f);
 }
@@ -173,22 +206,27 @@ k_preprocess(const float *__restrict__ params, int n_slots, int deg, const Group
         double dx = mx - V.campos[0], dy = my - V.campos[1], dz = mz - V.campos[2];
         const double dn = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
         dx *= dn; dy *= dn; dz *= dn;
-        double Y[16];
-        sh_basis64(deg, dx, dy, dz, Y);
         double col[3];
+        if constexpr (HOIST_SH) {
+            double acc[3] = {0.0, 0.0, 0.0};
+            sh_accumulate64(deg, dx, dy, dz, sh, acc);
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            double acc = 0.0;
-            if constexpr (HOIST_SH) {
-#pragma unroll
-                for (int kk = 0; kk < 16; ++kk)
-                    if (kk < nk) acc += Y[kk] * (double)sh[3 * kk + ch];
-            } else {
-                for (int kk = 0; kk < nk; ++kk) acc += Y[kk] * (double)params[(11 + 3 * kk + ch) * S + slot];
+            for (int ch = 0; ch < 3; ++ch) {
+                const double a = acc[ch] + 0.5;
+                col[ch] = a > 0.0 ? a : 0.0;
+                flags |= a > 0.0 ? 0u : (1u << ch);
             }
-            acc += 0.5;
-            col[ch] = acc > 0.0 ? acc : 0.0;
-            flags |= acc > 0.0 ? 0u : (1u << ch);
+        } else {
+            double Y[16];
+            sh_basis64(deg, dx, dy, dz, Y);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                double acc = 0.0;
+                for (int kk = 0; kk < nk; ++kk) acc += Y[kk] * (double)params[(11 + 3 * kk + ch) * S + slot];
+                acc += 0.5;
+                col[ch] = acc > 0.0 ? acc : 0.0;
+                flags |= acc > 0.0 ? 0u : (1u << ch);
+            }
         }
         cflags[r] = (uint8_t)flags;
         const float zf = (float)pz;
