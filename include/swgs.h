@@ -155,8 +155,7 @@ enum {
                                   -log2(e) A/2, -log2(e) B, -log2(e) C/2 (conic [[A,B],[B,C]]), opacity,
                                   r, g, b, FP32 depth */
     SWGS_BUF_PAIR_KEY,         /* uint32 [cap] global tile id of each sorted pair */
-    SWGS_BUF_PAIR_VAL,         /* uint32 [cap] of each sorted pair, its record's position in the
-                                  depth order (the record: the depth-order buffer at that index) */
+    SWGS_BUF_PAIR_VAL,         /* uint32 [cap] record of each sorted pair */
     SWGS_BUF_PAIR_COUNT,       /* uint32 [2]: pairs emitted, overflow flag */
     SWGS_BUF_TILE_RANGE,       /* uint32 [n_tiles][2] first, last pair of each tile */
     SWGS_BUF_T_FINAL,          /* float [P] final transmittance per pixel */

@@ -162,6 +162,7 @@ void swgs::compute_layout(const LayoutDims &d, Layout &lay, size_t &consts_bytes
     sz[WB_SSIM_PART] = 9 * P * 4;                     // dS/d(mu_x, E[x^2], E[xy]) per pixel and channel
     sz[WB_SSIM_SUM] = (3 * d.Tssim + 256) * 8;          // per (SSIM tile, channel), then 256 chunk sums
     sz[WB_IMAGE] = 3 * P * 4;                         // renders when the caller passes no image buffer
+    sz[WB_PAIR_BASE] = R * 4;                         // first emission slot of each record
     sz[WB_PAIR_MASK] = (cap + 3) / 4 * 4;             // each pair's support mask over the tile's waves (forward -> backward)
     sz[WB_PAIR_GRAD] = cap * 9 * 4 + 16;              // 9 gradient terms per (tile, record) pair, emission
                                                       // order (+16: the reduce reads whole 16-byte vectors)
@@ -170,7 +171,7 @@ void swgs::compute_layout(const LayoutDims &d, Layout &lay, size_t &consts_bytes
         // no loss, no step
         for (int b : {WB_ACTIVE_LIST, WB_GATE_BLK, WB_POS_OF, WB_DLDC, WB_REC_GRAD, WB_LOSS_PART, WB_RELOC_W,
                       WB_RELOC_FLAG, WB_RELOC_CNT, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_SCAN, WB_REG_PART,
-                      WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE, WB_PAIR_GRAD, WB_PAIR_MASK})
+                      WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE, WB_PAIR_BASE, WB_PAIR_GRAD, WB_PAIR_MASK})
             sz[b] = 0;
         if (d.own_lists) {
             // a standalone batch render gates into its workspace (no
@@ -286,7 +287,7 @@ void seq_forward(hipStream_t s, swgs_plan &p, uint8_t *ws, int view, float *imag
         radix_sort_pairs(s, wsp<uint32_t>(ws, p, WB_DEPTH_KEY) + rec_lo, wsp<uint32_t>(ws, p, WB_REC_IDX) + rec_lo,
                          wsp<uint32_t>(ws, p, WB_KEY_ALT) + rec_lo, wsp<uint32_t>(ws, p, WB_IDX_ALT) + rec_lo, nullptr,
                          rec_hi - rec_lo, rec_hi - rec_lo, 32, hist, tot, wsp<uint2>(ws, p, WB_RECT),
-                         wsp<uint2>(ws, p, WB_RECT_SORTED) + rec_lo, wsp<uint32_t>(ws, p, WB_PAIR_OFFSET) + rec_lo);
+                         wsp<uint2>(ws, p, WB_RECT_SORTED), wsp<uint32_t>(ws, p, WB_PAIR_OFFSET));
         launch_pair_offsets(s, p, ws, rec_lo, rec_hi);
         launch_emit_pairs(s, p, ws, rec_lo, rec_hi);
         uint32_t *pc = wsp<uint32_t>(ws, p, WB_PAIR_COUNT);

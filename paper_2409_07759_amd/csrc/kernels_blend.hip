@@ -232,8 +232,7 @@ __device__ __forceinline__ int view_of_tile(const ViewDev *views, int n_views, u
 template <int TW, int TH, int BATCH, bool COUNT>
 __global__ void __launch_bounds__(TW *TH)
 k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_val,
-            const uint32_t *__restrict__ depth_order, const float4 *__restrict__ splat,
-            const ViewDev *__restrict__ views,
+            const float4 *__restrict__ splat, const ViewDev *__restrict__ views,
             int n_views, uint32_t tile_lo, float *__restrict__ images,
             float *__restrict__ T_final, uint32_t *__restrict__ last_out,
             const float *__restrict__ targets, float *__restrict__ dLdC, double *__restrict__ loss_part,
@@ -273,7 +272,7 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         if (__syncthreads_and(done)) break;
         for (int k = threadIdx.x; k < BATCH; k += NT) {
             if (b0 + k < n) {
-                const uint32_t r = depth_order[pair_val[rg.x + b0 + k]];
+                const uint32_t r = pair_val[rg.x + b0 + k];
                 const float4 a = splat[3 * (size_t)r], b = splat[3 * (size_t)r + 1];
                 sa[k] = block_offset(a, tx * TW, ty * TH);
                 sb[k] = b;
@@ -382,10 +381,10 @@ constexpr int kTerm = 12;                 // 9 terms padded to 3 x float4
 template <int TW, int TH, int BATCH, bool COUNT>
 __global__ void __launch_bounds__(TW *TH)
 k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_val,
-            const uint32_t *__restrict__ depth_order, const float4 *__restrict__ splat,
-            const ViewDev *__restrict__ views, int n_views, uint32_t tile_lo, const float *__restrict__ T_final,
+            const float4 *__restrict__ splat, const ViewDev *__restrict__ views,
+            int n_views, uint32_t tile_lo, const float *__restrict__ T_final,
             const uint32_t *__restrict__ last_in, const float *__restrict__ dLdC,
-            const uint2 *__restrict__ rect_sorted, const uint32_t *__restrict__ pair_offset,
+            const uint2 *__restrict__ rect, const uint32_t *__restrict__ pair_base,
             const uint8_t *__restrict__ pair_mask, float *__restrict__ pair_grad,
             unsigned long long *__restrict__ counters, uint32_t spread) {
     constexpr int NT = TW * TH;
@@ -445,13 +444,12 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
 #pragma unroll
     for (int w = 0; w < NW; ++w) nmax = max(nmax, swlast[w]);
     if (COUNT && threadIdx.x == 0) atomicAdd(counters + 4 * (blockIdx.x % kCounterSlots) + 1, cnt_evals);
-    // A pair's slot: the first emission slot of the record at depth
-    // position i plus this tile's row-major index inside the record's tile
-    // rect (both kept in depth order).
-    auto slot_of = [&](uint32_t i) {
-        const uint2 rc = rect_sorted[i];
+    // A pair's slot: the record's first emission slot plus this tile's
+    // row-major index inside the record's tile rect.
+    auto slot_of = [&](uint32_t r) {
+        const uint2 rc = rect[r];
         const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu;
-        return pair_offset[i] + ((uint32_t)ty - y0) * (x1 - x0) + ((uint32_t)tx - x0);
+        return pair_base[r] + ((uint32_t)ty - y0) * (x1 - x0) + ((uint32_t)tx - x0);
     };
     // pairs past every pixel's last contributor get zero terms
     for (uint32_t q = nmax + threadIdx.x; q < rg.y - rg.x; q += NT) {
@@ -475,8 +473,8 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         const uint32_t b_start = b_end > (uint32_t)BB ? b_end - BB : 0;
         const int m = (int)(b_end - b_start);
         for (int k = threadIdx.x; k < m; k += NT) {
-            const uint32_t i = pair_val[rg.x + b_start + k], r = depth_order[i];
-            sslot[k] = slot_of(i);
+            const uint32_t r = pair_val[rg.x + b_start + k];
+            sslot[k] = slot_of(r);
             sa[k] = block_offset(splat[3 * (size_t)r], tx * TW, ty * TH);
             sb[k] = splat[3 * (size_t)r + 1];
             sc[k] = splat[3 * (size_t)r + 2];
@@ -712,7 +710,7 @@ void fwd_launch(hipStream_t s, const swgs_plan &p, uint8_t *ws, float *images, c
     auto kern = counters ? k_blend_fwd<TW, TH, BATCH, true> : k_blend_fwd<TW, TH, BATCH, false>;
     hipLaunchKernelGGL(kern, dim3(tile_hi - tile_lo), dim3(TW * TH), 0, s,
                        wsp<uint2>(ws, p, WB_TILE_RANGE), wsp<uint32_t>(ws, p, WB_PAIR_VAL),
-                       wsp<uint32_t>(ws, p, WB_REC_IDX), wsp<float4>(ws, p, WB_SPLAT), wsp<ViewDev>(ws, p, WB_VIEWS),
+                       wsp<float4>(ws, p, WB_SPLAT), wsp<ViewDev>(ws, p, WB_VIEWS),
                        (int)p.views.size(), tile_lo, images, wsp<float>(ws, p, WB_T_FINAL),
                        wsp<uint32_t>(ws, p, WB_LAST), targets, write_dldc ? wsp<float>(ws, p, WB_DLDC) : nullptr,
                        wsp<double>(ws, p, WB_LOSS_PART) + 2 * (size_t)tile_lo, counters, l1_weight,
@@ -726,10 +724,10 @@ void bwd_launch(hipStream_t s, const swgs_plan &p, uint8_t *ws, const float *dLd
     auto kern = counters ? k_blend_bwd<TW, TH, BATCH, true> : k_blend_bwd<TW, TH, BATCH, false>;
     hipLaunchKernelGGL(kern, dim3(tile_hi - tile_lo), dim3(TW * TH), 0, s,
                        wsp<uint2>(ws, p, WB_TILE_RANGE), wsp<uint32_t>(ws, p, WB_PAIR_VAL),
-                       wsp<uint32_t>(ws, p, WB_REC_IDX), wsp<float4>(ws, p, WB_SPLAT), wsp<ViewDev>(ws, p, WB_VIEWS),
+                       wsp<float4>(ws, p, WB_SPLAT), wsp<ViewDev>(ws, p, WB_VIEWS),
                        (int)p.views.size(), tile_lo, wsp<float>(ws, p, WB_T_FINAL),
-                       wsp<uint32_t>(ws, p, WB_LAST), dLdC, wsp<uint2>(ws, p, WB_RECT_SORTED),
-                       wsp<uint32_t>(ws, p, WB_PAIR_OFFSET), wsp<uint8_t>(ws, p, WB_PAIR_MASK),
+                       wsp<uint32_t>(ws, p, WB_LAST), dLdC, wsp<uint2>(ws, p, WB_RECT),
+                       wsp<uint32_t>(ws, p, WB_PAIR_BASE), wsp<uint8_t>(ws, p, WB_PAIR_MASK),
                        wsp<float>(ws, p, WB_PAIR_GRAD), counters,
                        p.uneven && tile_hi - tile_lo == (uint32_t)p.T ? spread_multiplier(tile_hi - tile_lo) : 0u);
 }
@@ -779,7 +777,7 @@ void launch_pair_grad_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, uin
     if (rec_hi <= rec_lo) return;
     const uint32_t n = rec_hi - rec_lo;
     hipLaunchKernelGGL(k_pair_grad_reduce, dim3((n + kReduceRecs - 1) / kReduceRecs), dim3(256), 0, s,
-                       wsp<uint32_t>(ws, p, WB_REC_IDX) + rec_lo, wsp<uint32_t>(ws, p, WB_PAIR_OFFSET) + rec_lo,
+                       wsp<uint32_t>(ws, p, WB_REC_IDX) + rec_lo, wsp<uint32_t>(ws, p, WB_PAIR_OFFSET),
                        wsp<uint32_t>(ws, p, WB_PAIR_COUNT), wsp<float>(ws, p, WB_PAIR_GRAD), (uint32_t)p.pair_cap, n,
                        wsp<float>(ws, p, WB_REC_GRAD));
 }

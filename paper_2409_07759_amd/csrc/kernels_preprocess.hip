@@ -249,16 +249,13 @@ k_preprocess(const float *__restrict__ params, int n_slots, int deg, const Group
 // lanes' offsets), and the slot's tile is the record's rect tile at the
 // slot's row-major index.  Stores are coalesced, and a record covering
 // many tiles spreads over the wave instead of holding it up.  The rects
-// come in depth order (gathered by the depth sort's last pass).  A pair's
-// value is its record's position in the depth order (pos0 + index here):
-// the blend reads the record through the depth order, and the backward
-// finds the pair's emission slot from the depth-ordered offsets and rects.
+// come in depth order (gathered by the depth sort's last pass).
 __global__ void __launch_bounds__(kBlock)
 k_emit_pairs(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ offsets,
              const uint32_t *__restrict__ total_ptr, const uint2 *__restrict__ rect_sorted,
              const uint32_t *__restrict__ rec_view_base, int n_views, const ViewDev *__restrict__ views,
              uint32_t n, uint32_t cap, uint32_t *__restrict__ pair_key, uint32_t *__restrict__ pair_val,
-             uint32_t pos0) {
+             uint32_t *__restrict__ pair_base) {
     const int lane = threadIdx.x & 63;
     const uint32_t j0 = blockIdx.x * kBlock + (threadIdx.x & ~63u);   // the wave's first record
     if (j0 >= n) return;                                                 // whole waves only
@@ -281,6 +278,9 @@ k_emit_pairs(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict
         const uint2 rc = rect_sorted[j];
         xy0 = rc.x;
         w = max((rc.y & 0xFFFFu) - (rc.x & 0xFFFFu), 1u);
+        // the record's pairs take slots off .. off + count - 1 (the
+        // backward finds a pair's slot from this base)
+        if (pair_base) pair_base[r] = off;
     }
     const uint32_t start = __shfl(off, 0, 64);
     for (uint32_t base = start; base < end; base += 64) {   // uniform trip count: all lanes shuffle
@@ -291,7 +291,7 @@ k_emit_pairs(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict
             const uint32_t o = __shfl(off, l + step, 64);
             if (o <= slot) l += step;
         }
-        const uint32_t lxy = __shfl(xy0, l, 64), lw = __shfl(w, l, 64);
+        const uint32_t lr = __shfl(r, l, 64), lxy = __shfl(xy0, l, 64), lw = __shfl(w, l, 64);
         const uint32_t lbase = __shfl(tbase, l, 64), ltx = __shfl(tiles_x, l, 64);
         const uint32_t loc = slot - __shfl(off, l, 64);
         uint32_t q = (uint32_t)((float)loc / (float)lw);       // loc / lw, corrected below
@@ -300,7 +300,7 @@ k_emit_pairs(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict
         const uint32_t tx = (lxy & 0xFFFFu) + (loc - q * lw), ty = (lxy >> 16) + q;
         if (slot < end && slot < cap) {
             pair_key[slot] = lbase + ty * ltx + tx;
-            pair_val[slot] = pos0 + j0 + (uint32_t)l;   // the record's depth position
+            pair_val[slot] = lr;
         }
     }
 }
@@ -383,7 +383,7 @@ void launch_pair_offsets(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_
     // the depth sort's last pass) become, in place, their first pair slots;
     // then the pair total + overflow flag
     uint32_t *pc = wsp<uint32_t>(ws, p, WB_PAIR_COUNT);
-    uint32_t *off = wsp<uint32_t>(ws, p, WB_PAIR_OFFSET) + rec_lo;
+    uint32_t *off = wsp<uint32_t>(ws, p, WB_PAIR_OFFSET);
     exclusive_scan_u32(s, off, off, rec_hi - rec_lo, pc + 2, wsp<uint32_t>(ws, p, WB_SORT_TOTAL));
     hipLaunchKernelGGL(k_pair_total, dim3(1), dim3(1), 0, s, pc + 2, (uint32_t)p.pair_cap, pc);
 }
@@ -394,11 +394,12 @@ void launch_emit_pairs(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t 
     // into the buffers the tile sort reads its input from
     const bool alt = radix_input_in_alt(p.tile_key_bits);
     hipLaunchKernelGGL(k_emit_pairs, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                       wsp<uint32_t>(ws, p, WB_REC_IDX) + rec_lo, wsp<uint32_t>(ws, p, WB_PAIR_OFFSET) + rec_lo,
-                       wsp<uint32_t>(ws, p, WB_PAIR_COUNT) + 2, wsp<uint2>(ws, p, WB_RECT_SORTED) + rec_lo,
+                       wsp<uint32_t>(ws, p, WB_REC_IDX) + rec_lo, wsp<uint32_t>(ws, p, WB_PAIR_OFFSET),
+                       wsp<uint32_t>(ws, p, WB_PAIR_COUNT) + 2, wsp<uint2>(ws, p, WB_RECT_SORTED),
                        wsp<uint32_t>(ws, p, WB_REC_VIEW_BASE), (int)p.views.size(), wsp<ViewDev>(ws, p, WB_VIEWS),
                        n, (uint32_t)p.pair_cap, wsp<uint32_t>(ws, p, alt ? WB_PAIR_KEY_ALT : WB_PAIR_KEY),
-                       wsp<uint32_t>(ws, p, alt ? WB_PAIR_VAL_ALT : WB_PAIR_VAL), rec_lo);
+                       wsp<uint32_t>(ws, p, alt ? WB_PAIR_VAL_ALT : WB_PAIR_VAL),
+                       p.forward_only ? nullptr : wsp<uint32_t>(ws, p, WB_PAIR_BASE));
 }
 
 void launch_tile_ranges(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t tile_lo, uint32_t tile_hi) {

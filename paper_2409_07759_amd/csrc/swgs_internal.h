@@ -112,7 +112,7 @@ enum WsBuf {
     WB_PAIR_OFFSET, WB_SORT_HIST, WB_SORT_TOTAL, WB_LAST, WB_LOSS_PART, WB_STATS, WB_STEP,
     WB_VIEWS, WB_GROUPS, WB_GROUP_VIEWS,
     WB_RELOC_W, WB_RELOC_FLAG, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_CNT, WB_RELOC_SCAN, WB_REG_PART, WB_COUNTERS, WB_CFLAGS,
-    WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE, WB_PAIR_GRAD, WB_RECT_SORTED, WB_PAIR_MASK,
+    WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE, WB_PAIR_BASE, WB_PAIR_GRAD, WB_RECT_SORTED, WB_PAIR_MASK,
     WB_COUNT
 };
 

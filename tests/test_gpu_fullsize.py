@@ -116,10 +116,7 @@ def run():
                rect=host(plan.buffer(sw.SWGS_BUF_RECT)).reshape(-1, 2),
                splat=host(plan.buffer(sw.SWGS_BUF_SPLAT, torch.float32)).reshape(-1, 12),
                ranges=host(plan.buffer(sw.SWGS_BUF_TILE_RANGE)).reshape(-1, 2),
-               # a sorted pair's value is its record's depth position (slots
-               # past the pair count hold stale values: clipped, never read)
-               pair_rec=np.take(host(plan.buffer(sw.SWGS_BUF_DEPTH_ORDER)), host(plan.buffer(sw.SWGS_BUF_PAIR_VAL)),
-                                mode="clip"))
+               pair_val=host(plan.buffer(sw.SWGS_BUF_PAIR_VAL)))
     say("step done; stats", out["stats"])
     plan.close()
     del dp
@@ -195,7 +192,7 @@ def test_fullsize_tile_lists_and_pixels(run):
             ref = cs[np.lexsort((cs, rec[cs, O.R_DEPTH].astype(np.float32)))]
             t = vi * tx * ty + y * tx + x
             lo, hi = r["ranges"][t]
-            got = slots[r["pair_rec"][lo:hi] - r0]
+            got = slots[r["pair_val"][lo:hi] - r0]
             if (rec[cs, O.R_MARGIN] >= MARGIN_INT).all():
                 assert np.array_equal(got.astype(np.int64), ref), (vi, x, y)
             # pixels of the tile from the Gaussians covering it

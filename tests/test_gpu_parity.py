@@ -158,8 +158,7 @@ def test_sorted_pairs_and_ranges_bit_exact(sw, ctx, tile):
     recs = records_of(sw, pl, pool, views)
     K = int(host(pl.buffer(sw.SWGS_BUF_PAIR_COUNT))[0])
     keys = host(pl.buffer(sw.SWGS_BUF_PAIR_KEY))[:K]
-    # a sorted pair's value is its record's position in the depth order
-    vals = host(pl.buffer(sw.SWGS_BUF_DEPTH_ORDER))[host(pl.buffer(sw.SWGS_BUF_PAIR_VAL))[:K]]
+    vals = host(pl.buffer(sw.SWGS_BUF_PAIR_VAL))[:K]
     ranges = host(pl.buffer(sw.SWGS_BUF_TILE_RANGE)).reshape(-1, 2)
     rvb = host(pl.buffer(sw.SWGS_BUF_RECORD_VIEW_BASE))
     # record -> slot
@@ -206,7 +205,7 @@ def test_dense_tiles_lists_and_pixels(sw, ctx):
     dp, pl = plan_for(sw, ctx, pool, views, tile=(16, 16))
     img = host(pl.forward())
     K = int(host(pl.buffer(sw.SWGS_BUF_PAIR_COUNT))[0])
-    vals = host(pl.buffer(sw.SWGS_BUF_DEPTH_ORDER))[host(pl.buffer(sw.SWGS_BUF_PAIR_VAL))[:K]]
+    vals = host(pl.buffer(sw.SWGS_BUF_PAIR_VAL))[:K]
     ranges = host(pl.buffer(sw.SWGS_BUF_TILE_RANGE)).reshape(-1, 2)
     rvb = host(pl.buffer(sw.SWGS_BUF_RECORD_VIEW_BASE))
     recs = records_of(sw, pl, pool, views)
