@@ -162,7 +162,7 @@ void swgs::compute_layout(const LayoutDims &d, Layout &lay, size_t &consts_bytes
     sz[WB_SSIM_PART] = 9 * P * 4;                     // dS/d(mu_x, E[x^2], E[xy]) per pixel and channel
     sz[WB_SSIM_SUM] = (3 * d.Tssim + 256) * 8;          // per (SSIM tile, channel), then 256 chunk sums
     sz[WB_IMAGE] = 3 * P * 4;                         // renders when the caller passes no image buffer
-    sz[WB_PAIR_BASE] = R * 4;                         // first emission slot of each record
+    sz[WB_PAIR_BASE] = R * 8;                         // each record's slot base and rect width (emission -> backward)
     sz[WB_PAIR_MASK] = (cap + 3) / 4 * 4;             // each pair's support mask over the tile's waves (forward -> backward)
     sz[WB_PAIR_GRAD] = cap * 9 * 4 + 16;              // 9 gradient terms per (tile, record) pair, emission
                                                       // order (+16: the reduce reads whole 16-byte vectors)

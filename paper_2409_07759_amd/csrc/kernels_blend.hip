@@ -384,7 +384,7 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             const float4 *__restrict__ splat, const ViewDev *__restrict__ views,
             int n_views, uint32_t tile_lo, const float *__restrict__ T_final,
             const uint32_t *__restrict__ last_in, const float *__restrict__ dLdC,
-            const uint2 *__restrict__ rect, const uint32_t *__restrict__ pair_base,
+            const uint2 *__restrict__ slot_base,
             const uint8_t *__restrict__ pair_mask, float *__restrict__ pair_grad,
             unsigned long long *__restrict__ counters, uint32_t spread) {
     constexpr int NT = TW * TH;
@@ -445,11 +445,12 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     for (int w = 0; w < NW; ++w) nmax = max(nmax, swlast[w]);
     if (COUNT && threadIdx.x == 0) atomicAdd(counters + 4 * (blockIdx.x % kCounterSlots) + 1, cnt_evals);
     // A pair's slot: the record's first emission slot plus this tile's
-    // row-major index inside the record's tile rect.
+    // row-major index inside the record's tile rect, from the record's
+    // (base, rect width) = (first slot - y0 w - x0, w) as base + ty w + tx
+    // (modulo 2^32).
     auto slot_of = [&](uint32_t r) {
-        const uint2 rc = rect[r];
-        const uint32_t x0 = rc.x & 0xFFFFu, y0 = rc.x >> 16, x1 = rc.y & 0xFFFFu;
-        return pair_base[r] + ((uint32_t)ty - y0) * (x1 - x0) + ((uint32_t)tx - x0);
+        const uint2 sb = slot_base[r];
+        return sb.x + (uint32_t)ty * sb.y + (uint32_t)tx;
     };
     // pairs past every pixel's last contributor get zero terms
     for (uint32_t q = nmax + threadIdx.x; q < rg.y - rg.x; q += NT) {
@@ -726,8 +727,8 @@ void bwd_launch(hipStream_t s, const swgs_plan &p, uint8_t *ws, const float *dLd
                        wsp<uint2>(ws, p, WB_TILE_RANGE), wsp<uint32_t>(ws, p, WB_PAIR_VAL),
                        wsp<float4>(ws, p, WB_SPLAT), wsp<ViewDev>(ws, p, WB_VIEWS),
                        (int)p.views.size(), tile_lo, wsp<float>(ws, p, WB_T_FINAL),
-                       wsp<uint32_t>(ws, p, WB_LAST), dLdC, wsp<uint2>(ws, p, WB_RECT),
-                       wsp<uint32_t>(ws, p, WB_PAIR_BASE), wsp<uint8_t>(ws, p, WB_PAIR_MASK),
+                       wsp<uint32_t>(ws, p, WB_LAST), dLdC, wsp<uint2>(ws, p, WB_PAIR_BASE),
+                       wsp<uint8_t>(ws, p, WB_PAIR_MASK),
                        wsp<float>(ws, p, WB_PAIR_GRAD), counters,
                        p.uneven && tile_hi - tile_lo == (uint32_t)p.T ? spread_multiplier(tile_hi - tile_lo) : 0u);
 }
