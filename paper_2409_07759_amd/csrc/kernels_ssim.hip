@@ -123,8 +123,10 @@ k_ssim_fwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
         for (int u = 0; u < kStageRows; ++u) {
             const int r = wave + kWaves * u, yy = tl.y0 + r - kR;
             const bool row = r < kH && yy >= 0 && yy < V.height;   // wave-uniform
-            const uint32_t o = (row ? (uint32_t)yy : 0u) * (uint32_t)V.width + cx;
-            v[u] = make_float2(col && row ? X[o] : 0.0f, col && row ? Y[o] : 0.0f);
+            // every load in bounds (pixel 0 outside the image), no branch
+            const uint32_t o = col && row ? (uint32_t)yy * (uint32_t)V.width + cx : 0u;
+            const float xv = X[o], yv = Y[o];
+            v[u] = make_float2(col && row ? xv : 0.0f, col && row ? yv : 0.0f);
         }
 #pragma unroll
         for (int u = 0; u < kStageRows; ++u) {
@@ -249,9 +251,13 @@ k_ssim_bwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
         for (int u = 0; u < kStageRows; ++u) {
             const int r = wave + kWaves * u, yy = tl.y0 + r - kR;
             const bool row = r < kH && yy >= 0 && yy < V.height;   // wave-uniform
-            const uint32_t o = (row ? (uint32_t)yy : 0u) * (uint32_t)V.width + cx;
+            // every load in bounds (pixel 0 outside the image), no branch
+            const uint32_t o = col && row ? (uint32_t)yy * (uint32_t)V.width + cx : 0u;
 #pragma unroll
-            for (int m = 0; m < 3; ++m) v[m][u] = col && row ? P[(size_t)m * HW + o] : 0.0f;
+            for (int m = 0; m < 3; ++m) {
+                const float pv = P[(size_t)m * HW + o];
+                v[m][u] = col && row ? pv : 0.0f;
+            }
         }
 #pragma unroll
         for (int u = 0; u < kStageRows; ++u) {
@@ -313,9 +319,11 @@ k_ssim_bwd(const ViewDev *__restrict__ views, int n_views, uint32_t t_lo, const 
     for (int j = 0; j < kSeg; ++j) {
         const int y = tl.y0 + r0 + j;
         const bool in = x < V.width && y < V.height;
-        o[j] = in ? 3 * (size_t)V.pix_base + (size_t)tl.ch * HW + (size_t)y * V.width + x : 0;
-        xi[j] = in ? img[o[j]] : 0.0f;
-        ti[j] = in ? tgt[o[j]] : 0.0f;
+        // (out of the image: the view's first pixel, loaded and not used)
+        o[j] = 3 * (size_t)V.pix_base + (size_t)tl.ch * HW + (in ? (size_t)y * V.width + x : 0);
+        const float xv = img[o[j]], tv = tgt[o[j]];
+        xi[j] = in ? xv : 0.0f;
+        ti[j] = in ? tv : 0.0f;
     }
     float a[kSeg], b[kSeg], g[kSeg];
 #pragma unroll
