@@ -188,7 +188,9 @@ swgs_status swgs_render_forward(swgs_context *ctx, swgs_plan *plan, void *worksp
  * backward): given dL/dimage (device float [3 P], or NULL to use the fused
  * L1 gradient of the forward), writes dL/dparams of the optimisable slots
  * that are live in a frame of the plan into pool->grads (other slots'
- * gradients are not written).  Frozen slots receive nothing.
+ * gradients are not written).  Frozen slots receive nothing.  After a
+ * forward whose pairs overflowed the capacity (stats flag 1) the image
+ * term contributes zero gradients.
  * When add_regulariser != 0 the gradient of
  * lambda_o mean_A sigmoid(logit) + lambda_s mean_A sum_j exp(s_j) is added,
  * with the weights of `cfg` (may be NULL only when add_regulariser == 0). */
@@ -251,7 +253,9 @@ swgs_status swgs_relocate(swgs_context *ctx, swgs_plan *plan, void *workspace, s
  * stats (device double[8]): [0] image term
  * (1/V) sum_v [(1 - l) mean|C - GT| + l (1 - SSIM_v)], [1] MSE, [2] regulariser,
  * [3] total loss, [4] pairs, [5] dead slots relocated, [6] flags: bit 0
- * (value 1) the pair capacity overflowed, bit 1 (value 2) a frame's live
+ * (value 1) the pair capacity overflowed (BATCHED and GRAPH modes: the
+ * step's image term then contributes zero gradients; PLAIN mode fails with
+ * SWGS_ERR_CAPACITY), bit 1 (value 2) a frame's live
  * count differs from the count at plan creation (the lifespans changed, e.g.
  * by mature() or apply_update(): the plan's lists are stale and the step's
  * results are not valid; make a new plan), [7] |A|. */

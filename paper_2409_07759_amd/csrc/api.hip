@@ -162,16 +162,18 @@ void swgs::compute_layout(const LayoutDims &d, Layout &lay, size_t &consts_bytes
     sz[WB_SSIM_PART] = 9 * P * 4;                     // dS/d(mu_x, E[x^2], E[xy]) per pixel and channel
     sz[WB_SSIM_SUM] = (3 * d.Tssim + 256) * 8;          // per (SSIM tile, channel), then 256 chunk sums
     sz[WB_IMAGE] = 3 * P * 4;                         // renders when the caller passes no image buffer
-    sz[WB_PAIR_BASE] = R * 8;                         // each record's slot base and rect width (emission -> backward)
+    sz[WB_PAIR_BASE] = R * 8;                         // each record's slot base and rect width (row scan -> backward)
+    sz[WB_ROW_OFFSET] = (R + 1) * 4;                  // each record's first gradient row (row scan -> reduce)
     sz[WB_PAIR_MASK] = (cap + 3) / 4 * 4;             // each pair's support mask over the tile's waves (forward -> backward)
-    sz[WB_PAIR_GRAD] = cap * 9 * 4 + 16;              // 9 gradient terms per (tile, record) pair, emission
+    sz[WB_PAIR_GRAD] = cap * 9 * 4 + 16;              // 9 gradient terms per (tile, record) pair, record
                                                       // order (+16: the reduce reads whole 16-byte vectors)
     if (d.forward_only) {
         // serving: no gating (the live lists are resident), no gradients,
         // no loss, no step
         for (int b : {WB_ACTIVE_LIST, WB_GATE_BLK, WB_POS_OF, WB_DLDC, WB_REC_GRAD, WB_LOSS_PART, WB_RELOC_W,
                       WB_RELOC_FLAG, WB_RELOC_CNT, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_SCAN, WB_REG_PART,
-                      WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE, WB_PAIR_BASE, WB_PAIR_GRAD, WB_PAIR_MASK})
+                      WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE, WB_PAIR_BASE, WB_PAIR_GRAD, WB_PAIR_MASK,
+                      WB_ROW_OFFSET})
             sz[b] = 0;
         if (d.own_lists) {
             // a standalone batch render gates into its workspace (no
@@ -290,6 +292,7 @@ void seq_forward(hipStream_t s, swgs_plan &p, uint8_t *ws, int view, float *imag
                          wsp<uint2>(ws, p, WB_RECT_SORTED), wsp<uint32_t>(ws, p, WB_PAIR_OFFSET));
         launch_pair_offsets(s, p, ws, rec_lo, rec_hi);
         launch_emit_pairs(s, p, ws, rec_lo, rec_hi);
+        launch_row_offsets(s, p, ws, rec_lo, rec_hi);
         uint32_t *pc = wsp<uint32_t>(ws, p, WB_PAIR_COUNT);
         radix_sort_pairs(s, wsp<uint32_t>(ws, p, WB_PAIR_KEY), wsp<uint32_t>(ws, p, WB_PAIR_VAL),
                          wsp<uint32_t>(ws, p, WB_PAIR_KEY_ALT), wsp<uint32_t>(ws, p, WB_PAIR_VAL_ALT), pc, 0,

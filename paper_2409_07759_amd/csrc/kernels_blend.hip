@@ -26,8 +26,10 @@
 // Per-splat gradient terms are summed over each wave with lane swaps and
 // DPP steps, the wave partials are combined per batch through LDS in wave
 // order, and each pair's nine terms are stored as one row at the pair's
-// emission slot; an ordered per-record reduce then sums a record's rows in
-// slot order.  No float atomics: gradients are bit-reproducible.
+// gradient row (a record's rows consecutive, row-major over its tile rect,
+// records in record order); an ordered per-record reduce then sums a
+// record's rows in row order.  No float atomics: gradients are
+// bit-reproducible.
 #include "swgs_internal.h"
 
 namespace swgs {
@@ -384,7 +386,7 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             const float4 *__restrict__ splat, const ViewDev *__restrict__ views,
             int n_views, uint32_t tile_lo, const float *__restrict__ T_final,
             const uint32_t *__restrict__ last_in, const float *__restrict__ dLdC,
-            const uint2 *__restrict__ slot_base,
+            const uint2 *__restrict__ slot_base, const uint32_t *__restrict__ pair_count,
             const uint8_t *__restrict__ pair_mask, float *__restrict__ pair_grad,
             unsigned long long *__restrict__ counters, uint32_t spread) {
     constexpr int NT = TW * TH;
@@ -395,10 +397,13 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     __shared__ float4 sa[BB], sb[BB], sc[BB];
     __shared__ uint32_t smask[BB];
     __shared__ uint16_t slist[CULL ? NW : 1][CULL ? BB : 1];
-    __shared__ uint32_t sslot[BB];        // emission slot of each batch pair
+    __shared__ uint32_t sslot[BB];        // gradient row of each batch pair
     __shared__ float4 part[BB][NW][kTerm / 4];
     __shared__ uint32_t swlast[NW];
     __shared__ unsigned long long cnt_evals;
+    // after a pair overflow some of the listed pairs' rows lie past the
+    // capacity: nothing is stored (the reduce then writes zero gradients)
+    if (pair_count[1] != 0) return;
     // neighbouring tiles share an XCD's L2; a window of uneven views is
     // spread over the XCDs in chunks of tiles
     const uint32_t lt_idx = xcd_spread(xcd_order(blockIdx.x, gridDim.x), gridDim.x, spread);
@@ -444,9 +449,9 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
 #pragma unroll
     for (int w = 0; w < NW; ++w) nmax = max(nmax, swlast[w]);
     if (COUNT && threadIdx.x == 0) atomicAdd(counters + 4 * (blockIdx.x % kCounterSlots) + 1, cnt_evals);
-    // A pair's slot: the record's first emission slot plus this tile's
+    // A pair's gradient row: the record's first row plus this tile's
     // row-major index inside the record's tile rect, from the record's
-    // (base, rect width) = (first slot - y0 w - x0, w) as base + ty w + tx
+    // (base, rect width) = (first row - y0 w - x0, w) as base + ty w + tx
     // (modulo 2^32).
     auto slot_of = [&](uint32_t r) {
         const uint2 sb = slot_base[r];
@@ -530,8 +535,8 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         __syncthreads();
         // flush: one thread per (splat, term group) sums the group's row
         // partials over the waves whose block the splat reaches (in wave
-        // order) and stores its terms of the pair's 36-byte row
-        // d/d(u, v, A, B, C, o, r, g, b) at the pair's emission slot, conic
+        // order) and stores its terms of the pair's 36-byte gradient row
+        // d/d(u, v, A, B, C, o, r, g, b), conic
         // unscaled (A = -2 A' ln2, B = -B' ln2, C = -2 C' ln2): no atomics,
         // and a fixed summation order.  Groups: 0 colour 3 + opacity,
         // 1 conic terms 3 (+ offset x), 2 offset y (four rows) with offset x.
@@ -626,23 +631,24 @@ k_loss_final(const double *__restrict__ sums, double inv_3p, double *__restrict_
     }
 }
 
-// Record gradients: each record's nine terms summed over its emission
-// slots in slot order (deterministic).  A block takes kReduceRecs records
-// in depth order, the order their slots were emitted in, so their terms
-// form one contiguous stretch: it is staged through LDS with 16-byte loads
-// (kReduceChunk pairs at a time, from the 16-byte boundary at or below its
-// start), then nine lanes per record (lane t summing term t) add their
-// record's rows, seven records per wave and round, and store each record's
-// sums as one 36-byte row.
+// Record gradients: each record's nine terms summed over its gradient rows
+// in row order (deterministic).  A record's rows are consecutive and the
+// records' rows follow record order, so the kReduceRecs consecutive records
+// of a block own one contiguous stretch of rows: it is staged through LDS
+// with 16-byte loads (kReduceChunk rows at a time, from the 16-byte boundary
+// at or below its start), then nine lanes per record (lane t summing term t)
+// add their record's rows, seven records per wave and round, and store each
+// record's sums as one 36-byte row (the block's records: one contiguous
+// stretch of sums).  After a pair overflow the rows are incomplete, and
+// every record's sums are zero.
 constexpr int kReduceRounds = 8;
 constexpr int kReduceRecs = 4 * 7 * kReduceRounds;   // 4 waves
-constexpr int kReduceChunk = 512;                    // pairs per LDS stage (18 KB: 8 blocks per CU)
+constexpr int kReduceChunk = 512;                    // rows per LDS stage (18 KB: 8 blocks per CU)
 constexpr int kReduceVec = (9 * kReduceChunk + 3) / 4 + 1;
 
 __global__ void __launch_bounds__(256, 8)
-k_pair_grad_reduce(const uint32_t *__restrict__ order, const uint32_t *__restrict__ offsets,
-                   const uint32_t *__restrict__ pair_count, const float *__restrict__ pair_grad, uint32_t cap,
-                   uint32_t n, float *__restrict__ rec_grad) {
+k_pair_grad_reduce(const uint32_t *__restrict__ first_row, const uint32_t *__restrict__ pair_count,
+                   const float *__restrict__ pair_grad, uint32_t cap, uint32_t n, float *__restrict__ rec_grad) {
     __shared__ float4 buf4[kReduceVec];
     __shared__ uint32_t bound[kReduceRecs + 1];
     const float *buf = reinterpret_cast<const float *>(buf4);
@@ -651,14 +657,10 @@ k_pair_grad_reduce(const uint32_t *__restrict__ order, const uint32_t *__restric
     const uint32_t j0 = blockIdx.x * kReduceRecs;
     const uint32_t nb = min((uint32_t)kReduceRecs, n - j0);
     const uint32_t total = pair_count[0];
-    // record boundaries; slots at or past the capacity were never emitted
-    for (uint32_t x = threadIdx.x; x <= nb; x += 256) bound[x] = min(j0 + x < n ? offsets[j0 + x] : total, cap);
-    uint32_t rec[kReduceRounds];
-#pragma unroll
-    for (int q = 0; q < kReduceRounds; ++q) {
-        const uint32_t jj = (uint32_t)(7 * (kReduceRounds * wave + q) + g);
-        rec[q] = (g < 7 && jj < nb) ? order[j0 + jj] : 0u;
-    }
+    const bool overflow = pair_count[1] != 0;
+    // record boundaries (all empty after an overflow)
+    for (uint32_t x = threadIdx.x; x <= nb; x += 256)
+        bound[x] = overflow ? 0u : min(j0 + x < n ? first_row[j0 + x] : total, cap);
     __syncthreads();
     const uint32_t lo = bound[0], hi = bound[nb];
     float acc[kReduceRounds];
@@ -685,7 +687,7 @@ k_pair_grad_reduce(const uint32_t *__restrict__ order, const uint32_t *__restric
             const uint32_t jj = (uint32_t)(7 * (kReduceRounds * wave + q) + g);
             if (g < 7 && jj < nb) {
                 const uint32_t s0 = max(bound[jj], base), s1 = min(bound[jj + 1], base + cnt);
-                // rows added in slot order, four reads in flight at a time
+                // rows added in row order, four reads in flight at a time
                 const float *row = buf + shift + 9 * (s0 - base) + t;
                 uint32_t i = s0;
                 for (; i + 4 <= s1; i += 4, row += 36) {
@@ -700,7 +702,7 @@ k_pair_grad_reduce(const uint32_t *__restrict__ order, const uint32_t *__restric
 #pragma unroll
     for (int q = 0; q < kReduceRounds; ++q) {
         const uint32_t jj = (uint32_t)(7 * (kReduceRounds * wave + q) + g);
-        if (g < 7 && jj < nb) rec_grad[9 * (size_t)rec[q] + t] = acc[q];
+        if (g < 7 && jj < nb) rec_grad[9 * (size_t)(j0 + jj) + t] = acc[q];
     }
 }
 
@@ -728,7 +730,7 @@ void bwd_launch(hipStream_t s, const swgs_plan &p, uint8_t *ws, const float *dLd
                        wsp<float4>(ws, p, WB_SPLAT), wsp<ViewDev>(ws, p, WB_VIEWS),
                        (int)p.views.size(), tile_lo, wsp<float>(ws, p, WB_T_FINAL),
                        wsp<uint32_t>(ws, p, WB_LAST), dLdC, wsp<uint2>(ws, p, WB_PAIR_BASE),
-                       wsp<uint8_t>(ws, p, WB_PAIR_MASK),
+                       wsp<uint32_t>(ws, p, WB_PAIR_COUNT), wsp<uint8_t>(ws, p, WB_PAIR_MASK),
                        wsp<float>(ws, p, WB_PAIR_GRAD), counters,
                        p.uneven && tile_hi - tile_lo == (uint32_t)p.T ? spread_multiplier(tile_hi - tile_lo) : 0u);
 }
@@ -773,14 +775,14 @@ void launch_loss_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, const sw
 }
 
 void launch_pair_grad_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi) {
-    // depth-sorted positions [rec_lo, rec_hi), their emission offsets and
-    // the emitted total of the same range
+    // records [rec_lo, rec_hi), their first gradient rows and the pair
+    // total of the same range
     if (rec_hi <= rec_lo) return;
     const uint32_t n = rec_hi - rec_lo;
     hipLaunchKernelGGL(k_pair_grad_reduce, dim3((n + kReduceRecs - 1) / kReduceRecs), dim3(256), 0, s,
-                       wsp<uint32_t>(ws, p, WB_REC_IDX) + rec_lo, wsp<uint32_t>(ws, p, WB_PAIR_OFFSET),
-                       wsp<uint32_t>(ws, p, WB_PAIR_COUNT), wsp<float>(ws, p, WB_PAIR_GRAD), (uint32_t)p.pair_cap, n,
-                       wsp<float>(ws, p, WB_REC_GRAD));
+                       wsp<uint32_t>(ws, p, WB_ROW_OFFSET) + rec_lo, wsp<uint32_t>(ws, p, WB_PAIR_COUNT),
+                       wsp<float>(ws, p, WB_PAIR_GRAD), (uint32_t)p.pair_cap, n,
+                       wsp<float>(ws, p, WB_REC_GRAD) + 9 * (size_t)rec_lo);
 }
 
 }  // namespace swgs

@@ -254,8 +254,7 @@ __global__ void __launch_bounds__(kBlock)
 k_emit_pairs(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict__ offsets,
              const uint32_t *__restrict__ total_ptr, const uint2 *__restrict__ rect_sorted,
              const uint32_t *__restrict__ rec_view_base, int n_views, const ViewDev *__restrict__ views,
-             uint32_t n, uint32_t cap, uint32_t *__restrict__ pair_key, uint32_t *__restrict__ pair_val,
-             uint2 *__restrict__ slot_base) {
+             uint32_t n, uint32_t cap, uint32_t *__restrict__ pair_key, uint32_t *__restrict__ pair_val) {
     const int lane = threadIdx.x & 63;
     const uint32_t j0 = blockIdx.x * kBlock + (threadIdx.x & ~63u);   // the wave's first record
     if (j0 >= n) return;                                                 // whole waves only
@@ -278,11 +277,6 @@ k_emit_pairs(const uint32_t *__restrict__ sorted_rec, const uint32_t *__restrict
         const uint2 rc = rect_sorted[j];
         xy0 = rc.x;
         w = max((rc.y & 0xFFFFu) - (rc.x & 0xFFFFu), 1u);
-        // the record's pairs take slots off .. off + count - 1: the pair of
-        // tile (tx, ty) is at off + (ty - y0) w + (tx - x0) = base + ty w +
-        // tx, base = off - y0 w - x0 in modulo-2^32 arithmetic (the
-        // backward's one lookup per pair)
-        if (slot_base) slot_base[r] = make_uint2(off - (rc.x >> 16) * w - (rc.x & 0xFFFFu), w);
     }
     const uint32_t start = __shfl(off, 0, 64);
     for (uint32_t base = start; base < end; base += 64) {   // uniform trip count: all lanes shuffle
@@ -400,8 +394,22 @@ void launch_emit_pairs(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t 
                        wsp<uint32_t>(ws, p, WB_PAIR_COUNT) + 2, wsp<uint2>(ws, p, WB_RECT_SORTED),
                        wsp<uint32_t>(ws, p, WB_REC_VIEW_BASE), (int)p.views.size(), wsp<ViewDev>(ws, p, WB_VIEWS),
                        n, (uint32_t)p.pair_cap, wsp<uint32_t>(ws, p, alt ? WB_PAIR_KEY_ALT : WB_PAIR_KEY),
-                       wsp<uint32_t>(ws, p, alt ? WB_PAIR_VAL_ALT : WB_PAIR_VAL),
-                       p.forward_only ? nullptr : wsp<uint2>(ws, p, WB_PAIR_BASE));
+                       wsp<uint32_t>(ws, p, alt ? WB_PAIR_VAL_ALT : WB_PAIR_VAL));
+}
+
+void launch_row_offsets(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi) {
+    // The backward stores a pair's nine gradient terms as one row, and a
+    // record's rows are consecutive, row-major over its tile rect, with the
+    // records' rows in record order: a record's first row is the exclusive
+    // scan of the tile counts in record order, so the per-record reduce
+    // reads and writes contiguous memory.  The pair of tile (tx, ty) is at
+    // row first + (ty - y0) w + (tx - x0) = base + ty w + tx, base = first -
+    // y0 w - x0 in modulo-2^32 arithmetic: the backward's one lookup per
+    // pair.
+    if (rec_hi <= rec_lo || p.forward_only) return;
+    exclusive_scan_rows(s, wsp<uint32_t>(ws, p, WB_TILE_COUNT) + rec_lo, wsp<uint2>(ws, p, WB_RECT) + rec_lo,
+                        rec_hi - rec_lo, wsp<uint32_t>(ws, p, WB_ROW_OFFSET) + rec_lo,
+                        wsp<uint2>(ws, p, WB_PAIR_BASE) + rec_lo, wsp<uint32_t>(ws, p, WB_SORT_TOTAL));
 }
 
 void launch_tile_ranges(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t tile_lo, uint32_t tile_hi) {

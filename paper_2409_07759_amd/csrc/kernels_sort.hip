@@ -284,9 +284,12 @@ k_scan_sums(uint32_t *__restrict__ sums, uint32_t nb, uint32_t *__restrict__ tot
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
+// with slot_base, element i is a record's tile count: its first row r goes
+// to out[i] and (r - y0 w - x0, w) of its rect (rect[i]) to slot_base[i]
 __global__ void __launch_bounds__(kBlock)
 k_scan_write(const uint32_t *in, const uint32_t *__restrict__ idx, uint32_t n,
-             const uint32_t *__restrict__ sums, uint32_t *out) {   // in may equal out (in-place scan)
+             const uint32_t *__restrict__ sums, uint32_t *out,   // in may equal out (in-place scan)
+             const uint2 *__restrict__ rect, uint2 *__restrict__ slot_base) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __shared__ uint32_t wsum[kWaves];
     uint32_t carry = sums[blockIdx.x];
@@ -304,6 +307,11 @@ k_scan_write(const uint32_t *in, const uint32_t *__restrict__ idx, uint32_t n,
         uint32_t before = carry;
         for (int w = 0; w < wave; ++w) before += wsum[w];
         if (i < n) out[i] = before + x - v;
+        if (slot_base && i < n) {
+            const uint2 rc = rect[i];
+            const uint32_t w = max((rc.y & 0xFFFFu) - (rc.x & 0xFFFFu), 1u);
+            slot_base[i] = make_uint2(before + x - v - (rc.x >> 16) * w - (rc.x & 0xFFFFu), w);
+        }
         uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
         __syncthreads();
         carry += tot;
@@ -362,7 +370,17 @@ void exclusive_scan_u32(hipStream_t s, const uint32_t *in, uint32_t *out, uint32
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, in, (const uint32_t *)nullptr, n, scratch);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, scratch, nb, total_out);
     hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(kBlock), 0, s, in, (const uint32_t *)nullptr, n, scratch,
-                       out);
+                       out, (const uint2 *)nullptr, (uint2 *)nullptr);
+}
+
+void exclusive_scan_rows(hipStream_t s, const uint32_t *count, const uint2 *rect, uint32_t n, uint32_t *first,
+                         uint2 *slot_base, uint32_t *scratch) {
+    const uint32_t nb = (n + kScanChunk - 1) / kScanChunk;
+    if (nb == 0) return;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, count, (const uint32_t *)nullptr, n, scratch);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, scratch, nb, (uint32_t *)nullptr);
+    hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(kBlock), 0, s, count, (const uint32_t *)nullptr, n, scratch,
+                       first, rect, slot_base);
 }
 
 

@@ -113,7 +113,7 @@ enum WsBuf {
     WB_VIEWS, WB_GROUPS, WB_GROUP_VIEWS,
     WB_RELOC_W, WB_RELOC_FLAG, WB_RELOC_SRC, WB_RELOC_DST, WB_RELOC_CNT, WB_RELOC_SCAN, WB_REG_PART, WB_COUNTERS, WB_CFLAGS,
     WB_SSIM_PART, WB_SSIM_SUM, WB_IMAGE, WB_PAIR_BASE, WB_PAIR_GRAD, WB_RECT_SORTED, WB_PAIR_MASK,
-    WB_COUNT
+    WB_ROW_OFFSET, WB_COUNT
 };
 
 }  // namespace swgs
@@ -179,6 +179,9 @@ void launch_count_live(hipStream_t s, const int32_t *start, const int32_t *expir
 void launch_preprocess(hipStream_t s, const swgs_plan &p, uint8_t *ws, int view_lo, int view_hi);
 void launch_pair_offsets(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi);
 void launch_emit_pairs(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi);
+// gradient-row layout of records [rec_lo, rec_hi) for the backward: each
+// record's first row (record order) and slot base
+void launch_row_offsets(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi);
 void launch_tile_ranges(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t tile_lo, uint32_t tile_hi);
 
 // Radix sort (kernels_sort.hip): stable LSD sort of (key, val) uint32 pairs,
@@ -199,6 +202,11 @@ void radix_sort_pairs(hipStream_t s, uint32_t *keys, uint32_t *vals, uint32_t *k
 // exclusive scan (in may equal out); *total_out = sum
 void exclusive_scan_u32(hipStream_t s, const uint32_t *in, uint32_t *out, uint32_t n,
                         uint32_t *total_out, uint32_t *scratch);
+// exclusive scan of tile counts into first rows, also writing, per element,
+// (first row - y0 w - x0, w) of its tile rect (packed as in the binning) to
+// slot_base (w = the rect's width, at least 1)
+void exclusive_scan_rows(hipStream_t s, const uint32_t *count, const uint2 *rect, uint32_t n, uint32_t *first,
+                         uint2 *slot_base, uint32_t *scratch);
 
 // Blend (kernels_blend.hip)
 // counters (nullable): [0] pixel x list entries evaluated by the forward,

@@ -746,6 +746,13 @@ def test_pair_capacity_overflow_is_reported(sw, ctx):
     pl.forward(stats=stats)
     st = host(stats)
     assert st[6] == 1.0 and st[4] > 1000
+    # the image term of an overflowed render contributes zero gradients
+    # (the pairs past the capacity were never listed), never stale rows
+    dp.grads.fill_(float("nan"))
+    pl.backward(torch.ones(3 * pl.n_pixels, dtype=torch.float32, device="cuda"))
+    g = dp.grads.cpu().numpy()
+    written = ~np.isnan(g)
+    assert written.any() and np.all(g[written] == 0.0)
     tgt = torch.as_tensor(S.random_images(views, 1), device="cuda")
     with pytest.raises(sw.SwgsError) as e:
         pl.window_step(sw.step_cfg(mode=sw.SWGS_MODE_PLAIN), tgt, 1, 0, 0)
