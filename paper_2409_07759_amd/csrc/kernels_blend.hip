@@ -23,9 +23,13 @@
 // and keeping W, the colour behind the splat including the background seen
 // through it (W <- c alpha + (1 - alpha) W from W = bg), so that
 //     dC/dalpha_k = T_k (c_k - W_k).
-// Per-splat gradient terms are summed over each wave with lane swaps and
-// DPP steps, the wave partials are combined per batch through LDS in wave
-// order, and each pair's nine terms are stored as one row at the pair's
+// Each wave takes its splats eight at a time in two phases: with a lane per
+// pixel it runs the recurrence and leaves two values per (splat, pixel) in
+// LDS, then with a lane per (pixel row, splat) it sums them along the row
+// into the splat's nine gradient terms (closed forms in the pixel's column
+// offset) and adds the eight rows by lane swaps and a DPP step.  The wave
+// partials are combined per batch through LDS in wave order, and each
+// pair's nine terms are stored as one row at the pair's
 // gradient row (a record's rows consecutive, row-major over its tile rect,
 // records in record order); an ordered per-record reduce then sums a
 // record's rows in row order.  No float atomics: gradients are
@@ -98,23 +102,6 @@ __device__ __forceinline__ float xswap32(float a, float c) {
 __device__ __forceinline__ float xswap16(float a, float c) {
     const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(c), false, false);
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-
-// Wave sums of eight values at once (a transposed reduction): the half and
-// row-pair swaps leave row r of x0 / x1 holding values (0, 2, 1, 3)[r] /
-// (4, 6, 5, 7)[r], each summed over 4 lanes; an xor-1 exchange puts x0's
-// value on even lanes and x1's on odd ones, and xor-2, rotate-4 and
-// rotate-8 adds finish the sums.  Lane l then holds the wave sum of value
-// 4 (l & 1) + brev2(l >> 4), brev2 = (0, 2, 1, 3); 18 VALU operations.
-__device__ __forceinline__ float wave_sum_x8(float v0, float v1, float v2, float v3, float v4, float v5,
-                                             float v6, float v7, int lane) {
-    const float w0 = xswap32(v0, v1), w1 = xswap32(v2, v3), w2 = xswap32(v4, v5), w3 = xswap32(v6, v7);
-    const float x0 = xswap16(w0, w1), x1 = xswap16(w2, w3);
-    float y = xstep<0xB1>(x0, x1, lane & 1);
-    y += dpp_f<0x4E, 0xf>(y);    // quad_perm [2,3,0,1]
-    y += dpp_f<0x124, 0xf>(y);   // row_ror:4
-    y += dpp_f<0x128, 0xf>(y);   // row_ror:8
-    return y;
 }
 
 // max over the 16 lanes of each DPP row; every lane of a row holds it
@@ -374,14 +361,49 @@ k_blend_fwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     }
 }
 
-// Backward batches are BB splats; per splat each wave reduces eight of its
-// gradient terms over the whole wave and the ninth to one value per 16-lane
-// row, and twelve lanes store them to LDS: floats 0-7 the terms (colour 3,
-// opacity, conic 3, offset x), 8-11 the row sums of the offset-y term.
-constexpr int kTerm = 12;                 // 9 terms padded to 3 x float4
+// Backward batches are BB splats; each wave stores, per splat of its list,
+// its partial sums of the nine gradient terms to LDS: floats 0-8 colour 3,
+// opacity, conic 3 (dx^2, dx dy, dy^2 products), offset x, offset y.
+constexpr int kTerm = 9;
+constexpr int kSub = 8;                   // splats per sub-batch (phase A -> phase B)
+constexpr int kPitch = 65;                // float2 per (sub-batch splat) row: 64 pixels + 1 (bank spread)
+
+// 3-bit reversal: the term a phase-B lane of pixel row r holds after the
+// row reduction
+__device__ __forceinline__ int brev3(int r) { return ((r & 1) << 2) | (r & 2) | ((r >> 2) & 1); }
+
+// Phase-B step over column i of a pixel row: (w, m') of the lane's splat
+// at pixel (r, i), that pixel's dL/dC from phase-A lane 8 r + i by a
+// swizzle inside each 32-lane half (lane (l & 24) | i), and the row sums
+// of g.w and of m', i' m', i'^2 m' (i' = i - 3.5)
+template <int I>
+__device__ __forceinline__ float swz_col(float v) {
+    return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 24 | (I << 5)));
+}
+template <int I>
+__device__ __forceinline__ void row_step(const float2 *prow, float g0, float g1, float g2, float &C0, float &C1,
+                                         float &C2, float &S0, float &S1, float &S2) {
+    constexpr float c = (float)I - 3.5f;
+    const float2 pm = prow[I];
+    C0 = fmaf(swz_col<I>(g0), pm.x, C0);
+    C1 = fmaf(swz_col<I>(g1), pm.x, C1);
+    C2 = fmaf(swz_col<I>(g2), pm.x, C2);
+    S0 += pm.y;
+    S1 = fmaf(c, pm.y, S1);
+    S2 = fmaf(c * c, pm.y, S2);
+}
+
+// orders one wave's LDS accesses across its lanes (stores before the
+// following loads, loads before the following stores): the compiler keeps
+// them on their side, and the LDS carries out one wave's accesses in order
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <int TW, int TH, int BATCH, bool COUNT>
-__global__ void __launch_bounds__(TW *TH)
+__global__ void __launch_bounds__(TW *TH, TW *TH >= 256 ? 6 : 1)
 k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_val,
             const float4 *__restrict__ splat, const ViewDev *__restrict__ views,
             int n_views, uint32_t tile_lo, const float *__restrict__ T_final,
@@ -392,13 +414,14 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     constexpr int NT = TW * TH;
     static_assert(64 % TW == 0 && 64 % TH == 0, "a tile lies inside one 64x64-aligned block");
     constexpr int NW = NT / 64;           // waves
-    constexpr int BB = 64;                // splats per LDS batch (partials: BB x NW x 48 B)
+    constexpr int BB = 48;                // splats per LDS batch (26 KB of LDS per 16x16 block: 6 per CU)
     constexpr bool CULL = NW > 1;
     __shared__ float4 sa[BB], sb[BB], sc[BB];
     __shared__ uint32_t smask[BB];
     __shared__ uint16_t slist[CULL ? NW : 1][CULL ? BB : 1];
     __shared__ uint32_t sslot[BB];        // gradient row of each batch pair
-    __shared__ float4 part[BB][NW][kTerm / 4];
+    __shared__ float part[BB][NW][kTerm];
+    __shared__ float2 pbuf[NW][kSub][kPitch];   // phase A -> B: (w, m') per (sub-batch splat, pixel)
     __shared__ uint32_t swlast[NW];
     __shared__ unsigned long long cnt_evals;
     // after a pair overflow some of the listed pairs' rows lie past the
@@ -435,6 +458,7 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         g1 = dl1[o];
         g2 = dl2[o];
     }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // a wave never needs splats at or beyond its pixels' largest `last`;
     // the tile's largest is the largest of its waves'
     const uint32_t wlast = wave_max_u32(lst);
@@ -470,10 +494,12 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     // = dL/dC of the pixel; only gW = g.W is needed, and it follows the same
     // recurrence: gW <- gW + a (g.c - gW).
     float gW = g0 * V.bg[0] + g1 * V.bg[1] + g2 * V.bg[2];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int r16 = lane & 15;
-    // store slot of this lane's reduced value (lanes 0-2 of each row)
-    const int pslot = r16 < 2 ? 4 * r16 + (((lane >> 4) & 1) << 1 | (lane >> 5)) : 8 + (lane >> 4);
+    // phase B: lane (r, s) takes pixel row r of the wave's 8x8 block (pixels
+    // r, columns 0-7: lanes 8 r .. 8 r + 7 of phase A) and sub-batch splat
+    // s; (bx + i, byr) are the row's pixels inside the 64x64-aligned block
+    const int sB = lane & 7, rB = lane >> 3;
+    const float bx = (float)((tx * TW + (wave % (TW / 8)) * 8) & 63);
+    const float byr = (float)(((ty * TH + (wave / (TW / 8)) * 8) & 63) + rB);
 
     for (uint32_t b_end = nmax; b_end > 0;) {
         const uint32_t b_start = b_end > (uint32_t)BB ? b_end - BB : 0;
@@ -494,43 +520,76 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         // entries of this batch before the pixel's last contributor, as a
         // byte-offset bound (entry k is before it iff 16 k < lim)
         const int lim = 16 * ((int)min(lst, b_end) - (int)min(lst, b_start));
-        for (int i = cnt - 1; i >= 0; --i) {
-            const int off = CULL ? (int)slist[CULL ? wave : 0][i] : 16 * i;
-            // contrib = the forward blended this splat here
-            const Px e = eval_splat(lxf, lyf, at16(sa, off), at16(sb, off));
-            const float alpha = fminf(0.99f, e.og);
-            const bool contrib = off < lim && alpha >= (1.0f / 255.0f);
-            // this lane's partial slot of the entry (off = 16 x entry index)
-            float *pdst = reinterpret_cast<float *>(reinterpret_cast<char *>(&part[0][wave][0]) +
-                                                    off * (NW * kTerm / 4)) + pslot;
-            // T and W change only where the splat was blended: a wave with
-            // no such pixel skips the gradient (branch-free inside) and
-            // stores zero partials
-            float part_out = 0.0f;
-            if (__ballot(contrib) != 0) {
-                const float ri = __builtin_amdgcn_rcpf(1.0f - alpha);
-                const float Tk = T * ri;                                     // transmittance in front of k
-                const float4 c = at16(sc, off);
-                const float diff = fmaf(g2, c.z, fmaf(g1, c.y, g0 * c.x)) - gW;
-                const float da = Tk * diff;                                  // dL/dalpha
-                const float ac = contrib ? alpha : 0.0f;
-                const float w = ac * Tk;
-                float v0 = g0 * w, v1 = g1 * w, v2 = g2 * w;
-                // alpha = o g, g = exp(-Q/2): dL/do = g da and dL/dQ =
-                // -o g da / 2, both zero where alpha is clamped; the
-                // partials carry q = -2 dL/dQ (the flush applies -1/2)
-                const float m = (contrib && e.og < 0.99f) ? da : 0.0f;
-                float v3 = e.g * m;
-                const float q = e.og * m;
-                float v7 = q * e.dx, v8 = q * e.dy;
-                float v4 = v7 * e.dx, v5 = v7 * e.dy, v6 = v8 * e.dy;
-                T = contrib ? Tk : T;
-                gW = fmaf(ac, diff, gW);                                     // a = 0 keeps gW
-                const float y = wave_sum_x8(v0, v1, v2, v3, v4, v5, v6, v7, lane);
-                const float s8 = row_sum16(v8);
-                part_out = r16 < 2 ? y : s8;
+        for (int i0 = cnt - 1; i0 >= 0; i0 -= kSub) {
+            const int nsb = min(kSub, i0 + 1);
+            // phase B's splat: entry i0 - s (lanes past the sub-batch take
+            // any entry and store nothing); read before phase A
+            const int ie = max(i0 - sB, 0);
+            const int offs = CULL ? (int)slist[CULL ? wave : 0][ie] : 16 * ie;
+            const float4 as = at16(sa, offs);
+            const float os = at16(sb, offs).w;
+            // phase A, lane = pixel, entries i0, i0 - 1, ... (back to front)
+            // into sub-batch slots 0, 1, ...: the colour weight w = alpha
+            // T_k and m' = g dL/dalpha (g = exp(-Q/2); zero where alpha is
+            // clamped), both zero where the splat was not blended here
+            for (int j = 0; j < nsb; ++j) {
+                const int off = CULL ? (int)slist[CULL ? wave : 0][i0 - j] : 16 * (i0 - j);
+                // contrib = the forward blended this splat here
+                const Px e = eval_splat(lxf, lyf, at16(sa, off), at16(sb, off));
+                const float alpha = fminf(0.99f, e.og);
+                const bool contrib = off < lim && alpha >= (1.0f / 255.0f);
+                // T and W change only where the splat was blended: a wave
+                // with no such pixel skips the recurrence (branch-free inside)
+                float wv = 0.0f, mp = 0.0f;
+                if (__ballot(contrib) != 0) {
+                    const float ri = __builtin_amdgcn_rcpf(1.0f - alpha);
+                    const float Tk = T * ri;                                 // transmittance in front of k
+                    const float4 c = at16(sc, off);
+                    const float diff = fmaf(g2, c.z, fmaf(g1, c.y, g0 * c.x)) - gW;
+                    const float ac = contrib ? alpha : 0.0f;
+                    wv = ac * Tk;
+                    // alpha = o g: dL/do = g dL/dalpha, dL/dQ = -o g dL/dalpha / 2
+                    mp = (contrib && e.og < 0.99f) ? e.g * (Tk * diff) : 0.0f;
+                    T = contrib ? Tk : T;
+                    gW = fmaf(ac, diff, gW);                                 // a = 0 keeps gW
+                }
+                pbuf[wave][j][lane] = make_float2(wv, mp);
             }
-            if (r16 < 3) *pdst = part_out;
+            wave_lds_sync();
+            // phase B: row sums of g.w (colour) and of m', i' m', i'^2 m'
+            // (i' = i - 3.5, the column's offset from the row centre); with
+            // dx = d0 + i' and dy constant along the row, the partials of
+            // q = o m' (= -2 dL/dQ) follow: sum q dx = o (d0 S0 + S1), sum q
+            // dx^2 = o (d0^2 S0 + 2 d0 S1 + S2), and dy factors out
+            float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;
+            const float2 *prow = &pbuf[CULL ? wave : 0][sB][8 * rB];
+            row_step<0>(prow, g0, g1, g2, C0, C1, C2, S0, S1, S2);
+            row_step<1>(prow, g0, g1, g2, C0, C1, C2, S0, S1, S2);
+            row_step<2>(prow, g0, g1, g2, C0, C1, C2, S0, S1, S2);
+            row_step<3>(prow, g0, g1, g2, C0, C1, C2, S0, S1, S2);
+            row_step<4>(prow, g0, g1, g2, C0, C1, C2, S0, S1, S2);
+            row_step<5>(prow, g0, g1, g2, C0, C1, C2, S0, S1, S2);
+            row_step<6>(prow, g0, g1, g2, C0, C1, C2, S0, S1, S2);
+            row_step<7>(prow, g0, g1, g2, C0, C1, C2, S0, S1, S2);
+            wave_lds_sync();
+            const float d0 = (bx + 3.5f) + as.x, dy = byr + as.y;
+            const float Q0 = os * S0, Qx = os * fmaf(d0, S0, S1);
+            const float Qxx = os * fmaf(d0, fmaf(d0, S0, 2.0f * S1), S2);
+            const float Qy = Q0 * dy;
+            // the eight rows of each splat added: lane swaps across halves
+            // and row pairs, then a DPP exchange inside rows; lane (r, s)
+            // ends with term brev3(r) of splat s and every lane with the
+            // offset-y term
+            const float b0 = xswap32(C0, C1), b1 = xswap32(C2, S0), b2 = xswap32(Qxx, Qx * dy);
+            const float b3 = xswap32(Qy * dy, Qx), b4 = xswap32(Qy, Qy);
+            const float c0 = xswap16(b0, b1), c1 = xswap16(b2, b3), c2 = xswap16(b4, b4);
+            const float d = xstep<0x128>(c0, c1, (lane >> 3) & 1);
+            const float d8 = c2 + dpp_f<0x128, 0xf>(c2);
+            if (sB < nsb) {
+                float *pd = part[offs >> 4][wave];
+                pd[brev3(rB)] = d;
+                if (rB == 0) pd[8] = d8;
+            }
         }
         __syncthreads();
         // flush: one thread per (splat, term group) sums the group's row
@@ -548,9 +607,13 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
                 // wave q wrote this partial only if the splat reaches its
                 // block and lies before its pixels' largest `last`
                 if (!((hit >> q) & 1u) || b_start + (uint32_t)k >= swlast[q]) continue;
-                const float4 a = part[k][q][j];
-                acc.x += a.x; acc.y += a.y; acc.z += a.z; acc.w += a.w;
-                if (j == 2) sx += part[k][q][1].w;
+                const float *a = part[k][q];
+                if (j == 2) {
+                    acc.x += a[8];
+                    sx += a[7];
+                } else {
+                    acc.x += a[4 * j]; acc.y += a[4 * j + 1]; acc.z += a[4 * j + 2]; acc.w += a[4 * j + 3];
+                }
             }
             float *row = pair_grad + 9 * (size_t)sslot[k];
             if (j == 0) {
@@ -567,15 +630,16 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
                 // dQ/ddx = 2(A dx + B dy), ddx/du = -1; partials hold -2 dL/dQ
                 const float4 b = sb[k];
                 const float A = -2.0f * kLn2 * b.x, B = -kLn2 * b.y, C = -2.0f * kLn2 * b.z;
-                const float sy = (acc.x + acc.y) + (acc.z + acc.w);
+                const float sy = acc.x;
                 row[0] = A * sx + B * sy;
                 row[1] = B * sx + C * sy;
             }
         };
-        if constexpr (NT >= 3 * BB) {
+        static_assert(BB <= 64, "one lane per batch splat in the flush");
+        if constexpr (NT >= 3 * 64) {
             // wave j takes term group j, lane k Gaussian k (the group's
             // branch is wave-uniform)
-            if (threadIdx.x < 3 * BB && (int)(threadIdx.x & 63) < m) flush((int)(threadIdx.x & 63), (int)(threadIdx.x >> 6));
+            if (threadIdx.x < 3 * 64 && (int)(threadIdx.x & 63) < m) flush((int)(threadIdx.x & 63), (int)(threadIdx.x >> 6));
         } else {
             for (int t = threadIdx.x; t < 3 * m; t += NT) flush(t % m, t / m);
         }
