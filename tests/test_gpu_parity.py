@@ -331,10 +331,13 @@ def masked_upstream(pool, views, seed):
     return np.concatenate(out)
 
 
-def test_backward_record_and_param_gradients(sw, ctx):
-    say("backward tiny")
+@pytest.mark.parametrize("tile", TILES)
+def test_backward_record_and_param_gradients(sw, ctx, tile):
+    # every tile shape: one wave per 8x8 tile (no per-wave lists) and four
+    # waves per 16x16 / 32x8 tile take different paths through the backward
+    say(f"backward tiny {tile}")
     pool, views = tiny(n=1200, deg=1)
-    dp, pl = plan_for(sw, ctx, pool, views)
+    dp, pl = plan_for(sw, ctx, pool, views, tile=tile)
     pl.forward()
     dL = masked_upstream(pool, views, 11)
     dp.grads.zero_()
