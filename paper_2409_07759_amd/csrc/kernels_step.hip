@@ -95,7 +95,12 @@ __device__ __forceinline__ void sh_weighted_grad(int deg, float x, float y, floa
 // Colour part of the backward preprocess (FP32): SH coefficient gradients
 // and the view-direction contribution to the mean gradient, summed over the
 // views where the slot is live; runs after k_prebwd_geom and adds to its
-// mean gradient.
+// mean gradient.  Three lanes per slot, lane c taking colour channel c (21
+// slots per wave, lane 63 idle): the channel's SH coefficient gradients and
+// its part of the view-direction term, which is linear in the channel's
+// weights; the three parts are added in channel order across the lanes.
+constexpr int kColorSlotsPerWave = 21;
+
 template <int DEG>
 __global__ void __launch_bounds__(kBlock)
 k_prebwd_color(const float *__restrict__ params, int n_slots, int num_gs, const uint32_t *__restrict__ listA,
@@ -105,14 +110,20 @@ k_prebwd_color(const float *__restrict__ params, int n_slots, int num_gs, const 
                const uint8_t *__restrict__ cflags, const float *__restrict__ rec_grad,
                float *__restrict__ grads) {
     constexpr int nk = (DEG + 1) * (DEG + 1);
-    const uint32_t a = blockIdx.x * kBlock + threadIdx.x;
-    if (a >= nA) return;
+    const int lane = threadIdx.x & 63, q = lane / 3, c = lane - 3 * q;
+    const uint32_t a = ((blockIdx.x * kBlock + threadIdx.x) >> 6) * kColorSlotsPerWave + (uint32_t)q;
+    // lanes without a slot work on the last one and store nothing (every
+    // lane reaches the cross-lane sums)
+    const bool act = lane < 3 * kColorSlotsPerWave && a < nA;
     const size_t S = (size_t)n_slots, NG = (size_t)num_gs;
-    const uint32_t slot = listA[a];
+    const uint32_t slot = listA[act ? a : nA - 1];
     const float mx = params[slot], my = params[S + slot], mz = params[2 * S + slot];
-    float dsh[3 * nk];
+    float f[nk], dsh[nk];
 #pragma unroll
-    for (int i = 0; i < 3 * nk; ++i) dsh[i] = 0.0f;
+    for (int k = 0; k < nk; ++k) {
+        f[k] = params[(11 + 3 * k + c) * S + slot];
+        dsh[k] = 0.0f;
+    }
     float dm0 = 0.0f, dm1 = 0.0f, dm2 = 0.0f;
     for (int g = 0; g < n_groups; ++g) {
         const int32_t j = pos_of[(size_t)g * NG + slot];
@@ -122,11 +133,8 @@ k_prebwd_color(const float *__restrict__ params, int n_slots, int num_gs, const 
             const ViewDev &V = views[group_views[G.view_first + kv]];
             const uint32_t r = V.rec_base + (uint32_t)j;
             if (tile_count[r] == 0) continue;                 // culled in this view
-            const uint32_t fl = cflags[r];
-            // rgb_c = max(0, sum_k Y_k f_kc + 1/2); clamped channels pass nothing
-            const float gc0 = (fl & 1u) ? 0.0f : rec_grad[9 * (size_t)r + 6];
-            const float gc1 = (fl & 2u) ? 0.0f : rec_grad[9 * (size_t)r + 7];
-            const float gc2 = (fl & 4u) ? 0.0f : rec_grad[9 * (size_t)r + 8];
+            // rgb_c = max(0, sum_k Y_k f_kc + 1/2); a clamped channel passes nothing
+            const float gc = ((cflags[r] >> c) & 1u) ? 0.0f : rec_grad[9 * (size_t)r + 6 + c];
             const float dxv = mx - (float)V.campos[0], dyv = my - (float)V.campos[1], dzv = mz - (float)V.campos[2];
             const float il = rsqrtf(dxv * dxv + dyv * dyv + dzv * dzv);
             const float hx = dxv * il, hy = dyv * il, hz = dzv * il;
@@ -134,11 +142,8 @@ k_prebwd_color(const float *__restrict__ params, int n_slots, int num_gs, const 
             sh_basis32(DEG, hx, hy, hz, Y);
 #pragma unroll
             for (int k = 0; k < nk; ++k) {
-                dsh[3 * k] += Y[k] * gc0;
-                dsh[3 * k + 1] += Y[k] * gc1;
-                dsh[3 * k + 2] += Y[k] * gc2;
-                wk[k] = params[(11 + 3 * k) * S + slot] * gc0 + params[(12 + 3 * k) * S + slot] * gc1 +
-                        params[(13 + 3 * k) * S + slot] * gc2;
+                dsh[k] += Y[k] * gc;
+                wk[k] = f[k] * gc;
             }
             float gx, gy, gz;
             sh_weighted_grad(DEG, hx, hy, hz, wk, gx, gy, gz);
@@ -149,11 +154,19 @@ k_prebwd_color(const float *__restrict__ params, int n_slots, int num_gs, const 
             dm2 += (gz - hz * dot) * il;
         }
     }
-    grads[slot] += dm0;
-    grads[NG + slot] += dm1;
-    grads[2 * NG + slot] += dm2;
+    // the slot's direction term: its channels' parts in channel order
+    const int l0 = 3 * q;
+    const float t0 = (__shfl(dm0, l0, 64) + __shfl(dm0, l0 + 1, 64)) + __shfl(dm0, l0 + 2, 64);
+    const float t1 = (__shfl(dm1, l0, 64) + __shfl(dm1, l0 + 1, 64)) + __shfl(dm1, l0 + 2, 64);
+    const float t2 = (__shfl(dm2, l0, 64) + __shfl(dm2, l0 + 1, 64)) + __shfl(dm2, l0 + 2, 64);
+    if (!act) return;
+    if (c == 0) {
+        grads[slot] += t0;
+        grads[NG + slot] += t1;
+        grads[2 * NG + slot] += t2;
+    }
 #pragma unroll
-    for (int i = 0; i < 3 * nk; ++i) grads[(11 + i) * NG + slot] = dsh[i];
+    for (int k = 0; k < nk; ++k) grads[(11 + 3 * k + c) * NG + slot] = dsh[k];
 }
 
 // Geometry part of the backward preprocess (FP64): projected mean, conic
@@ -680,13 +693,22 @@ void launch_preprocess_backward(hipStream_t s, const swgs_plan &p, uint8_t *ws, 
         wsp<float>(ws, p, WB_REC_GRAD), p.pool.grads
     hipLaunchKernelGGL(k_prebwd_geom, SWGS_PREBWD_COMMON, add_reg, (double)lambda_o * inv, (double)lambda_s * inv,
                        wsp<double>(ws, p, WB_REG_PART));
-    switch (p.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_prebwd_color<0>, SWGS_PREBWD_COMMON); break;
-    case 1: hipLaunchKernelGGL(k_prebwd_color<1>, SWGS_PREBWD_COMMON); break;
-    case 2: hipLaunchKernelGGL(k_prebwd_color<2>, SWGS_PREBWD_COMMON); break;
-    default: hipLaunchKernelGGL(k_prebwd_color<3>, SWGS_PREBWD_COMMON); break;
-    }
 #undef SWGS_PREBWD_COMMON
+    // colour: 21 slots per wave, four waves per block
+    const uint32_t cw = (nA + kColorSlotsPerWave - 1) / kColorSlotsPerWave;
+#define SWGS_PREBWD_COLOR                                                                                 \
+    dim3((cw + kBlock / 64 - 1) / (kBlock / 64)), dim3(kBlock), 0, s, p.pool.params, p.pool.n_slots,       \
+        p.pool.num_gs, wsp<uint32_t>(ws, p, WB_ACTIVE_LIST) + p.list_A_base, nA,                         \
+        wsp<GroupDev>(ws, p, WB_GROUPS), (int)p.groups.size(), wsp<int32_t>(ws, p, WB_GROUP_VIEWS),        \
+        wsp<ViewDev>(ws, p, WB_VIEWS), wsp<int32_t>(ws, p, WB_POS_OF), wsp<uint32_t>(ws, p, WB_TILE_COUNT), \
+        wsp<uint8_t>(ws, p, WB_CFLAGS), wsp<float>(ws, p, WB_REC_GRAD), p.pool.grads
+    switch (p.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_prebwd_color<0>, SWGS_PREBWD_COLOR); break;
+    case 1: hipLaunchKernelGGL(k_prebwd_color<1>, SWGS_PREBWD_COLOR); break;
+    case 2: hipLaunchKernelGGL(k_prebwd_color<2>, SWGS_PREBWD_COLOR); break;
+    default: hipLaunchKernelGGL(k_prebwd_color<3>, SWGS_PREBWD_COLOR); break;
+    }
+#undef SWGS_PREBWD_COLOR
     hipLaunchKernelGGL(k_reg_reduce, dim3(1), dim3(256), 0, s, wsp<double>(ws, p, WB_REG_PART), nb,
                        (double)lambda_o, (double)lambda_s, inv, wsp<uint32_t>(ws, p, WB_PAIR_COUNT),
                        wsp<double>(ws, p, WB_STATS));
