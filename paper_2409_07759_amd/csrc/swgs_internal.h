@@ -228,8 +228,9 @@ bool decode_layout(const int32_t h[16], size_t *need);
 void launch_decode(hipStream_t s, const swgs_pool &pool, int F, const uint8_t *rec, const int32_t h[16],
                    int64_t slot_base, uint32_t *scratch, uint32_t *bad);
 
-// record gradients [9][R] of records [rec_lo, rec_hi): the per-pair terms
-// the backward blend left at the records' emission slots, summed in order
+// record gradients [R][9] of records [rec_lo, rec_hi): the per-pair gradient
+// rows the backward blend left (a record's rows consecutive, records in
+// record order), summed in row order
 void launch_pair_grad_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t rec_lo, uint32_t rec_hi);
 void launch_loss_reduce(hipStream_t s, const swgs_plan &p, uint8_t *ws, const swgs_step_cfg *cfg,
                         bool with_reg);
