@@ -307,15 +307,41 @@ __global__ void k_pair_total(const uint32_t *__restrict__ total, uint32_t cap, u
     pair_count[1] = k > cap ? 1u : 0u;
 }
 
+// Tile ranges from the sorted pair keys: entry i opens its tile when the
+// key before it differs and closes it when the key after it differs.  A
+// thread takes four consecutive keys with one 16-byte load; the neighbours
+// of its first and last key come from the adjacent lanes (from memory at
+// the wave's ends).  The loop's trip count is uniform over a block, so
+// every lane reaches the lane exchanges.
 __global__ void __launch_bounds__(kBlock)
 k_tile_ranges(const uint32_t *__restrict__ pair_key, const uint32_t *__restrict__ pair_count, uint32_t cap,
               uint2 *__restrict__ ranges) {
     uint32_t n = pair_count[0];
     if (n > cap) n = cap;
-    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-        const uint32_t k = pair_key[i];
-        if (i == 0 || pair_key[i - 1] != k) ranges[k].x = i;
-        if (i == n - 1 || pair_key[i + 1] != k) ranges[k].y = i + 1;
+    const uint32_t nq = (n + 3) / 4;
+    const int lane = threadIdx.x & 63;
+    constexpr uint32_t kNone = 0xFFFFFFFFu;   // no tile id (ids are below the tile count)
+    for (uint32_t t0 = blockIdx.x * kBlock; t0 < nq; t0 += gridDim.x * kBlock) {
+        const uint32_t i0 = 4 * (t0 + threadIdx.x);
+        uint32_t k[4];
+        if (i0 + 4 <= n) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(pair_key + i0);
+            k[0] = v.x; k[1] = v.y; k[2] = v.z; k[3] = v.w;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) k[j] = i0 + j < n ? pair_key[i0 + j] : kNone;
+        }
+        uint32_t prev = __shfl_up(k[3], 1, 64), next = __shfl_down(k[0], 1, 64);
+        if (lane == 0) prev = i0 > 0 && i0 <= n ? pair_key[i0 - 1] : kNone;
+        if (lane == 63) next = i0 + 4 < n ? pair_key[i0 + 4] : kNone;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t i = i0 + j;
+            if (i >= n) break;
+            const uint32_t pk = j == 0 ? prev : k[j > 0 ? j - 1 : 0], nk = j == 3 ? next : k[j < 3 ? j + 1 : 3];
+            if (i == 0 || pk != k[j]) ranges[k[j]].x = i;
+            if (i == n - 1 || nk != k[j]) ranges[k[j]].y = i + 1;
+        }
     }
 }
 
@@ -415,7 +441,7 @@ void launch_row_offsets(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t
 void launch_tile_ranges(hipStream_t s, const swgs_plan &p, uint8_t *ws, uint32_t tile_lo, uint32_t tile_hi) {
     uint2 *ranges = wsp<uint2>(ws, p, WB_TILE_RANGE);
     launch_fill_u32(s, reinterpret_cast<uint32_t *>(ranges + tile_lo), 0, 2 * (size_t)(tile_hi - tile_lo));
-    int nb = (int)((p.pair_cap + kBlock - 1) / kBlock);
+    int nb = (int)((p.pair_cap + 4 * kBlock - 1) / (4 * kBlock));   // four keys per thread
     if (nb > 8192) nb = 8192;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_tile_ranges, dim3(nb), dim3(kBlock), 0, s, wsp<uint32_t>(ws, p, WB_PAIR_KEY),
