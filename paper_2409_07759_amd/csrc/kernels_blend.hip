@@ -34,6 +34,8 @@
 // records in record order); an ordered per-record reduce then sums a
 // record's rows in row order.  No float atomics: gradients are
 // bit-reproducible.
+#include <type_traits>
+
 #include "swgs_internal.h"
 
 namespace swgs {
@@ -416,9 +418,10 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     constexpr int NW = NT / 64;           // waves
     constexpr int BB = 48;                // splats per LDS batch (26 KB of LDS per 16x16 block: 6 per CU)
     constexpr bool CULL = NW > 1;
+    static_assert(BB % 8 == 0, "a sub-batch's eight list entries are one 16-byte LDS read");
     __shared__ float4 sa[BB], sb[BB], sc[BB];
     __shared__ uint32_t smask[BB];
-    __shared__ uint16_t slist[CULL ? NW : 1][CULL ? BB : 1];
+    __shared__ __align__(16) uint16_t slist[CULL ? NW : 1][CULL ? BB : 1];   // rows of 96 B
     __shared__ uint32_t sslot[BB];        // gradient row of each batch pair
     __shared__ float part[BB][NW][kTerm];
     __shared__ float2 pbuf[NW][kSub][kPitch];   // phase A -> B: (w, m') per (sub-batch splat, pixel)
@@ -516,24 +519,44 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         }
         __syncthreads();
         const int wm = (int)min((uint32_t)m, wlast > b_start ? wlast - b_start : 0u);
-        const int cnt = CULL ? wave_list<BB>(smask, wm, wave, lane, slist[CULL ? wave : 0]) : wm;
+        // the wave's list length, wave-uniform (scalar loop control below)
+        const int cnt = __builtin_amdgcn_readfirstlane(
+            CULL ? wave_list<BB>(smask, wm, wave, lane, slist[CULL ? wave : 0]) : wm);
         // entries of this batch before the pixel's last contributor, as a
         // byte-offset bound (entry k is before it iff 16 k < lim)
         const int lim = 16 * ((int)min(lst, b_end) - (int)min(lst, b_start));
-        for (int i0 = cnt - 1; i0 >= 0; i0 -= kSub) {
-            const int nsb = min(kSub, i0 + 1);
-            // phase B's splat: entry i0 - s (lanes past the sub-batch take
-            // any entry and store nothing); read before phase A
-            const int ie = max(i0 - sB, 0);
+        wave_lds_sync();   // the list's stores before its 16-byte reads
+        // sub-batches of list positions 8 m .. 8 m + 7, the top one first
+        // (possibly partial), each walked back to front
+        for (int top = cnt; top > 0;) {
+            const int base8 = (top - 1) & ~(kSub - 1), nsb = top - base8;
+            top = base8;
+            // the sub-batch's eight list entries (one 16-byte read, kept in
+            // scalar registers: position q's offset is a constant shift)
+            uint32_t sw[4] = {0u, 0u, 0u, 0u};
+            if (CULL) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(&slist[CULL ? wave : 0][base8]);
+                sw[0] = __builtin_amdgcn_readfirstlane(v.x);
+                sw[1] = __builtin_amdgcn_readfirstlane(v.y);
+                sw[2] = __builtin_amdgcn_readfirstlane(v.z);
+                sw[3] = __builtin_amdgcn_readfirstlane(v.w);
+            }
+            // phase B's splat: list position base8 + s (lanes past the
+            // sub-batch take the last position and store nothing); read
+            // before phase A
+            const int ie = min(base8 + sB, cnt - 1);
             const int offs = CULL ? (int)slist[CULL ? wave : 0][ie] : 16 * ie;
             const float4 as = at16(sa, offs);
             const float os = at16(sb, offs).w;
-            // phase A, lane = pixel, entries i0, i0 - 1, ... (back to front)
-            // into sub-batch slots 0, 1, ...: the colour weight w = alpha
-            // T_k and m' = g dL/dalpha (g = exp(-Q/2); zero where alpha is
-            // clamped), both zero where the splat was not blended here
-            for (int j = 0; j < nsb; ++j) {
-                const int off = CULL ? (int)slist[CULL ? wave : 0][i0 - j] : 16 * (i0 - j);
+            // phase A, lane = pixel, positions base8 + nsb - 1 down to base8
+            // (back to front) into sub-batch slots q = position - base8:
+            // the colour weight w = alpha T_k and m' = g dL/dalpha (g =
+            // exp(-Q/2); zero where alpha is clamped), both zero where the
+            // splat was not blended here
+            auto phase_a = [&](auto qc) {
+                constexpr int q = decltype(qc)::value;
+                if (q >= nsb) return;                            // wave-uniform
+                const int off = CULL ? (int)((sw[q >> 1] >> (16 * (q & 1))) & 0xFFFFu) : 16 * (base8 + q);
                 // contrib = the forward blended this splat here
                 const Px e = eval_splat(lxf, lyf, at16(sa, off), at16(sb, off));
                 const float alpha = fminf(0.99f, e.og);
@@ -553,8 +576,16 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
                     T = contrib ? Tk : T;
                     gW = fmaf(ac, diff, gW);                                 // a = 0 keeps gW
                 }
-                pbuf[wave][j][lane] = make_float2(wv, mp);
-            }
+                pbuf[wave][q][lane] = make_float2(wv, mp);
+            };
+            phase_a(std::integral_constant<int, 7>{});
+            phase_a(std::integral_constant<int, 6>{});
+            phase_a(std::integral_constant<int, 5>{});
+            phase_a(std::integral_constant<int, 4>{});
+            phase_a(std::integral_constant<int, 3>{});
+            phase_a(std::integral_constant<int, 2>{});
+            phase_a(std::integral_constant<int, 1>{});
+            phase_a(std::integral_constant<int, 0>{});
             wave_lds_sync();
             // phase B: row sums of g.w (colour) and of m', i' m', i'^2 m'
             // (i' = i - 3.5, the column's offset from the row centre); with
@@ -598,7 +629,7 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
         // d/d(u, v, A, B, C, o, r, g, b), conic
         // unscaled (A = -2 A' ln2, B = -B' ln2, C = -2 C' ln2): no atomics,
         // and a fixed summation order.  Groups: 0 colour 3 + opacity,
-        // 1 conic terms 3 (+ offset x), 2 offset y (four rows) with offset x.
+        // 1 conic terms 3 (+ offset x), 2 offset y with offset x.
         auto flush = [&](int k, int j) {
             const uint32_t hit = smask[k];
             float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
