@@ -559,6 +559,11 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
                 const int off = CULL ? (int)((sw[q >> 1] >> (16 * (q & 1))) & 0xFFFFu) : 16 * (base8 + q);
                 // contrib = the forward blended this splat here
                 const Px e = eval_splat(lxf, lyf, at16(sa, off), at16(sb, off));
+                // g.c, taken with the other reads of the entry (its LDS read
+                // then overlaps the evaluation)
+                const float4 c = at16(sc, off);
+                const float gc = fmaf(g2, c.z, fmaf(g1, c.y, g0 * c.x));
+                asm volatile("" : : "v"(gc));   // keeps the read and the product ahead of the branch
                 const float alpha = fminf(0.99f, e.og);
                 const bool contrib = off < lim && alpha >= (1.0f / 255.0f);
                 // T and W change only where the splat was blended: a wave
@@ -567,8 +572,7 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
                 if (__ballot(contrib) != 0) {
                     const float ri = __builtin_amdgcn_rcpf(1.0f - alpha);
                     const float Tk = T * ri;                                 // transmittance in front of k
-                    const float4 c = at16(sc, off);
-                    const float diff = fmaf(g2, c.z, fmaf(g1, c.y, g0 * c.x)) - gW;
+                    const float diff = gc - gW;
                     const float ac = contrib ? alpha : 0.0f;
                     wv = ac * Tk;
                     // alpha = o g: dL/do = g dL/dalpha, dL/dQ = -o g dL/dalpha / 2
