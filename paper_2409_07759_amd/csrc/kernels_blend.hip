@@ -504,11 +504,18 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
     const float bx = (float)((tx * TW + (wave % (TW / 8)) * 8) & 63);
     const float byr = (float)(((ty * TH + (wave / (TW / 8)) * 8) & 63) + rB);
 
+    // thread k stages entry k of a batch; its pair value (the record) is
+    // read one batch ahead, so staging waits for one dependent load only
+    static_assert(BB <= NT, "one staged entry per thread");
+    auto batch_start = [&](uint32_t e) { return e > (uint32_t)BB ? e - BB : 0u; };
+    uint32_t r_next = (uint32_t)threadIdx.x < nmax - batch_start(nmax)
+                          ? pair_val[rg.x + batch_start(nmax) + threadIdx.x] : 0u;
     for (uint32_t b_end = nmax; b_end > 0;) {
-        const uint32_t b_start = b_end > (uint32_t)BB ? b_end - BB : 0;
+        const uint32_t b_start = batch_start(b_end);
         const int m = (int)(b_end - b_start);
-        for (int k = threadIdx.x; k < m; k += NT) {
-            const uint32_t r = pair_val[rg.x + b_start + k];
+        if ((int)threadIdx.x < m) {
+            const int k = threadIdx.x;
+            const uint32_t r = r_next;
             sslot[k] = slot_of(r);
             sa[k] = block_offset(splat[3 * (size_t)r], tx * TW, ty * TH);
             sb[k] = splat[3 * (size_t)r + 1];
@@ -518,6 +525,9 @@ k_blend_bwd(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ pair_
             smask[k] = CULL ? (uint32_t)pair_mask[rg.x + b_start + k] : 1u;
         }
         __syncthreads();
+        // the next batch's pair value (the loop below does not touch it)
+        r_next = (uint32_t)threadIdx.x < b_start - batch_start(b_start)
+                     ? pair_val[rg.x + batch_start(b_start) + threadIdx.x] : 0u;
         const int wm = (int)min((uint32_t)m, wlast > b_start ? wlast - b_start : 0u);
         // the wave's list length, wave-uniform (scalar loop control below)
         const int cnt = __builtin_amdgcn_readfirstlane(
