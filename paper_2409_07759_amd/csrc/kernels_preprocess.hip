@@ -86,8 +86,10 @@ __device__ __forceinline__ int clip_tile(double f, int n) {
 // HOIST_SH: load the slot's SH rows into registers once, before the camera
 // loop (frames seen by several cameras); else per camera, after the
 // basis (one camera per frame: fewer registers, higher occupancy).
+// (With the SH rows in registers the kernel asks for three waves per SIMD:
+// at most 168 VGPRs, a few spilled, against 202 and two waves otherwise.)
 template <bool HOIST_SH>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, HOIST_SH ? 3 : 1)
 k_preprocess(const float *__restrict__ params, int n_slots, int deg, const GroupDev *__restrict__ groups,
              const int32_t *__restrict__ group_views, const ViewDev *__restrict__ views,
              const uint32_t *__restrict__ lists, int g_lo, int only_view, int tile_w, int tile_h,
